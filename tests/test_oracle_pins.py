@@ -1,0 +1,412 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these need a GPU.  Each pin is chosen so that a plausible mistake in
+the oracle (a dropped term, a wrong sign or index, a transposed operand, a
+wrong channel factor or prefactor) fails at least one of them:
+
+* Pf(A)^2 = det(A) (LAPACK) and textbook Pfaffian identities;
+* node weights reproduce the estimator's linear functional on polynomials;
+* the dense 2^n brute force (the plain definition) at n <= 8;
+* the exact average over the whole signed-permutation ensemble (n = 3)
+  equals <Psi_T|phi> -- pins the factor 2 and C(2N,2x)/C(N,x);
+* the closed form for signed-permutation shadows, up to the paper's n = 16;
+* special cases: pair-preserving Q gives 0;
+* structure: o(Phi R) = det(R) o, completion independence, degree window;
+* an mpmath re-evaluation bounds the oracle's own rounding error.
+"""
+import itertools
+import json
+import os
+from math import comb
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute, closed_form
+from paper_2506_22408_amd import workload as wl
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def rand_skew(rng, m):
+    A = rng.standard_normal((m, m)) + 1j * rng.standard_normal((m, m))
+    return A - A.T
+
+
+# ---------------------------------------------------------------- Pfaffian
+@pytest.mark.parametrize("m", [2, 4, 6, 10, 16, 24, 30, 36, 40])
+def test_pfaffian_squared_is_det(m):
+    rng = np.random.default_rng(m)
+    for _ in range(3):
+        A = rand_skew(rng, m)
+        pf = oracle.pfaffian(A)
+        det = np.linalg.det(A)
+        assert abs(pf * pf - det) <= 1e-10 * abs(det)
+
+
+def test_pfaffian_identities():
+    rng = np.random.default_rng(1)
+    # 2x2
+    a = 0.3 - 1.7j
+    assert oracle.pfaffian(np.array([[0, a], [-a, 0]])) == pytest.approx(a, abs=1e-15)
+    # symplectic J has Pf = 1
+    J = np.kron(np.eye(5), np.array([[0, 1], [-1, 0]]))
+    assert oracle.pfaffian(J) == pytest.approx(1.0, abs=1e-15)
+    # block diagonal: product of the blocks' Pfaffians
+    A1, A2 = rand_skew(rng, 4), rand_skew(rng, 6)
+    Bd = np.zeros((10, 10), complex)
+    Bd[:4, :4], Bd[4:, 4:] = A1, A2
+    assert oracle.pfaffian(Bd) == pytest.approx(oracle.pfaffian(A1) * oracle.pfaffian(A2), rel=1e-12)
+    # Pf(P A P^T) = det(P) Pf(A): a transposition flips the sign
+    A = rand_skew(rng, 8)
+    P = np.eye(8)[[0, 3, 2, 1, 4, 5, 6, 7]]
+    assert oracle.pfaffian(P @ A @ P.T) == pytest.approx(-oracle.pfaffian(A), rel=1e-12)
+    # Pf(M A M^T) = det(M) Pf(A) for a general complex M
+    M = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    assert oracle.pfaffian(M @ A @ M.T) == pytest.approx(np.linalg.det(M) * oracle.pfaffian(A), rel=1e-10)
+    # zero rows: Pf = 0; odd size: 0
+    Z = rand_skew(rng, 6)
+    Z[2, :] = 0
+    Z[:, 2] = 0
+    assert oracle.pfaffian(Z) == 0
+    assert oracle.pfaffian(np.zeros((0, 0))) == 1
+
+
+def test_pfaffian_brute_expansion():
+    """Pf by the definition (sum over perfect matchings) at m = 6."""
+    rng = np.random.default_rng(3)
+    A = rand_skew(rng, 6)
+
+    def pf_def(idx):
+        if not idx:
+            return 1.0
+        i = idx[0]
+        tot = 0.0
+        for r, j in enumerate(idx[1:]):
+            rest = [k for k in idx[1:] if k != j]
+            tot += (-1) ** r * A[i, j] * pf_def(rest)
+        return tot
+
+    assert oracle.pfaffian(A) == pytest.approx(pf_def(list(range(6))), rel=1e-12)
+
+
+# ---------------------------------------------------------------- weights
+@pytest.mark.parametrize("n,eta,family", [(4, 2, "unit"), (8, 4, "unit"), (16, 8, "unit"),
+                                          (24, 12, "unit"), (8, 4, "chebyshev"), (16, 8, "chebyshev")])
+def test_node_weights_reproduce_functional(n, eta, family):
+    """sum_k w_k P(z_k) = 2 i^{eta/2} 2^{-(n-eta/2)} sum_x c_x C(2n,2x)/C(n,x)
+    for random polynomials P of degree <= n - eta/2, evaluated at 50 digits."""
+    z, w = oracle.node_weights(n, eta, None, family)
+    assert len(z) == n + 1
+    ell = n - eta // 2
+    rng = np.random.default_rng(n)
+    with mpmath.workdps(50):
+        for _ in range(3):
+            c = rng.standard_normal(ell + 1) + 1j * rng.standard_normal(ell + 1)
+            lhs = sum(mpmath.mpc(complex(w[k])) *
+                      sum(mpmath.mpc(complex(c[x])) * mpmath.mpc(complex(z[k])) ** x for x in range(ell + 1))
+                      for k in range(len(z)))
+            rhs = 2 * mpmath.mpc(0, 1) ** (eta // 2) / mpmath.mpf(2) ** ell * sum(
+                mpmath.mpc(complex(c[x])) * mpmath.mpf(comb(2 * n, 2 * x)) / comb(n, x) for x in range(ell + 1))
+            assert abs(complex(lhs - rhs)) <= 1e-13 * abs(complex(rhs)) * (1 if family == "unit" else 1e3)
+
+
+def test_unit_weights_closed_form():
+    """Roots of unity: w_k = pref/K sum_x mu_x z_k^{-x} (a DFT)."""
+    n, eta = 16, 8
+    z, w = oracle.node_weights(n, eta)
+    K = n + 1
+    pref = 2 * 1j ** (eta // 2) / 2 ** (n - eta // 2)
+    ell = n - eta // 2
+    for k in range(K):
+        terms = [pref / K * comb(2 * n, 2 * x) / comb(n, x) * np.exp(-2j * np.pi * k * x / K)
+                 for x in range(ell + 1)]
+        # the FP64 sum here is the less accurate side: bound by its own rounding
+        assert abs(w[k] - sum(terms)) <= 1e-15 * len(terms) * sum(abs(t) for t in terms)
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("n,eta,orth", [(3, 2, True), (4, 2, True), (4, 4, True), (4, 2, False),
+                                        (5, 2, True), (5, 4, False), (6, 2, True), (6, 4, True),
+                                        (6, 6, False)])
+def test_oracle_matches_dense_brute_force(n, eta, orth):
+    rng = np.random.default_rng(100 * n + eta + orth)
+    phi = wl.walkers(rng, 1, n, eta, orth)[0]
+    Q = wl.haar_so(rng, 1, 2 * n)[0]
+    b = int(wl.even_bits(rng, 1, n)[0])
+    ob = brute.overlap_pair(phi, Q, b)
+    for fam in ("unit", "chebyshev"):
+        assert abs(oracle.pair(phi, Q, b, family=fam) - ob) <= 1e-12 * abs(ob)
+
+
+def test_oracle_matches_dense_brute_force_n8():
+    rng = np.random.default_rng(8)
+    phi = wl.walkers(rng, 1, 8, 4)[0]
+    Q = wl.haar_so(rng, 1, 16)[0]
+    b = int(wl.even_bits(rng, 1, 8)[0])
+    ob = brute.overlap_pair(phi, Q, b)
+    assert abs(oracle.pair(phi, Q, b) - ob) <= 1e-12 * abs(ob)
+
+
+def test_golden_brute_values():
+    """Stored brute-force values (written by tests/golden/make_golden.py)."""
+    with open(os.path.join(HERE, "golden", "brute_small.json")) as f:
+        data = json.load(f)
+    for c in data["cases"]:
+        phi = np.array(c["phi_re"]) + 1j * np.array(c["phi_im"])
+        Q = np.array(c["Q"])
+        ref = complex(*c["o"])
+        assert abs(oracle.pair(phi, Q, c["bits"]) - ref) <= 1e-12 * abs(ref)
+
+
+def test_brute_snapshot_covariance():
+    """The dense snapshot has covariance -i Tr(sigma gamma_mu gamma_nu) =
+    (Q^T C_b Q)_{mu nu} -- checks the brute force's U_Q and the oracle's C'."""
+    n = 4
+    rng = np.random.default_rng(11)
+    Q = wl.haar_so(rng, 1, 2 * n)[0]
+    b = int(wl.even_bits(rng, 1, n)[0])
+    sigma = brute.snapshot(Q, b)
+    g = brute.majoranas_dense(n)
+    C = np.array([[(-1j * np.trace(sigma @ g[a] @ g[c])).real if a != c else 0.0
+                   for c in range(2 * n)] for a in range(2 * n)])
+    assert np.abs(C - oracle.covariance(Q, b)).max() < 1e-12
+    assert abs(np.trace(sigma) - 1) < 1e-12
+
+
+# ---------------------------------------------------------------- exact average
+def test_exact_channel_average_signed_permutations():
+    """n = 3, eta = 2: averaging o over every det=+1 signed permutation Q and
+    every outcome b with its Born probability for |Psi> = (|0>+|Psi_T>)/sqrt2
+    gives <Psi_T|phi> exactly (pins the factor 2 and the channel factors)."""
+    n, eta = 3, 2
+    d = 2 * n
+    rng = np.random.default_rng(42)
+    g = brute.majoranas_dense(n)
+    dim = 1 << n
+    psiT = np.zeros(dim, complex)
+    two = [x for x in range(dim) if bin(x).count("1") == eta]
+    psiT[two] = rng.standard_normal(len(two)) + 1j * rng.standard_normal(len(two))
+    psiT /= np.linalg.norm(psiT)
+    vac = np.zeros(dim, complex)
+    vac[0] = 1
+    Psi = (vac + psiT) / np.sqrt(2)
+    phi = wl.walkers(rng, 1, n, eta)[0]
+    target = np.vdot(psiT, brute.slater_state(phi))
+    Qs, bl, probs = [], [], []
+    for perm in itertools.permutations(range(d)):
+        for sg in itertools.product([-1.0, 1.0], repeat=d):
+            Q = np.zeros((d, d))
+            Q[np.arange(d), perm] = sg
+            if np.linalg.det(Q) < 0:
+                continue
+            # bilinears M_j = -i s s gamma_{pi(2j)} gamma_{pi(2j+1)}; P(b) = <Psi| prod_j (1 + beta_j M_j)/2 |Psi>
+            M = [-1j * sg[2 * j] * sg[2 * j + 1] * (g[perm[2 * j]] @ g[perm[2 * j + 1]]) for j in range(n)]
+            for bits in range(1 << n):
+                P = np.eye(dim, dtype=complex)
+                for j in range(n):
+                    beta = -1.0 if (bits >> j) & 1 else 1.0
+                    P = P @ (np.eye(dim) + beta * M[j]) / 2
+                p = np.vdot(Psi, P @ Psi).real
+                if p > 1e-14:
+                    Qs.append(Q)
+                    bl.append(bits)
+                    probs.append(p)
+    Qs = np.array(Qs)
+    probs = np.array(probs)
+    n_group = 720 * 64 // 2
+    o = oracle.overlap_pairs(phi[None], Qs, np.array(bl, np.uint64))[0]
+    est = np.sum(probs * o) / n_group
+    assert abs(est - target) <= 1e-12 * max(1.0, abs(target))
+
+
+# ---------------------------------------------------------------- closed form
+@pytest.mark.parametrize("n,eta", [(4, 2), (6, 4), (8, 4), (10, 6)])
+def test_closed_form_signed_permutations(n, eta):
+    rng = np.random.default_rng(7 * n + eta)
+    phi = wl.walkers(rng, 1, n, eta)[0]
+    for _ in range(2):
+        Q, perm, signs = closed_form.random_signed_permutation(rng, n)
+        b = int(wl.even_bits(rng, 1, n)[0])
+        ref = closed_form.overlap_pair(phi, perm, signs, b)
+        o = oracle.pair(phi, Q, b)
+        assert abs(o - ref) <= 1e-12 * max(abs(ref), 1e-3)
+
+
+def test_closed_form_paper_size_n16():
+    """The paper's own size (N = 16, eta = 8) and ensemble (signed permutations)."""
+    rng = np.random.default_rng(1616)
+    phi = wl.walkers(rng, 1, 16, 8)[0]
+    Q, perm, signs = closed_form.random_signed_permutation(rng, 16)
+    b = int(wl.even_bits(rng, 1, 16)[0])
+    ref = closed_form.overlap_pair(phi, perm, signs, b)
+    o = oracle.pair(phi, Q, b)
+    assert abs(ref) > 0
+    assert abs(o - ref) <= 1e-11 * abs(ref)
+
+
+# ---------------------------------------------------------------- special cases
+def test_pair_preserving_q_gives_zero():
+    """A Q that maps each mode's Majorana pair to itself leaves |b> a number
+    state, so <0|rho_hat|phi> = 0 (every node Pfaffian vanishes)."""
+    n, eta = 6, 2
+    rng = np.random.default_rng(5)
+    phi = wl.walkers(rng, 1, n, eta)[0]
+    for Q in [np.eye(2 * n),
+              np.kron(np.eye(n), np.array([[np.cos(0.3), np.sin(0.3)], [-np.sin(0.3), np.cos(0.3)]]))]:
+        for b in (0, 0b11, 0b101101):
+            o, p = oracle.pair(phi, Q, b, return_nodes=True)
+            assert abs(o) <= 1e-14
+            assert np.abs(p).max() <= 1e-14
+
+
+# ---------------------------------------------------------------- structure
+def test_multilinearity_and_sign():
+    n, eta = 8, 4
+    rng = np.random.default_rng(9)
+    phi = wl.walkers(rng, 1, n, eta)[0]
+    Q = wl.haar_so(rng, 1, 2 * n)[0]
+    b = int(wl.even_bits(rng, 1, n)[0])
+    o = oracle.pair(phi, Q, b)
+    R = rng.standard_normal((eta, eta)) + 1j * rng.standard_normal((eta, eta))
+    assert abs(oracle.pair(phi @ R, Q, b) - np.linalg.det(R) * o) <= 1e-11 * abs(np.linalg.det(R) * o)
+    sw = phi[:, [1, 0, 2, 3]]
+    assert abs(oracle.pair(sw, Q, b) + o) <= 1e-12 * abs(o)
+
+
+def test_completion_independence():
+    n, eta = 8, 4
+    rng = np.random.default_rng(10)
+    phi = wl.walkers(rng, 1, n, eta)[0]
+    Q = wl.haar_so(rng, 1, 2 * n)[0]
+    b = int(wl.even_bits(rng, 1, n)[0])
+    perp = oracle.complement(phi)
+    U = np.linalg.qr(rng.standard_normal((n - eta, n - eta)) + 1j * rng.standard_normal((n - eta, n - eta)))[0]
+    o1 = oracle.pair(phi, Q, b, perp=perp)
+    o2 = oracle.pair(phi, Q, b, perp=perp @ U)
+    o3 = oracle.pair(phi, Q, b, perp=rng.standard_normal((n, n - eta)))   # any complement, not orthogonal
+    assert abs(o1 - o2) <= 1e-12 * abs(o1)
+    assert abs(o1 - o3) <= 1e-10 * abs(o1)
+
+
+def test_degree_window():
+    """Coefficients of Pf(A(z)) vanish outside x in [eta/2, n - eta/2]."""
+    n, eta = 10, 4
+    rng = np.random.default_rng(12)
+    phi = wl.walkers(rng, 1, n, eta)[0]
+    Q = wl.haar_so(rng, 1, 2 * n)[0]
+    b = int(wl.even_bits(rng, 1, n)[0])
+    K = n + 1
+    _, p = oracle.pair(phi, Q, b, K=K, return_nodes=True)
+    z = np.exp(2j * np.pi * np.arange(K) / K)
+    c = np.array([np.sum(p * z ** (-x)) / K for x in range(K)])
+    big = np.abs(c).max()
+    for x in range(K):
+        if x < eta // 2 or x > n - eta // 2:
+            assert abs(c[x]) <= 1e-13 * big
+    assert abs(c[eta // 2]) > 1e-6 * big
+
+
+def test_extended_precision_error_budget():
+    """Re-evaluate the Pfaffian route at 40 digits (mpmath) for one pair at
+    N = 16: the FP64 oracle's own rounding error is tiny."""
+    n, eta = 16, 8
+    rng = np.random.default_rng(16)
+    phi = wl.walkers(rng, 1, n, eta)[0]
+    Q = wl.haar_so(rng, 1, 2 * n)[0]
+    b = int(wl.even_bits(rng, 1, n)[0])
+    o = oracle.pair(phi, Q, b)
+    X = oracle.xmatrix(phi)
+    z, w = oracle.node_weights(n, eta)
+    m = 2 * n - eta
+    with mpmath.workdps(40):
+        Xm = mpmath.matrix([[mpmath.mpc(complex(v)) for v in row] for row in X])
+        Qm = mpmath.matrix(Q.tolist())
+        Cb = mpmath.zeros(2 * n, 2 * n)
+        for j in range(n):
+            beta = -1 if (b >> j) & 1 else 1
+            Cb[2 * j, 2 * j + 1] = beta
+            Cb[2 * j + 1, 2 * j] = -beta
+        Cp = Qm.T * Cb * Qm
+        B = Xm * Cp * Xm.T
+
+        def pf(A):
+            A = A.copy()
+            r = mpmath.mpc(1)
+            for k in range(0, m - 1, 2):
+                p = max(range(k + 1, m), key=lambda j: abs(A[k, j]))
+                if p != k + 1:
+                    for j in range(m):
+                        A[k + 1, j], A[p, j] = A[p, j], A[k + 1, j]
+                    for i in range(m):
+                        A[i, k + 1], A[i, p] = A[i, p], A[i, k + 1]
+                    r = -r
+                a = A[k, k + 1]
+                r *= a
+                for i in range(k + 2, m):
+                    ti, vi = A[k, i] / a, A[k + 1, i]
+                    for j in range(k + 2, m):
+                        A[i, j] += vi * A[k, j] / a - ti * A[k + 1, j]
+            return r
+
+        tot = mpmath.mpc(0)
+        for k in range(len(z)):
+            A = B * mpmath.mpc(complex(z[k]))
+            for u in range(n - eta):
+                r0 = eta + 2 * u
+                A[r0, r0 + 1] += 1
+                A[r0 + 1, r0] -= 1
+            tot += mpmath.mpc(complex(w[k])) * pf(A)
+        ref = complex(tot)
+    assert abs(o - ref) <= 1e-13 * abs(ref)
+
+
+# ---------------------------------------------------------------- gradient
+def test_gradient_finite_differences_and_invariants():
+    n, eta, W, S = 6, 4, 2, 4
+    rng = np.random.default_rng(21)
+    phi = wl.walkers(rng, W, n, eta)
+    Q = wl.haar_so(rng, S, 2 * n)
+    bits = wl.even_bits(rng, S, n)
+    Sw, D, G = oracle.grad(phi, Q, bits)
+    assert np.allclose(Sw, oracle.overlap(phi, Q, bits), rtol=1e-13)
+    h = 1e-6
+    for w in range(W):
+        assert np.abs(phi[w].T @ D[w] - np.eye(eta)).max() < 1e-12
+        assert abs(np.trace(G[w]) - eta) < 1e-12
+        assert np.abs(G[w].T @ phi[w] - phi[w]).max() < 1e-12
+        E = rng.standard_normal((n, eta)) + 1j * rng.standard_normal((n, eta))
+        for dirn in (E, 1j * E):          # holomorphy: real and imaginary directions
+            pp, pm = phi.copy(), phi.copy()
+            pp[w] += h * dirn
+            pm[w] -= h * dirn
+            fd = (np.log(oracle.overlap(pp, Q, bits)[w]) - np.log(oracle.overlap(pm, Q, bits)[w])) / (2 * h)
+            an = np.sum(D[w] * dirn)
+            assert abs(fd - an) <= 1e-7 * abs(an)
+
+
+def test_gradient_brute_force_green():
+    """N_pq = 2<0|rho_hat a_p^dag a_q|phi> by dense brute force equals o * G_pq."""
+    n, eta = 4, 2
+    rng = np.random.default_rng(22)
+    phi = wl.walkers(rng, 1, n, eta)
+    Q = wl.haar_so(rng, 1, 2 * n)
+    bits = wl.even_bits(rng, 1, n)
+    N = brute.mixed_one_body(phi[0], Q[0], int(bits[0]))
+    Sw, D, G = oracle.grad(phi, Q, bits)
+    assert np.abs(N - G[0] * Sw[0]).max() <= 1e-12 * np.abs(N).max()
+
+
+def test_force_bias_definition():
+    """x_bar = -sqrt(dt) <i L_gamma>: check against an explicit double sum."""
+    rng = np.random.default_rng(3)
+    n, ng = 4, 3
+    G = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
+    L = wl.cholesky_like(rng, n, ng)
+    xb = oracle.force_bias(G, L, 0.01)
+    for w in range(2):
+        for g in range(ng):
+            ref = -0.1 * 1j * sum(L[p * n + q, g] * G[w, p, q] for p in range(n) for q in range(n))
+            assert abs(xb[w, g] - ref) < 1e-14
