@@ -1,0 +1,144 @@
+/*
+ * shadowov.h -- C ABI of the MI355X (gfx950) matchgate-shadow overlap library.
+ *
+ * The library estimates, for every AFQMC walker Slater determinant phi_w and
+ * every matchgate shadow (Q_s, b_s), the single-shadow overlap estimate
+ * o_ws of <Psi_T|phi_w>, and the shadow average S_w = (1/S) sum_s o_ws
+ * (Zhao et al., arXiv:2506.22408, section "Classical shadows and the
+ * evaluation of overlaps": eqs. a_mat, b_mat, the interpolation of
+ * Pf(A(z)) at the nodes and the estimator o_p).  It also gives the
+ * holomorphic derivative d log S_w / d Phi_w and the mixed Green's function
+ * G_w (section "Force bias and local energy", eqs. force_bias_diff and
+ * Pfaffian_der).
+ *
+ * Conventions (fixed readings of the paper):
+ *   - o_ws = 2 <0|rho_hat_s|phi_w>, so that S_w estimates <Psi_T|phi_w>
+ *     for the measured state |Psi> = (|0> + |Psi_T>)/sqrt2; the paper's o_p
+ *     omits the factor 2 (SO_FLAG_PAPER_NORM reproduces it literally);
+ *   - W (not W^*) and W^T (not W^dagger) in B = W M_phi Q^T C_b Q M_phi^T W^T;
+ *   - the selected rows are the first Majorana of each occupied orbital and
+ *     both Majoranas of each empty orbital, in increasing order;
+ *   - Majoranas gamma_{2j-1} = a_j + a_j^dag, gamma_{2j} = -i(a_j - a_j^dag);
+ *     U_Q^dag gamma_mu U_Q = sum_nu Q_{mu nu} gamma_nu; bit j-1 of b_s is b_j.
+ *
+ * Memory: every array argument of shadow_overlap / shadow_overlap_grad is a
+ * DEVICE pointer owned by the caller.  The library never allocates device
+ * memory: scratch space is the caller's `workspace` (size from
+ * so_workspace_size).  All work is enqueued on `stream` (a hipStream_t;
+ * NULL = the default stream); the calls return without synchronising.
+ * Arguments are validated on the host before anything is enqueued; a
+ * failed check returns an error code and enqueues nothing.  Numerical
+ * conditions are reported per walker in the optional `status` array.
+ * Calls that share a workspace must not overlap in time.
+ */
+#ifndef SHADOWOV_H
+#define SHADOWOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Interleaved complex128 (re, im), 16 bytes. */
+typedef struct {
+    double re;
+    double im;
+} so_c64;
+
+typedef enum {
+    SO_OK = 0,
+    SO_ERR_ARG = -1,         /* invalid argument: sizes, eta, null pointer, flags */
+    SO_ERR_UNSUPPORTED = -2, /* (n, eta) outside the compiled kernel sizes */
+    SO_ERR_HIP = -3,         /* a HIP runtime call (launch) failed */
+    SO_ERR_WORKSPACE = -4    /* workspace pointer null or smaller than required */
+} so_status;
+
+/* Interpolation nodes for Pf(A(z)).  UNIT: z_k = exp(2 pi i k / K) (default;
+ * a DFT, condition number 1).  CHEBYSHEV: z_k = cos((2k+1) pi / (2K)) as
+ * printed in the paper (ill-conditioned for large n). */
+enum { SO_NODES_UNIT = 0, SO_NODES_CHEBYSHEV = 1 };
+
+/* Arithmetic of the pair formation B = X C' X^T.  FP64: everything in FP64.
+ * MIXED: B formed with complex-FP32 MFMA and FP32 accumulation; Pfaffians,
+ * interpolation and reductions stay FP64. */
+enum { SO_PREC_FP64 = 0, SO_PREC_MIXED = 1 };
+
+#define SO_FLAG_PAPER_NORM 1u /* omit the factor 2 (paper's o_p as printed) */
+
+typedef struct {
+    int n;          /* modes = qubits = spin orbitals; see so_max_n() */
+    int eta;        /* electrons in the walkers: even, 2 <= eta <= n */
+    int n_nodes;    /* K interpolation nodes; 0 means n + 1; must be >= n - eta/2 + 1 */
+    int nodes;      /* SO_NODES_UNIT or SO_NODES_CHEBYSHEV */
+    int precision;  /* SO_PREC_FP64 or SO_PREC_MIXED */
+    unsigned flags; /* SO_FLAG_* */
+} so_params;
+
+/* Per-walker status bits written to the optional `status` array. */
+#define SO_WSTAT_RANK 1      /* Phi_w is rank-deficient: outputs for w are NaN */
+#define SO_WSTAT_NONFINITE 2 /* a non-finite value reached S_w */
+#define SO_WSTAT_ZERO 4      /* sum_s o_ws == 0: log and gradient undefined (NaN) */
+
+/* Largest supported n (and the supported (n, eta) pairs are those with
+ * m = 2n - eta in the compiled set; see so_supported). */
+int so_max_n(void);
+
+/* 1 if kernels are compiled for (n, eta), else 0.  Host only. */
+int so_supported(int n, int eta);
+
+/* Bytes of device workspace needed by one call with these sizes.
+ * with_grad: 0 for shadow_overlap, 1 for shadow_overlap_grad.
+ * Host only; returns SO_ERR_ARG / SO_ERR_UNSUPPORTED on bad parameters. */
+so_status so_workspace_size(const so_params *p, int64_t n_walkers, int64_t n_shadows,
+                            int with_grad, size_t *bytes);
+
+/* Host copies of the K nodes z_k and weights w_k that the kernels use, with
+ * o = sum_k w_k Pf(A(z_k)) (section "Classical shadows and the evaluation of
+ * overlaps": interpolation at the nodes, then the estimator o_p).  `nodes`
+ * and `weights` are HOST arrays of at least K entries; K is returned in
+ * *n_nodes.  Host only (no GPU needed). */
+so_status so_node_weights(const so_params *p, so_c64 *nodes, so_c64 *weights, int *n_nodes);
+
+/* Shadow-averaged overlaps.
+ *   phi       [n_walkers][n][eta] complex128, row-major (Phi_{pj} of the walker
+ *             |phi> = prod_j (sum_p Phi_pj a_p^dag)|0>, column 1 leftmost);
+ *             need not be orthonormal but must have full column rank
+ *   Q         [n_shadows][2n][2n] float64 row-major, each in SO(2n) (trusted)
+ *   bits      [n_shadows] uint64, bit j-1 = b_j of the measured bitstring
+ *   overlap   [n_walkers] complex128 out: S_w = (1/S) sum_s o_ws
+ *   pair_out  [n_walkers][n_shadows] complex128 out (o_ws), or NULL
+ *   status    [n_walkers] int32 out (SO_WSTAT_* bits), or NULL
+ *   workspace device scratch of at least so_workspace_size(p, W, S, 0) bytes
+ *   stream    hipStream_t or NULL
+ * Sizes: n_walkers >= 1, n_shadows >= 1.  Deterministic: the reduction over
+ * shadows has a fixed order, so repeated calls give identical bits. */
+so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walkers,
+                         const double *Q, const uint64_t *bits, int64_t n_shadows,
+                         so_c64 *overlap, so_c64 *pair_out, int32_t *status,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* Overlaps and their first derivative (section "Force bias and local
+ * energy": d Pf = Pf/2 Tr(A^{-1} dA), eq. Pfaffian_der, applied through
+ * A(z) = C_0^(s) + z B and B(Phi)).
+ *   overlap   [n_walkers] complex128 out: S_w
+ *   dlog      [n_walkers][n][eta] complex128 out: D_w = d log S_w / d Phi_w,
+ *             the holomorphic derivative (S_w is a polynomial in Phi_w)
+ *   green     [n_walkers][n][n] complex128 out, or NULL: mixed Green's function
+ *             G_pq = <Psi_T|a_p^dag a_q|phi>/<Psi_T|phi> = (D_w Phi_w^T)_pq
+ *   other arguments as in shadow_overlap (workspace from with_grad = 1).
+ * Walkers with S_w == 0 get SO_WSTAT_ZERO and NaN derivatives. */
+so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_walkers,
+                              const double *Q, const uint64_t *bits, int64_t n_shadows,
+                              so_c64 *overlap, so_c64 *dlog, so_c64 *green, int32_t *status,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *so_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHADOWOV_H */

@@ -1,0 +1,183 @@
+"""ctypes binding of ``libshadowov.so`` (declared in ``include/shadowov.h``).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+kernels.  PyTorch supplies device memory (tensors, the workspace) and the
+current HIP stream.  There is no CPU fallback: if the library is missing the
+import of this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshadowov.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "shadowov.h")
+
+SO_OK, SO_ERR_ARG, SO_ERR_UNSUPPORTED, SO_ERR_HIP, SO_ERR_WORKSPACE = 0, -1, -2, -3, -4
+SO_NODES = {"unit": 0, "chebyshev": 1}
+SO_PREC = {"fp64": 0, "mixed": 1}
+SO_FLAG_PAPER_NORM = 1
+SO_WSTAT_RANK, SO_WSTAT_NONFINITE, SO_WSTAT_ZERO = 1, 2, 4
+
+
+class ShadowOvError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+        self.code = code
+
+
+class SoParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("eta", ctypes.c_int), ("n_nodes", ctypes.c_int),
+                ("nodes", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class SoC64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    P = c.c_void_p
+    lib.so_max_n.restype = c.c_int
+    lib.so_supported.argtypes = [c.c_int, c.c_int]
+    lib.so_supported.restype = c.c_int
+    lib.so_workspace_size.argtypes = [c.POINTER(SoParams), c.c_int64, c.c_int64, c.c_int, c.POINTER(c.c_size_t)]
+    lib.so_workspace_size.restype = c.c_int
+    lib.so_node_weights.argtypes = [c.POINTER(SoParams), c.POINTER(SoC64), c.POINTER(SoC64), c.POINTER(c.c_int)]
+    lib.so_node_weights.restype = c.c_int
+    lib.shadow_overlap.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, P, P, c.c_size_t, P]
+    lib.shadow_overlap.restype = c.c_int
+    lib.shadow_overlap_grad.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, P, P, P,
+                                        c.c_size_t, P]
+    lib.shadow_overlap_grad.restype = c.c_int
+    lib.so_status_string.argtypes = [c.c_int]
+    lib.so_status_string.restype = c.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def header_functions() -> list[str]:
+    """Names of the functions that include/shadowov.h declares."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:so_status|int|const char\s*\*)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def status_string(code: int) -> str:
+    return lib.so_status_string(int(code)).decode()
+
+
+def make_params(n: int, eta: int, n_nodes: int = 0, nodes: str = "unit", precision: str = "fp64",
+                paper_norm: bool = False) -> SoParams:
+    return SoParams(int(n), int(eta), int(n_nodes), SO_NODES[nodes], SO_PREC[precision],
+                    SO_FLAG_PAPER_NORM if paper_norm else 0)
+
+
+def workspace_size(p: SoParams, W: int, S: int, with_grad: bool = False) -> int:
+    out = ctypes.c_size_t(0)
+    st = lib.so_workspace_size(ctypes.byref(p), int(W), int(S), int(with_grad), ctypes.byref(out))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_workspace_size")
+    return int(out.value)
+
+
+def node_weights(p: SoParams):
+    """Host copy of the nodes and weights the kernels use (complex128 numpy)."""
+    import numpy as np
+    z = (SoC64 * 64)()
+    w = (SoC64 * 64)()
+    K = ctypes.c_int(0)
+    st = lib.so_node_weights(ctypes.byref(p), z, w, ctypes.byref(K))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_node_weights")
+    k = K.value
+    return (np.array([complex(z[i].re, z[i].im) for i in range(k)]),
+            np.array([complex(w[i].re, w[i].im) for i in range(k)]))
+
+
+def _dev_ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_inputs(phi, Q, bits):
+    if not (phi.is_cuda and Q.is_cuda and bits.is_cuda):
+        raise ValueError("phi, Q and bits must be device tensors")
+    if phi.dtype != torch.complex128 or Q.dtype != torch.float64:
+        raise TypeError("phi must be complex128 and Q float64")
+    if bits.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("bits must be int64/uint64")
+    if phi.dim() != 3 or Q.dim() != 3 or bits.dim() != 1:
+        raise ValueError("phi [W,n,eta], Q [S,2n,2n], bits [S]")
+    W, n, eta = phi.shape
+    S = Q.shape[0]
+    if Q.shape[1:] != (2 * n, 2 * n) or bits.shape[0] != S:
+        raise ValueError("shape mismatch between phi, Q and bits")
+    return W, n, eta, S
+
+
+_ws_cache: dict = {}
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    key = (str(device), nbytes)
+    t = _ws_cache.get(key)
+    if t is None:
+        _ws_cache.clear()
+        t = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        _ws_cache[key] = t
+    return t
+
+
+def shadow_overlap(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_nodes: int = 0,
+                   nodes: str = "unit", precision: str = "fp64", paper_norm: bool = False,
+                   return_pairs: bool = False, workspace: torch.Tensor | None = None):
+    """S_w = (1/S) sum_s o_ws for every walker (complex128 [W]); with
+    ``return_pairs`` also the [W,S] pair estimates.  Returns (overlap, pairs
+    or None, status int32 [W])."""
+    W, n, eta, S = _check_inputs(phi, Q, bits)
+    phi, Q, bits = phi.contiguous(), Q.contiguous(), bits.contiguous()
+    p = make_params(n, eta, n_nodes, nodes, precision, paper_norm)
+    nbytes = workspace_size(p, W, S)
+    ws = workspace if workspace is not None else _workspace(nbytes, phi.device)
+    out = torch.empty(W, dtype=torch.complex128, device=phi.device)
+    pairs = torch.empty((W, S), dtype=torch.complex128, device=phi.device) if return_pairs else None
+    status = torch.zeros(W, dtype=torch.int32, device=phi.device)
+    stream = torch.cuda.current_stream(phi.device).cuda_stream
+    st = lib.shadow_overlap(ctypes.byref(p), _dev_ptr(phi), W, _dev_ptr(Q), _dev_ptr(bits), S, _dev_ptr(out),
+                            _dev_ptr(pairs), _dev_ptr(status), _dev_ptr(ws), ws.numel(),
+                            ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "shadow_overlap")
+    return out, pairs, status
+
+
+def shadow_overlap_grad(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_nodes: int = 0,
+                        nodes: str = "unit", precision: str = "fp64", paper_norm: bool = False,
+                        with_green: bool = True, workspace: torch.Tensor | None = None):
+    """S_w, D_w = d log S_w / d Phi_w (holomorphic) and G_w = D_w Phi_w^T.
+    Returns (overlap [W], dlog [W,n,eta], green [W,n,n] or None, status [W])."""
+    W, n, eta, S = _check_inputs(phi, Q, bits)
+    phi, Q, bits = phi.contiguous(), Q.contiguous(), bits.contiguous()
+    p = make_params(n, eta, n_nodes, nodes, precision, paper_norm)
+    nbytes = workspace_size(p, W, S, with_grad=True)
+    ws = workspace if workspace is not None else _workspace(nbytes, phi.device)
+    out = torch.empty(W, dtype=torch.complex128, device=phi.device)
+    dlog = torch.empty((W, n, eta), dtype=torch.complex128, device=phi.device)
+    green = torch.empty((W, n, n), dtype=torch.complex128, device=phi.device) if with_green else None
+    status = torch.zeros(W, dtype=torch.int32, device=phi.device)
+    stream = torch.cuda.current_stream(phi.device).cuda_stream
+    st = lib.shadow_overlap_grad(ctypes.byref(p), _dev_ptr(phi), W, _dev_ptr(Q), _dev_ptr(bits), S,
+                                 _dev_ptr(out), _dev_ptr(dlog), _dev_ptr(green), _dev_ptr(status),
+                                 _dev_ptr(ws), ws.numel(), ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "shadow_overlap_grad")
+    return out, dlog, green, status

@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Tolerance (FP64 path): per pair |o_gpu - o_oracle| <= 1e-10 * max(|o_oracle|,
+1e-3 * median|o_oracle|), i.e. 1e-10 relative except for pairs whose value is
+a thousand times below the typical one, which are held to 1e-13 of the typical
+magnitude (their relative error is dominated by cancellation in the node sum,
+identical in both implementations up to rounding).  Walker averages:
+|S_gpu - S_oracle| <= 1e-10 |S_oracle|.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import closed_form
+from paper_2506_22408_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2506_22408_amd import binding
+    return binding
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def to_dev(phi, Q, bits):
+    return (torch.from_numpy(np.ascontiguousarray(phi)).to(dev()),
+            torch.from_numpy(np.ascontiguousarray(Q)).to(dev()),
+            torch.from_numpy(np.ascontiguousarray(bits).view(np.int64)).to(dev()))
+
+
+def gpu_overlap(B, phi, Q, bits, **kw):
+    t = to_dev(phi, Q, bits)
+    out, pairs, status = B.shadow_overlap(*t, return_pairs=True, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), pairs.cpu().numpy(), status.cpu().numpy()
+
+
+def assert_pairs_close(og, oo, rtol=RTOL, what=""):
+    scale = np.median(np.abs(oo))
+    bound = rtol * np.maximum(np.abs(oo), 1e-3 * scale)
+    err = np.abs(og - oo)
+    bad = err > bound
+    worst = np.max(err / np.maximum(np.abs(oo), 1e-3 * scale))
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} pairs out of tolerance, worst rel {worst:.3e}"
+    return worst
+
+
+def assert_walkers_close(sg, so, rtol=RTOL, what=""):
+    rel = np.abs(sg - so) / np.abs(so)
+    assert np.all(rel <= rtol), f"{what}: worst rel {rel.max():.3e}"
+    return rel.max()
+
+
+def test_small_workload_all_pairs(B):
+    w = wl.config("small_n8")
+    sg, pg, st = gpu_overlap(B, w.phi, w.Q, w.bits)
+    po = oracle.overlap_pairs(w.phi, w.Q, w.bits)
+    print(f"small_n8 pairs worst rel {assert_pairs_close(pg, po, what='small_n8'):.2e}")
+    assert_walkers_close(sg, po.mean(axis=1), what="small_n8 S_w")
+    assert not st.any()
+
+
+@pytest.mark.parametrize("n,eta,W,S", [
+    (2, 2, 3, 4), (4, 2, 3, 5), (5, 4, 2, 7), (6, 2, 5, 9), (8, 8, 2, 3), (10, 4, 4, 11), (12, 6, 3, 13),
+    (14, 4, 2, 6), (16, 8, 5, 33), (16, 2, 2, 3), (20, 10, 3, 9), (17, 2, 2, 5), (18, 2, 2, 3),
+    (20, 4, 2, 3), (24, 12, 2, 5)])
+def test_sizes_and_ragged_shapes(B, n, eta, W, S):
+    """Every compiled size class: m = 2n - eta from 2 to 36, both kernels."""
+    w = wl.make("t", n, eta, W, S, seed=1000 + 7 * n + eta, orthonormal=(n % 2 == 0))
+    sg, pg, st = gpu_overlap(B, w.phi, w.Q, w.bits)
+    po = oracle.overlap_pairs(w.phi, w.Q, w.bits)
+    print(f"n={n} eta={eta} m={2 * n - eta}: worst rel {assert_pairs_close(pg, po, what=f'n{n}e{eta}'):.2e}")
+    assert_walkers_close(sg, po.mean(axis=1), what="S_w")
+    assert not st.any()
+
+
+def test_chebyshev_nodes_and_custom_node_count(B):
+    w = wl.make("t", 10, 4, 3, 8, seed=77)
+    for kw in (dict(nodes="chebyshev"), dict(n_nodes=14), dict(nodes="chebyshev", n_nodes=12)):
+        _, pg, _ = gpu_overlap(B, w.phi, w.Q, w.bits, **kw)
+        po = oracle.overlap_pairs(w.phi, w.Q, w.bits, K=kw.get("n_nodes") or None,
+                                  family=kw.get("nodes", "unit"))
+        assert_pairs_close(pg, po, rtol=1e-9 if kw.get("nodes") == "chebyshev" else RTOL, what=str(kw))
+
+
+def test_paper_norm_flag(B):
+    w = wl.make("t", 8, 4, 2, 5, seed=5)
+    _, p1, _ = gpu_overlap(B, w.phi, w.Q, w.bits)
+    _, p2, _ = gpu_overlap(B, w.phi, w.Q, w.bits, paper_norm=True)
+    assert np.allclose(p2 * 2, p1, rtol=1e-14, atol=0)
+
+
+def test_signed_permutation_closed_form_paper_size(B):
+    """N = 16, eta = 8 on the paper's own ensemble: exact closed form."""
+    rng = np.random.default_rng(160)
+    phi = wl.walkers(rng, 2, 16, 8)
+    Qs, refs, bl = [], [], []
+    for _ in range(3):
+        Q, perm, signs = closed_form.random_signed_permutation(rng, 16)
+        b = int(wl.even_bits(rng, 1, 16)[0])
+        Qs.append(Q)
+        bl.append(b)
+        refs.append([closed_form.overlap_pair(phi[i], perm, signs, b) for i in range(2)])
+    _, pg, _ = gpu_overlap(B, phi, np.array(Qs), np.array(bl, np.uint64))
+    ref = np.array(refs).T
+    assert_pairs_close(pg, ref, rtol=1e-10, what="closed form")
+
+
+def test_paper_sized_workload_sampled(B):
+    """The full N=16 workload (1024 walkers x 10,000 shadows, 179 shadow
+    chunks) exactly as the benchmark runs it; the oracle checks all shadows
+    of 4 walkers and 512 random pairs."""
+    w = wl.config("paper_n16")
+    sg, pg, st = gpu_overlap(B, w.phi, w.Q, w.bits)
+    assert not st.any()
+    rng = np.random.default_rng(9)
+    ws = rng.choice(w.W, 4, replace=False)
+    po_w = oracle.overlap_pairs(w.phi[ws], w.Q, w.bits)
+    assert_pairs_close(pg[ws], po_w, what="paper_n16 walkers")
+    assert_walkers_close(sg[ws], po_w.mean(axis=1), what="paper_n16 S_w")
+    pairs = np.stack([rng.integers(0, w.W, 512), rng.integers(0, w.S, 512)], axis=1)
+    po = oracle.overlap_pairs(w.phi, w.Q, w.bits, pairs=pairs)
+    worst = assert_pairs_close(pg[pairs[:, 0], pairs[:, 1]], po, what="paper_n16 sample")
+    print(f"paper_n16 sampled worst rel {worst:.2e}")
+    # S_w must be the mean of the pair estimates the kernel wrote
+    assert np.allclose(sg, pg.mean(axis=1), rtol=1e-12, atol=0)
+
+
+def test_determinism(B):
+    w = wl.make("t", 16, 8, 7, 45, seed=3)
+    a = gpu_overlap(B, w.phi, w.Q, w.bits)
+    b = gpu_overlap(B, w.phi, w.Q, w.bits)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_edge_cases(B):
+    n, eta = 8, 4
+    rng = np.random.default_rng(4)
+    phi = wl.walkers(rng, 4, n, eta)
+    Q = wl.haar_so(rng, 3, 2 * n)
+    bits = wl.even_bits(rng, 3, n)
+    # single walker, single shadow
+    sg, pg, _ = gpu_overlap(B, phi[:1], Q[:1], bits[:1])
+    assert_pairs_close(pg, oracle.overlap_pairs(phi[:1], Q[:1], bits[:1]), what="1x1")
+    # pair-preserving shadows give exactly (to rounding) zero
+    Qi = np.stack([np.eye(2 * n), np.kron(np.eye(n), [[np.cos(.4), np.sin(.4)], [-np.sin(.4), np.cos(.4)]])])
+    _, pz, _ = gpu_overlap(B, phi, Qi, np.array([0, 0b1001], np.uint64))
+    assert np.abs(pz).max() < 1e-13
+    # non-orthonormal walker with full rank is fine
+    phi2 = phi.copy()
+    phi2[1] = phi2[1] @ np.array([[2.0, 0.5, 0, 0], [0, 1, 0, 0], [0, 0, 3, 1j], [0, 0, 0, 0.7]])
+    _, pg2, st2 = gpu_overlap(B, phi2, Q, bits)
+    assert_pairs_close(pg2, oracle.overlap_pairs(phi2, Q, bits), what="non-orthonormal")
+    assert not st2.any()
+    # rank-deficient walker: flagged, NaN, the other walkers unaffected
+    phi3 = phi.copy()
+    phi3[2][:, 3] = phi3[2][:, 1]
+    sg3, pg3, st3 = gpu_overlap(B, phi3, Q, bits)
+    assert st3[2] & B.SO_WSTAT_RANK and np.isnan(sg3[2])
+    assert not st3[[0, 1, 3]].any()
+    assert_pairs_close(pg3[[0, 1, 3]], oracle.overlap_pairs(phi3[[0, 1, 3]], Q, bits), what="others")
+    # non-finite input
+    phi4 = phi.copy()
+    phi4[0, 0, 0] = np.nan
+    sg4, _, st4 = gpu_overlap(B, phi4, Q, bits)
+    assert st4[0] & B.SO_WSTAT_NONFINITE and not np.isfinite(sg4[0])
+
+
+def test_gpu_multilinearity_full_size(B):
+    """o(Phi R) = det(R) o at the paper's size, on every pair of a slice."""
+    w = wl.make("t", 16, 8, 8, 200, seed=8)
+    rng = np.random.default_rng(1)
+    R = rng.standard_normal((8, 8)) + 1j * rng.standard_normal((8, 8))
+    _, p1, _ = gpu_overlap(B, w.phi, w.Q, w.bits)
+    _, p2, _ = gpu_overlap(B, w.phi @ R, w.Q, w.bits)
+    assert_pairs_close(p2, np.linalg.det(R) * p1, rtol=1e-9, what="multilinearity")
+
+
+def test_error_paths_through_binding(B):
+    w = wl.make("t", 8, 4, 2, 3, seed=2)
+    phi, Q, bits = to_dev(w.phi, w.Q, w.bits)
+    with pytest.raises(B.ShadowOvError) as e:
+        B.shadow_overlap(phi[:, :, :3], Q, bits)          # odd eta
+    assert e.value.code == B.SO_ERR_ARG
+    small = torch.empty(16, dtype=torch.uint8, device=dev())
+    with pytest.raises(B.ShadowOvError) as e:
+        B.shadow_overlap(phi, Q, bits, workspace=small)
+    assert e.value.code == B.SO_ERR_WORKSPACE
+    with pytest.raises(B.ShadowOvError):
+        B.shadow_overlap(phi, Q, bits, n_nodes=3)          # too few nodes for the degree
