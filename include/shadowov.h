@@ -134,6 +134,17 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
                               so_c64 *overlap, so_c64 *dlog, so_c64 *green, int32_t *status,
                               void *workspace, size_t workspace_bytes, void *stream);
 
+/* Kernel timing for benchmarks (not for the hot path of an application).
+ * so_profile_enable(1) makes every later shadow_overlap call bracket each
+ * launch of its node-Pfaffian kernel (kind 0) and of its formation kernel
+ * (kind 1) with HIP events recorded on the call's stream.  so_profile_read
+ * waits for the recorded events of one kind, returns their summed duration
+ * in milliseconds, the number of launches and the number of walker x shadow
+ * pairs those launches processed, and forgets them.  Host only; events are
+ * created with hipEventCreate while enabled. */
+so_status so_profile_enable(int on);
+so_status so_profile_read(int kind, double *ms, int64_t *launches, int64_t *pairs);
+
 /* Static description of a status code. */
 const char *so_status_string(int status);
 

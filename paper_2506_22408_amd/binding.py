@@ -57,6 +57,10 @@ def _load():
     lib.shadow_overlap_grad.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, P, P, P,
                                         c.c_size_t, P]
     lib.shadow_overlap_grad.restype = c.c_int
+    lib.so_profile_enable.argtypes = [c.c_int]
+    lib.so_profile_enable.restype = c.c_int
+    lib.so_profile_read.argtypes = [c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
+    lib.so_profile_read.restype = c.c_int
     lib.so_status_string.argtypes = [c.c_int]
     lib.so_status_string.restype = c.c_char_p
     return lib
@@ -102,6 +106,24 @@ def node_weights(p: SoParams):
     k = K.value
     return (np.array([complex(z[i].re, z[i].im) for i in range(k)]),
             np.array([complex(w[i].re, w[i].im) for i in range(k)]))
+
+
+PROF_PFAFF, PROF_FORM = 0, 1
+
+
+def profile_enable(on: bool = True) -> None:
+    lib.so_profile_enable(1 if on else 0)
+
+
+def profile_read(kind: int = PROF_PFAFF):
+    """(milliseconds, launches, pairs) of the timed launches of one kernel kind."""
+    ms = ctypes.c_double(0)
+    n = ctypes.c_int64(0)
+    u = ctypes.c_int64(0)
+    st = lib.so_profile_read(int(kind), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(u))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_profile_read")
+    return ms.value, n.value, u.value
 
 
 def _dev_ptr(t: torch.Tensor | None):

@@ -20,6 +20,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <utility>
 
@@ -788,6 +789,39 @@ hipError_t launch_pfaff(int m, const double2 *B, int ne, const NodeTab &tab, int
     }
 }
 
+// ---- optional per-kernel timing (benchmarks): HIP events around launches
+enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_NKIND = 2 };
+struct ProfRec { hipEvent_t a, b; int kind; int64_t units; };
+struct ProfState {
+    bool on = false;
+    ProfRec *recs = nullptr;
+    size_t n = 0, cap = 0;
+};
+ProfState g_prof;
+
+hipError_t prof_begin(hipStream_t st, hipEvent_t *a) {
+    if (!g_prof.on) return hipSuccess;
+    hipError_t e = hipEventCreate(a);
+    if (e == hipSuccess) e = hipEventRecord(*a, st);
+    return e;
+}
+hipError_t prof_end(hipStream_t st, hipEvent_t a, int kind, int64_t units) {
+    if (!g_prof.on) return hipSuccess;
+    hipEvent_t b;
+    hipError_t e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e != hipSuccess) return e;
+    if (g_prof.n == g_prof.cap) {
+        size_t nc = g_prof.cap ? 2 * g_prof.cap : 1024;
+        ProfRec *nr = static_cast<ProfRec *>(realloc(g_prof.recs, nc * sizeof(ProfRec)));
+        if (!nr) return hipErrorOutOfMemory;
+        g_prof.recs = nr;
+        g_prof.cap = nc;
+    }
+    g_prof.recs[g_prof.n++] = ProfRec{a, b, kind, units};
+    return hipSuccess;
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -860,9 +894,14 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
     for (int64_t s0 = 0; s0 < S; s0 += L.Sc) {
         const int Sc = (int)((S - s0) < L.Sc ? (S - s0) : L.Sc);
         dim3 fgrid((unsigned)W, (unsigned)((Sc + spb - 1) / spb));
+        hipEvent_t ea = nullptr, eb = nullptr;
+        if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
         hipLaunchKernelGGL(k_form, fgrid, dim3(256), form_lds, st, n, m, X, Cp, s0, Sc, spb, Bb);
         if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+        if (prof_end(st, ea, PROF_FORM, W * Sc) != hipSuccess) return SO_ERR_HIP;
+        if (prof_begin(st, &eb) != hipSuccess) return SO_ERR_HIP;
         if (launch_pfaff(m, Bb, n - eta, tab, S, s0, Sc, W * Sc, pairs, st) != hipSuccess) return SO_ERR_HIP;
+        if (prof_end(st, eb, PROF_PFAFF, W * Sc) != hipSuccess) return SO_ERR_HIP;
     }
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)W), dim3(64), 0, st, pairs, S,
                        reinterpret_cast<double2 *>(overlap), wst);
@@ -877,6 +916,35 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
     (void)p; (void)phi; (void)n_walkers; (void)Q; (void)bits; (void)n_shadows; (void)overlap;
     (void)dlog; (void)green; (void)status; (void)workspace; (void)workspace_bytes; (void)stream;
     return SO_ERR_UNSUPPORTED;
+}
+
+so_status so_profile_enable(int on) {
+    g_prof.on = on != 0;
+    return SO_OK;
+}
+
+so_status so_profile_read(int kind, double *ms, int64_t *launches, int64_t *units) {
+    if (kind < 0 || kind >= PROF_NKIND || !ms || !launches || !units) return SO_ERR_ARG;
+    double tot = 0.0;
+    int64_t cnt = 0, un = 0;
+    size_t keep = 0;
+    for (size_t i = 0; i < g_prof.n; ++i) {
+        ProfRec &r = g_prof.recs[i];
+        if (r.kind != kind) { g_prof.recs[keep++] = r; continue; }
+        float t = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+            return SO_ERR_HIP;
+        tot += t;
+        ++cnt;
+        un += r.units;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.n = keep;
+    *ms = tot;
+    *launches = cnt;
+    *units = un;
+    return SO_OK;
 }
 
 const char *so_status_string(int s) {
