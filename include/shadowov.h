@@ -80,6 +80,9 @@ typedef struct {
 #define SO_WSTAT_RANK 1      /* Phi_w is rank-deficient: outputs for w are NaN */
 #define SO_WSTAT_NONFINITE 2 /* a non-finite value reached S_w */
 #define SO_WSTAT_ZERO 4      /* sum_s o_ws == 0: log and gradient undefined (NaN) */
+#define SO_WSTAT_FALLBACK_LOST 8 /* a pair needed the full-size path but its queue
+                                    was full: that pair's estimate may carry the
+                                    rounding of an ill-conditioned elimination */
 
 /* Largest supported n (and the supported (n, eta) pairs are those with
  * m = 2n - eta in the compiled set; see so_supported). */

@@ -21,7 +21,7 @@ SO_OK, SO_ERR_ARG, SO_ERR_UNSUPPORTED, SO_ERR_HIP, SO_ERR_WORKSPACE = 0, -1, -2,
 SO_NODES = {"unit": 0, "chebyshev": 1}
 SO_PREC = {"fp64": 0, "mixed": 1}
 SO_FLAG_PAPER_NORM = 1
-SO_WSTAT_RANK, SO_WSTAT_NONFINITE, SO_WSTAT_ZERO = 1, 2, 4
+SO_WSTAT_RANK, SO_WSTAT_NONFINITE, SO_WSTAT_ZERO, SO_WSTAT_FALLBACK_LOST = 1, 2, 4, 8
 
 
 class ShadowOvError(RuntimeError):

@@ -1,0 +1,108 @@
+// so_common.h -- device helpers shared by the shadow-overlap kernels:
+// complex arithmetic on double2, 64-lane shuffles, DPP row broadcasts and
+// reductions, and the node table passed to the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <utility>
+
+// complex helpers on double2 (x = re, y = im)
+__device__ __forceinline__ double2 c_make(double r, double i) { double2 v; v.x = r; v.y = i; return v; }
+__device__ __forceinline__ double2 c_add(double2 a, double2 b) { return c_make(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 c_sub(double2 a, double2 b) { return c_make(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 c_neg(double2 a) { return c_make(-a.x, -a.y); }
+__device__ __forceinline__ double2 c_scale(double2 a, double s) { return c_make(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 c_conj(double2 a) { return c_make(a.x, -a.y); }
+__device__ __forceinline__ double2 c_mul(double2 a, double2 b) {
+    return c_make(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// c + a * b
+__device__ __forceinline__ double2 c_fma(double2 a, double2 b, double2 c) {
+    return c_make(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double c_abs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ double2 c_sel(bool p, double2 a, double2 b) { return c_make(p ? a.x : b.x, p ? a.y : b.y); }
+// 1/a for a != 0 (scaled to avoid overflow of |a|^2)
+__device__ __forceinline__ double2 c_inv(double2 a) {
+    const double s = fmax(fabs(a.x), fabs(a.y));
+    const double2 b = c_scale(a, 1.0 / s);
+    return c_scale(c_conj(b), 1.0 / (s * c_abs2(b)));
+}
+
+// sums and broadcasts over groups of W lanes (ds_bpermute based)
+template <int W>
+__device__ __forceinline__ double grp_sum(double v) {
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, W);
+    return v;
+}
+template <int W>
+__device__ __forceinline__ double2 grp_bcast(double2 v, int src) {
+    return c_make(__shfl(v.x, src, W), __shfl(v.y, src, W));
+}
+
+// ---- DPP within 16-lane rows ------------------------------------------------
+// a 32-bit DPP move applied to both halves of a double
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64_32(double v) {
+    const long long b = __double_as_longlong(v);
+    int lo = (int)b, hi = (int)(b >> 32);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+}
+// broadcast lane SRC of each 16-lane row to the whole row (row_newbcast, a
+// 64-bit DPP move)
+template <int SRC>
+__device__ __forceinline__ double bc16(double v) {
+    long long b = __double_as_longlong(v);
+    b = __builtin_amdgcn_update_dpp(b, b, 0x150 + SRC, 0xf, 0xf, false);
+    return __longlong_as_double(b);
+}
+template <int SRC>
+__device__ __forceinline__ double2 bc16c(double2 v) { return c_make(bc16<SRC>(v.x), bc16<SRC>(v.y)); }
+// the same broadcast with an artificial data dependence on `dep` (an empty
+// asm, no instruction): it cannot be scheduled before `dep` exists, which
+// bounds how far the scheduler hoists broadcasts ahead of their use
+template <int SRC>
+__device__ __forceinline__ double bc16d(double v, double dep) {
+    asm("" : "+v"(v) : "v"(dep));
+    return bc16<SRC>(v);
+}
+template <int SRC>
+__device__ __forceinline__ double2 bc16cd(double2 v, double dep) {
+    return c_make(bc16d<SRC>(v.x, dep), bc16d<SRC>(v.y, dep));
+}
+// sum over the 16 lanes of a row (rotations: every lane gets the total)
+__device__ __forceinline__ double sum16(double v) {
+    v += dpp_f64_32<0x128>(v);   // row_ror:8
+    v += dpp_f64_32<0x124>(v);   // row_ror:4
+    v += dpp_f64_32<0x122>(v);   // row_ror:2
+    v += dpp_f64_32<0x121>(v);   // row_ror:1
+    return v;
+}
+// lane 15-i of the row (row_mirror) and lane 7-i of each half row (row_half_mirror)
+__device__ __forceinline__ double2 mirror16c(double2 v) { return c_make(dpp_f64_32<0x140>(v.x), dpp_f64_32<0x140>(v.y)); }
+__device__ __forceinline__ double2 mirror8c(double2 v) { return c_make(dpp_f64_32<0x141>(v.x), dpp_f64_32<0x141>(v.y)); }
+
+// ---- node table ---------------------------------------------------------------
+// Node matrices are s_k B + c_k J in the row order [occupied, empty] (see
+// so_prep.h).  w_k weighs pfo * Pf(s_k S + c_k J) (the Schur-complement path),
+// wf_k weighs Pf(s_k B + c_k J) (the full-size path); both carry the
+// interpolation, the inverse-channel factors, the estimator's prefactor and
+// the sign of the row permutation.
+#define SO_KMAX 49
+struct NodeTab {
+    double2 s[SO_KMAX];
+    double2 c[SO_KMAX];
+    double2 w[SO_KMAX];
+    double2 wf[SO_KMAX];
+    int K;
+    int unit_b;   // 1: every s_k == 1
+};
+
+#define SO_NMAX 32
+#define SO_NMAX_SUPPORTED 24
+#define SO_MMAX 48

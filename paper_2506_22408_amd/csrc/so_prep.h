@@ -1,0 +1,128 @@
+// so_prep.h -- per-walker and per-shadow preparation kernels.
+//
+// Row order of X, B and the node matrices.  The paper's selected index set
+// (first Majorana of each occupied orbital, both Majoranas of each empty
+// orbital) is stored as [occupied (eta rows), empty (2 ne rows)] with
+// ne = n - eta; the two rows of empty orbital t sit at eta + t and
+// eta + 2ne - 1 - t.  The selected vacuum covariance J is then zero on the
+// occupied rows and J[eta+t][eta+2ne-1-t] = +1, J[eta+2ne-1-t][eta+t] = -1.
+// The Pfaffian in this order differs from the paper's order by the sign of
+// the permutation, folded into the node weights on the host.
+#pragma once
+#include "so_common.h"
+
+// --------------------------------------------------------------------------
+// k_walker_prep: X_w (m x 2n) from Phi_w (Supp. "Matrix Definitions": the
+// selected rows of W M_phi, with the walker's orbital rotation G = [Phi | Phi_perp]).
+// Occupied orbital j:  X[j,2p] = Phi_pj/sqrt2, X[j,2p+1] = -i Phi_pj/sqrt2.
+// Empty orbital t with an orthonormal basis vector g of col(Phi)^perp (from a
+// Householder QR of Phi):
+//   row eta+t:         X[.,2p] = Re g_p,  X[.,2p+1] = Im g_p
+//   row eta+2ne-1-t:   X[.,2p] = -Im g_p, X[.,2p+1] = Re g_p
+// One 64-lane workgroup per walker, lane = orbital row p (n <= 32).  Block 0
+// also clears the fallback-queue counter of this call.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double2 *__restrict__ phi,
+                                                    double2 *__restrict__ X, int32_t *__restrict__ wstat,
+                                                    uint32_t *__restrict__ fb_count) {
+    __shared__ double2 R[SO_NMAX][SO_NMAX];
+    __shared__ double2 V[SO_NMAX][SO_NMAX];
+    __shared__ double betas[SO_NMAX];
+    const int w = blockIdx.x;
+    const int p = threadIdx.x;
+    if (w == 0 && p == 0 && fb_count) *fb_count = 0u;
+    const int m = 2 * n - eta;
+    const int d = 2 * n;
+    const int ne = n - eta;
+    const double2 *ph = phi + (size_t)w * n * eta;
+    double2 *Xw = X + (size_t)w * m * d;
+    double fro = 0.0;
+    int finite = 1;
+    if (p < n)
+        for (int j = 0; j < eta; ++j) {
+            double2 v = ph[p * eta + j];
+            R[p][j] = v;
+            fro += c_abs2(v);
+            if (!isfinite(v.x) || !isfinite(v.y)) finite = 0;
+        }
+    fro = grp_sum<64>(fro);
+    finite = __all(finite);
+    const double fnorm = sqrt(fro);
+    int rank_ok = 1;
+    __syncthreads();
+    for (int j = 0; j < eta; ++j) {
+        double2 x = (p < n && p >= j) ? R[p][j] : c_make(0, 0);
+        double nx2 = grp_sum<64>(c_abs2(x));
+        double nx = sqrt(nx2);
+        if (!(nx > 1e-13 * fnorm)) rank_ok = 0;
+        double2 x0 = R[j][j];
+        double ax = sqrt(c_abs2(x0));
+        double2 phs = ax > 0 ? c_scale(x0, 1.0 / ax) : c_make(1, 0);
+        double2 v = x;
+        if (p == j) v = c_add(v, c_scale(phs, nx));
+        double beta = (nx > 0) ? 1.0 / (nx2 + nx * ax) : 0.0;   // 2 / (v^H v)
+        if (p < n) V[p][j] = v;
+        if (p == 0) betas[j] = beta;
+        __syncthreads();
+        for (int c = j; c < eta; ++c) {
+            double2 r = (p < n) ? R[p][c] : c_make(0, 0);
+            double2 t = c_mul(c_conj(v), r);
+            double sr = grp_sum<64>(t.x), si = grp_sum<64>(t.y);
+            double2 s = c_scale(c_make(sr, si), beta);
+            __syncthreads();
+            if (p < n && p >= j) R[p][c] = c_sub(r, c_mul(s, v));
+            __syncthreads();
+        }
+    }
+    const double rs2 = 0.70710678118654752440;
+    if (p < n)
+        for (int j = 0; j < eta; ++j) {
+            double2 v = ph[p * eta + j];
+            Xw[(size_t)j * d + 2 * p] = c_scale(v, rs2);
+            Xw[(size_t)j * d + 2 * p + 1] = c_make(v.y * rs2, -v.x * rs2);
+        }
+    // g = H_0 ... H_{eta-1} e_{eta+t}
+    for (int t = 0; t < ne; ++t) {
+        double2 g = c_make(p == eta + t ? 1.0 : 0.0, 0.0);
+        for (int j = eta - 1; j >= 0; --j) {
+            double2 vj = (p < n) ? V[p][j] : c_make(0, 0);
+            double2 tt = c_mul(c_conj(vj), g);
+            double sr = grp_sum<64>(tt.x), si = grp_sum<64>(tt.y);
+            double2 s = c_scale(c_make(sr, si), betas[j]);
+            if (p < n) g = c_sub(g, c_mul(s, vj));
+        }
+        if (p < n) {
+            const int r0 = eta + t, r1 = eta + 2 * ne - 1 - t;
+            Xw[(size_t)r0 * d + 2 * p] = c_make(g.x, 0.0);
+            Xw[(size_t)r0 * d + 2 * p + 1] = c_make(g.y, 0.0);
+            Xw[(size_t)r1 * d + 2 * p] = c_make(-g.y, 0.0);
+            Xw[(size_t)r1 * d + 2 * p + 1] = c_make(g.x, 0.0);
+        }
+    }
+    if (p == 0 && wstat) wstat[w] = (rank_ok ? 0 : SO_WSTAT_RANK) | (finite ? 0 : SO_WSTAT_NONFINITE);
+}
+
+// --------------------------------------------------------------------------
+// k_shadow_prep: C'_s = Q^T C_b Q (eq. b_mat; Supp. covariance matrix),
+// C'_{mu nu} = sum_j beta_j (Q_{2j,mu} Q_{2j+1,nu} - Q_{2j+1,mu} Q_{2j,nu}).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_shadow_prep(int n, const double *__restrict__ Q,
+                                                     const uint64_t *__restrict__ bits, double *__restrict__ Cp) {
+    extern __shared__ double Qs[];
+    const int d = 2 * n;
+    const int s = blockIdx.x;
+    const double *Qg = Q + (size_t)s * d * d;
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) Qs[e] = Qg[e];
+    __syncthreads();
+    const uint64_t b = bits[s];
+    double *Cg = Cp + (size_t)s * d * d;
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+        const int mu = e / d, nu = e % d;
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double beta = ((b >> j) & 1u) ? -1.0 : 1.0;
+            acc = fma(beta, Qs[(2 * j) * d + mu] * Qs[(2 * j + 1) * d + nu] - Qs[(2 * j + 1) * d + mu] * Qs[(2 * j) * d + nu], acc);
+        }
+        Cg[e] = acc;
+    }
+}

@@ -196,3 +196,42 @@ def test_error_paths_through_binding(B):
     assert e.value.code == B.SO_ERR_WORKSPACE
     with pytest.raises(B.ShadowOvError):
         B.shadow_overlap(phi, Q, bits, n_nodes=3)          # too few nodes for the degree
+
+
+def test_occupied_elimination_growth_and_fallback(B):
+    """Shadows close to a pair-preserving rotation make the occupied block
+    B_OO nearly singular: mild cases stay on the elimination path, strong
+    ones (growth above the threshold, or an exactly zero pivot) go through
+    the full-size path; all must match the oracle."""
+    import scipy.linalg as sla
+    n, eta = 16, 8
+    rng = np.random.default_rng(31)
+    phi = wl.walkers(rng, 3, n, eta)
+    Qs = []
+    for eps in (3e-1, 1e-1, 1e-2, 1e-3, 1e-5, 1e-7, 0.0):
+        h = rng.standard_normal((2 * n, 2 * n))
+        Qs.append(sla.expm(eps * (h - h.T)))
+    Qs = np.array(Qs)
+    bits = wl.even_bits(rng, len(Qs), n)
+    sg, pg, st = gpu_overlap(B, phi, Qs, bits)
+    po = oracle.overlap_pairs(phi, Qs, bits)
+    assert not st.any()
+    scale = np.median(np.abs(po[:, :3]))      # the well-conditioned shadows set the scale
+    err = np.abs(pg - po)
+    assert np.all(err <= 1e-10 * np.maximum(np.abs(po), 1e-3 * scale)), err / np.maximum(np.abs(po), 1e-3 * scale)
+
+
+def test_fallback_queue_overflow_is_reported(B):
+    """Every pair needs the full-size path (pair-preserving shadows) and the
+    queue holds 4096 entries: the walkers whose pairs were dropped are
+    flagged; a walker without the flag has every pair exact."""
+    n, eta, W, S = 8, 4, 48, 100
+    rng = np.random.default_rng(5)
+    phi = wl.walkers(rng, W, n, eta)
+    Q = np.broadcast_to(np.eye(2 * n), (S, 2 * n, 2 * n)).copy()
+    bits = wl.even_bits(rng, S, n)
+    sg, pg, st = gpu_overlap(B, phi, Q, bits)
+    lost = (st & B.SO_WSTAT_FALLBACK_LOST) != 0
+    assert lost.any()
+    if (~lost).any():
+        assert np.abs(pg[~lost]).max() < 1e-13
