@@ -13,8 +13,9 @@
 //   k_walker_prep   X_w from Phi_w (so_prep.h)
 //   k_shadow_prep   C'_s = Q_s^T C_b Q_s (so_prep.h)
 //   per chunk of shadows:
-//     k_form_schur  B_ws, then the node-independent elimination of the
-//                   occupied indices: S_ws and Pf(B_OO) (so_form.h)
+//     k_form_mfma   B_ws on the matrix cores, then the node-independent
+//                   elimination of the occupied indices: S_ws and Pf(B_OO)
+//                   (so_form.h)
 //     k_nodes       node Pfaffians Pf(s_k S + c_k J), weighted sum (so_nodes.h)
 //   k_fallback      full-size path for the rare pairs flagged above (so_fallback.h)
 //   k_reduce        S_w = (1/S) sum_s o_ws, fixed order (deterministic)
@@ -242,6 +243,7 @@ void build_nodetab(const so_params *p, int K, NodeTab *t) {
 
 constexpr size_t kSChunkBytes = (size_t)512 << 20;   // budget for one chunk of S matrices
 constexpr int FB_GRID = 256;                           // blocks of the fallback kernel
+constexpr int kFormShadowsPerWave = 8;                 // shadows per formation wave
 
 struct Layout {
     size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_fbB, total;
@@ -253,7 +255,7 @@ size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 Layout make_layout(int n, int eta, int64_t W, int64_t S) {
     Layout L{};
-    const int m = mvalue(n, eta), d = 2 * n, M2 = m - eta;
+    const int m = mvalue(n, eta), DP = 16 * so_tiles(n), M2 = m - eta;
     const size_t per_shadow = (size_t)W * ((size_t)M2 * M2 + 1) * sizeof(double2);
     int64_t Sc = (int64_t)(kSChunkBytes / per_shadow);
     if (Sc < 1) Sc = 1;
@@ -264,8 +266,8 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S) {
     if (cap > W * S) cap = W * S;
     L.fb_cap = cap;
     size_t o = 0;
-    L.off_X = o; o = align_up(o + (size_t)W * m * d * sizeof(double2));
-    L.off_C = o; o = align_up(o + (size_t)S * d * d * sizeof(double));
+    L.off_X = o; o = align_up(o + (size_t)W * DP * DP * sizeof(double));
+    L.off_C = o; o = align_up(o + (size_t)S * DP * DP * sizeof(double));
     L.off_S = o; o = align_up(o + (size_t)W * Sc * M2 * M2 * sizeof(double2));
     L.off_P = o; o = align_up(o + (size_t)W * Sc * sizeof(double2));
     L.off_pairs = o; o = align_up(o + (size_t)W * S * sizeof(double2));
@@ -277,9 +279,54 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S) {
     return L;
 }
 
-size_t form_lds_bytes(int n, int eta, bool cs_lds) {
-    const int d = 2 * n, m = mvalue(n, eta);
-    return (size_t)(m * d + FORM_RB * d + m * (m + 1)) * sizeof(double2) + (cs_lds ? (size_t)d * d * sizeof(double) : 0);
+// Formation launch: T = ceil(2n/16) tiles, NS = S entries per lane rounded
+// up to a power of two.
+struct FormArgs {
+    int n, eta;
+    const double2 *Xa, *Ca;
+    int64_t S_total, s0;
+    int Sc, spw;
+    double2 *Sb, *Pb;
+    uint32_t *fbc;
+    int64_t *fbl, fb_cap;
+    int32_t *wst;
+    int64_t W;
+};
+
+template <int T, int NS>
+hipError_t launch_form_tn(const FormArgs &a, hipStream_t st) {
+    const int m = mvalue(a.n, a.eta);
+    const size_t lds = form_lds_bytes_t(T, a.eta, m);
+    dim3 grid((unsigned)a.W, (unsigned)((a.Sc + a.spw - 1) / a.spw));
+    hipLaunchKernelGGL((k_form_mfma<T, NS>), grid, dim3(64), lds, st, a.n, a.eta, a.Xa, a.Ca, a.S_total, a.s0,
+                       a.Sc, a.spw, a.Sb, a.Pb, a.fbc, a.fbl, a.fb_cap, a.wst);
+    return hipGetLastError();
+}
+
+template <int T>
+hipError_t launch_form_t(const FormArgs &a, int ns, hipStream_t st) {
+    if (ns <= 1) return launch_form_tn<T, 1>(a, st);
+    if (ns <= 2) return launch_form_tn<T, 2>(a, st);
+    if (ns <= 4) return launch_form_tn<T, 4>(a, st);
+    if constexpr (T >= 2) {
+        if (ns <= 8) return launch_form_tn<T, 8>(a, st);
+        if (ns <= 16) return launch_form_tn<T, 16>(a, st);
+    }
+    if constexpr (T >= 3) {
+        if (ns <= 32) return launch_form_tn<T, 32>(a, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_form(const FormArgs &a, hipStream_t st) {
+    const int M2 = 2 * (a.n - a.eta);
+    const int ns = (M2 * M2 + 63) / 64;
+    switch (so_tiles(a.n)) {
+        case 1: return launch_form_t<1>(a, ns, st);
+        case 2: return launch_form_t<2>(a, ns, st);
+        case 3: return launch_form_t<3>(a, ns, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int M2>
@@ -395,8 +442,8 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
     if (!workspace || workspace_bytes < L.total) return SO_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     char *ws = static_cast<char *>(workspace);
-    double2 *X = reinterpret_cast<double2 *>(ws + L.off_X);
-    double *Cp = reinterpret_cast<double *>(ws + L.off_C);
+    double *Xa = reinterpret_cast<double *>(ws + L.off_X);
+    double *Ca = reinterpret_cast<double *>(ws + L.off_C);
     double2 *Sb = reinterpret_cast<double2 *>(ws + L.off_S);
     double2 *Pb = reinterpret_cast<double2 *>(ws + L.off_P);
     double2 *pairs = pair_out ? reinterpret_cast<double2 *>(pair_out) : reinterpret_cast<double2 *>(ws + L.off_pairs);
@@ -408,29 +455,27 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
     build_nodetab(p, K, &tab);
 
     hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
-                       reinterpret_cast<const double2 *>(phi), X, wst, fbc);
+                       reinterpret_cast<const double2 *>(phi), Xa, wst, fbc);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q,
-                       bits, Cp);
+                       bits, Ca);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
-    const int spb = 8;
-    const bool cs_lds = form_lds_bytes(n, eta, true) <= 64 * 1024;
-    const size_t flds = form_lds_bytes(n, eta, cs_lds);
+    FormArgs fa{n, eta, reinterpret_cast<const double2 *>(Xa), reinterpret_cast<const double2 *>(Ca), S, 0, 0,
+                kFormShadowsPerWave, Sb, Pb, fbc, fbl, L.fb_cap, wst, W};
     for (int64_t s0 = 0; s0 < S; s0 += L.Sc) {
         const int Sc = (int)((S - s0) < L.Sc ? (S - s0) : L.Sc);
-        dim3 fgrid((unsigned)W, (unsigned)((Sc + spb - 1) / spb));
+        fa.s0 = s0;
+        fa.Sc = Sc;
         hipEvent_t ea = nullptr, eb = nullptr;
         if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
-        hipLaunchKernelGGL(k_form_schur, fgrid, dim3(256), flds, st, n, eta, X, Cp, S, s0, Sc, spb,
-                           cs_lds ? 1 : 0, Sb, Pb, fbc, fbl, L.fb_cap, wst);
-        if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+        if (launch_form(fa, st) != hipSuccess) return SO_ERR_HIP;
         if (prof_end(st, ea, PROF_FORM, W * Sc) != hipSuccess) return SO_ERR_HIP;
         if (prof_begin(st, &eb) != hipSuccess) return SO_ERR_HIP;
         if (launch_nodes(M2, Sb, Pb, tab, W * Sc, S, s0, Sc, pairs, st) != hipSuccess) return SO_ERR_HIP;
         if (prof_end(st, eb, PROF_PFAFF, W * Sc) != hipSuccess) return SO_ERR_HIP;
     }
-    hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), 0, st, n, eta, X, Cp, tab, fbc, fbl, L.fb_cap, S, fbB,
-                       pairs);
+    hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), 0, st, n, eta, Xa, Ca, tab, fbc, fbl, L.fb_cap, S,
+                       fbB, pairs);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)W), dim3(64), 0, st, pairs, S,
                        reinterpret_cast<double2 *>(overlap), wst);

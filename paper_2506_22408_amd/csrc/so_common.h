@@ -106,3 +106,27 @@ struct NodeTab {
 #define SO_NMAX 32
 #define SO_NMAX_SUPPORTED 24
 #define SO_MMAX 48
+
+// ---- MFMA operand order of the d x d walker and shadow matrices --------------
+// v_mfma_f64_16x16x4f64 reads, in lane l at k-step kk of row tile I, the A
+// element M[16 I + l%16][4 kk + l/16] (and the B element B[4 kk + l/16][16 J +
+// l%16]); register r of its 16 x 16 accumulator holds D[4 r + l/16][l%16].
+// The walker matrices Xall and the shadow covariances C' are stored padded
+// with zeros to DP = 16 T (T = ceil(2n/16)) in that A order, two k-steps per
+// lane as one double2, so that a wave fetches one operand pair with a single
+// coalesced 1 KiB access:
+//   flat(I, kk, l) = ((I (KK/2) + kk/2) 64 + l) 2 + kk % 2,  KK = 4 T.
+typedef double so_d4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline int so_tiles(int n) { return (2 * n + 15) / 16; }
+
+__device__ __forceinline__ int ao_index(int row, int col, int T) {
+    const int I = row >> 4, kk = col >> 2, l = (row & 15) | ((col & 3) << 4);
+    return ((I * 2 * T + (kk >> 1)) * 64 + l) * 2 + (kk & 1);
+}
+__device__ __forceinline__ void ao_rowcol(int f, int T, int &row, int &col) {
+    const int c = f & 1, l = (f >> 1) & 63, rest = f >> 7;
+    const int kh = rest % (2 * T), I = rest / (2 * T);
+    row = 16 * I + (l & 15);
+    col = 4 * (2 * kh + c) + (l >> 4);
+}

@@ -8,9 +8,16 @@
 #pragma once
 #include "so_common.h"
 
+// Row i of the complex walker matrix X from Xall (A order): Re X_O[i] and
+// Im X_O[i] for i < eta, X_U[i - eta] (real) otherwise.
+__device__ __forceinline__ double2 fb_xrow(const double *Xw, int i, int col, int eta, int T) {
+    if (i < eta) return c_make(Xw[ao_index(i, col, T)], Xw[ao_index(eta + i, col, T)]);
+    return c_make(Xw[ao_index(eta + i, col, T)], 0.0);
+}
+
 // grid FB_GRID, 64 threads; Bscratch holds FB_GRID matrices of m x m.
-__global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double2 *__restrict__ X,
-                                                 const double *__restrict__ Cp, NodeTab tab,
+__global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double *__restrict__ Xa,
+                                                 const double *__restrict__ Ca, NodeTab tab,
                                                  const uint32_t *__restrict__ fb_count,
                                                  const int64_t *__restrict__ fb_list, int64_t fb_cap, int64_t S_total,
                                                  double2 *__restrict__ Bscratch, double2 *__restrict__ pairs) {
@@ -20,27 +27,26 @@ __global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double2 *
     __shared__ double2 ybuf[SO_MMAX];
     const int q = threadIdx.x;
     const int d = 2 * n, m = 2 * n - eta, ne = n - eta, LDA = m + 1;
+    const int T = so_tiles(n), DP = 16 * T;
     const int64_t cnt = min((int64_t)(*fb_count), fb_cap);
     double2 *Bg = Bscratch + (size_t)blockIdx.x * m * m;
     for (int64_t e = blockIdx.x; e < cnt; e += gridDim.x) {
         const int64_t gs = fb_list[e];
         const int64_t w = gs / S_total, s = gs - w * S_total;
-        const double2 *Xw = X + (size_t)w * m * d;
-        const double *C = Cp + (size_t)s * d * d;
+        const double *Xw = Xa + (size_t)w * DP * DP;
+        const double *C = Ca + (size_t)s * DP * DP;
         for (int i = 0; i < m; ++i) {
             __syncthreads();
             if (q < d) {
-                double ar = 0.0, ai = 0.0;
-                for (int mu = 0; mu < d; ++mu) {
-                    ar = fma(Xw[i * d + mu].x, C[mu * d + q], ar);
-                    ai = fma(Xw[i * d + mu].y, C[mu * d + q], ai);
-                }
-                trow[q] = c_make(ar, ai);
+                double2 acc = c_make(0, 0);
+                for (int mu = 0; mu < d; ++mu)
+                    acc = c_fma(fb_xrow(Xw, i, mu, eta, T), c_make(C[ao_index(mu, q, T)], 0.0), acc);
+                trow[q] = acc;
             }
             __syncthreads();
             if (q < m) {
                 double2 acc = c_make(0, 0);
-                for (int nu = 0; nu < d; ++nu) acc = c_fma(trow[nu], Xw[q * d + nu], acc);
+                for (int nu = 0; nu < d; ++nu) acc = c_fma(trow[nu], fb_xrow(Xw, q, nu, eta, T), acc);
                 Bg[i * m + q] = acc;
             }
         }

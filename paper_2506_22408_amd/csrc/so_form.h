@@ -1,5 +1,5 @@
-// so_form.h -- pair formation and the node-independent part of the node
-// Pfaffians.
+// so_form.h -- pair formation on the matrix cores and the node-independent
+// part of the node Pfaffians.
 //
 // For a pair (w, s) the node matrices are A_k = s_k B + c_k J with
 // B = X C' X^T (eq. b_mat) and J the selected vacuum covariance (eq. a_mat),
@@ -12,144 +12,227 @@
 // confined to the occupied block; when it meets a zero pivot or S grows
 // beyond SO_SCHUR_GROWTH x max|B| the pair is queued for the full-size path
 // (so_fallback.h), which uses no elimination shortcut.
+//
+// Formation.  The empty rows of X are real, so with the real d x d matrix
+// Xall = [Re X_O; Im X_O; X_U] (so_prep.h) the pair needs two real products,
+//   U = C' Xall^T,   P = Xall U = Xall C' Xall^T,
+// on v_mfma_f64_16x16x4f64 (so_common.h for the operand order).  The
+// accumulator of U's tile (I, J), register r, is exactly the B operand of
+// P at k-step 4 I + r, so U never leaves the registers.  P is antisymmetric;
+// only its tiles I <= J are formed.  Then, with i, j < eta and t, u < 2ne,
+//   B_OO[i][j] = P[i][j] - P[eta+i][eta+j] + i (P[i][eta+j] + P[eta+i][j])
+//   B_OU[i][t] = P[i][2eta+t] + i P[eta+i][2eta+t]
+//   B_UU[t][u] = P[2eta+t][2eta+u].
+//
+// Elimination.  Only the eta occupied rows R = [B_OO | B_OU] are kept (in
+// LDS); by antisymmetry every entry the pairwise step needs below them is a
+// negated entry of R.  Step k (pivot pair k, k+1, a = R[k][k+1]) adds
+//   (R[k+1][i] R[k][j] - R[k][i] R[k+1][j]) / a
+// to every trailing entry (i, j), which for i, j empty is a rank-2 update of
+// S, accumulated in registers starting from B_UU.
 #pragma once
 #include "so_common.h"
 
-#define FORM_RB 8                 // rows of T = X C' held at a time
 #define SO_SCHUR_GROWTH 1.0e3
 
-__device__ __forceinline__ double block_max256(double v, double *red) {
-    v = fmax(v, __shfl_xor(v, 32, 64));
-    v = fmax(v, __shfl_xor(v, 16, 64));
-    v = fmax(v, __shfl_xor(v, 8, 64));
-    v = fmax(v, __shfl_xor(v, 4, 64));
-    v = fmax(v, __shfl_xor(v, 2, 64));
-    v = fmax(v, __shfl_xor(v, 1, 64));
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    const double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    __syncthreads();
-    return r;
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
 }
 
-// grid (W, ceil(Sc / spb)), 256 threads.  Dynamic LDS: X (m x 2n), T block
-// (FORM_RB x 2n), B (m x (m+1)) as complex, then C' (2n x 2n) as real when
-// cs_lds (else C' is read from global memory).
-__global__ __launch_bounds__(256) void k_form_schur(int n, int eta, const double2 *__restrict__ X,
-                                                    const double *__restrict__ Cp, int64_t S_total, int64_t s0,
-                                                    int Sc, int spb, int cs_lds, double2 *__restrict__ Sbuf,
-                                                    double2 *__restrict__ Pbuf, uint32_t *__restrict__ fb_count,
-                                                    int64_t *__restrict__ fb_list, int64_t fb_cap,
-                                                    int32_t *__restrict__ wstat) {
-    extern __shared__ double2 lds2[];
-    __shared__ double red[4];
-    __shared__ int s_piv;
-    __shared__ double s_pmax;
-    const int d = 2 * n, m = 2 * n - eta, M2 = m - eta, LDB = m + 1;
-    double2 *Xs = lds2;
-    double2 *Ts = Xs + m * d;
-    double2 *Bs = Ts + FORM_RB * d;
-    double *Cs = reinterpret_cast<double *>(Bs + m * LDB);
-    const int tid = threadIdx.x;
+// LDS (dynamic): P as DP x (DP + 1) doubles, then R as eta x m complex.
+__host__ __device__ inline size_t form_lds_bytes_t(int T, int eta, int m) {
+    const int DP = 16 * T;
+    const size_t pb = ((size_t)DP * (DP + 1) * sizeof(double) + 15) & ~(size_t)15;
+    return pb + (size_t)eta * m * sizeof(double2);
+}
+
+// grid (W, ceil(Sc / spw)), one wave per block: walker blockIdx.x, shadows
+// s0 + [blockIdx.y spw, ...) of the chunk.  NS >= ceil((2ne)^2 / 64) entries
+// of S per lane: lane l holds S[e / M2][e % M2], e = l + 64 q.
+template <int T, int NS>
+__global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const double2 *__restrict__ Xa,
+                                                  const double2 *__restrict__ Ca, int64_t S_total, int64_t s0,
+                                                  int Sc, int spw, double2 *__restrict__ Sbuf,
+                                                  double2 *__restrict__ Pbuf, uint32_t *__restrict__ fb_count,
+                                                  int64_t *__restrict__ fb_list, int64_t fb_cap,
+                                                  int32_t *__restrict__ wstat) {
+    constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
+    constexpr int MAT2 = DP * DP / 2;   // double2 per stored matrix
+    extern __shared__ double lds[];
+    double *Pl = lds;
+    double2 *Rl = reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
+                                              ((DP * LDP * sizeof(double) + 15) & ~(size_t)15));
+    const int l = threadIdx.x;
     const int w = blockIdx.x;
-    const double2 *Xg = X + (size_t)w * m * d;
-    for (int e = tid; e < m * d; e += 256) Xs[e] = Xg[e];
-    const int sl0 = blockIdx.y * spb;
-    const int sl1 = min(Sc, sl0 + spb);
-    for (int sl = sl0; sl < sl1; ++sl) {
-        const double *Cg = Cp + (size_t)(s0 + sl) * d * d;
-        __syncthreads();
-        if (cs_lds)
-            for (int e = tid; e < d * d; e += 256) Cs[e] = Cg[e];
-        const double *Csrc = cs_lds ? Cs : Cg;
-        double lmax = 0.0;
-        // B = X C' X^T, upper triangle computed, lower written as its negation
-        for (int i0 = 0; i0 < m; i0 += FORM_RB) {
-            const int rb = min(FORM_RB, m - i0);
-            __syncthreads();
-            for (int e = tid; e < rb * d; e += 256) {
-                const int i = i0 + e / d, nu = e % d;
-                double ar = 0.0, ai = 0.0;
-                for (int mu = 0; mu < d; ++mu) {
-                    const double2 xv = Xs[i * d + mu];
-                    const double c = Csrc[mu * d + nu];
-                    ar = fma(xv.x, c, ar);
-                    ai = fma(xv.y, c, ai);
-                }
-                Ts[e] = c_make(ar, ai);
+    const int m = 2 * n - eta, ne = n - eta, M2 = 2 * ne;
+
+    double xa[T][KK];
+    {
+        const double2 *Xw = Xa + (size_t)w * MAT2;
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int h = 0; h < KH; ++h) {
+                const double2 v = Xw[(I * KH + h) * 64 + l];
+                xa[I][2 * h] = v.x;
+                xa[I][2 * h + 1] = v.y;
             }
-            __syncthreads();
-            for (int e = tid; e < rb * m; e += 256) {
-                const int i = i0 + e / m, j = e % m;
-                if (j < i) continue;
-                double2 acc = c_make(0, 0);
-                if (j > i)
-                    for (int nu = 0; nu < d; ++nu) acc = c_fma(Ts[(i - i0) * d + nu], Xs[j * d + nu], acc);
-                Bs[i * LDB + j] = acc;
-                Bs[j * LDB + i] = c_neg(acc);
-                lmax = fmax(lmax, c_abs2(acc));
+    }
+    // P[a][b] for any a, b < DP from the stored tiles I <= J
+    auto Pget = [&](int a, int b) -> double {
+        return ((a >> 4) <= (b >> 4)) ? Pl[a * LDP + b] : -Pl[b * LDP + a];
+    };
+
+    const int sl0 = blockIdx.y * spw;
+    const int sl1 = min(Sc, sl0 + spw);
+    for (int sl = sl0; sl < sl1; ++sl) {
+        const double2 *Cs = Ca + (size_t)(s0 + sl) * MAT2;
+        double ca[T][KK];
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int h = 0; h < KH; ++h) {
+                const double2 v = Cs[(I * KH + h) * 64 + l];
+                ca[I][2 * h] = v.x;
+                ca[I][2 * h + 1] = v.y;
+            }
+        // U = C' Xall^T
+        so_d4 U[T][T];
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = 0; J < T; ++J) U[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = 0; J < T; ++J)
+                    U[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[I][kk], xa[J][kk], U[I][J], 0, 0, 0);
+        // P = Xall U, tiles I <= J
+        so_d4 P[T][T];
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = 0; J < T; ++J) P[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = I; J < T; ++J)
+                    P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0, 0, 0);
+
+        __syncthreads();   // the previous pair's reads of Pl and Rl are done
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = I; J < T; ++J)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Pl[(16 * I + 4 * r + (l >> 4)) * LDP + 16 * J + (l & 15)] = P[I][J][r];
+        __syncthreads();
+
+        // R = [B_OO | B_OU] and S = B_UU
+        double bmax = 0.0;
+        for (int e = l; e < eta * m; e += 64) {
+            const int i = e / m, j = e - i * m;
+            double2 v;
+            if (j < eta) {
+                v.x = Pget(i, j) - Pget(eta + i, eta + j);
+                v.y = Pget(i, eta + j) + Pget(eta + i, j);
+            } else {
+                const int c = eta + j;   // 2 eta + (j - eta)
+                v.x = Pget(i, c);
+                v.y = Pget(eta + i, c);
+            }
+            Rl[e] = v;
+            bmax = fmax(bmax, c_abs2(v));
+        }
+        double2 Sv[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int e = l + 64 * q;
+            Sv[q] = c_make(0.0, 0.0);
+            if (e < M2 * M2) {
+                const int i = e / M2, j = e - i * M2;
+                Sv[q].x = Pget(2 * eta + i, 2 * eta + j);
+                bmax = fmax(bmax, Sv[q].x * Sv[q].x);
             }
         }
-        const double maxB2 = block_max256(lmax, red);   // also orders the B writes
-        // eliminate the occupied indices 0..eta-1 pairwise
-        double2 pfo = c_make(1, 0);
+        bmax = wave_max(bmax);
+        __syncthreads();
+
+        // eliminate the occupied indices pairwise
+        double2 pfo = c_make(1.0, 0.0);
         bool zero = false;
         for (int k = 0; k < eta; k += 2) {
-            if (tid < 64) {
-                const int p = k + 1 + tid;
-                double v = (p < eta) ? c_abs2(Bs[k * LDB + p]) : -1.0;
-                int pi = p;
+            const int pc = k + 1 + l;
+            double pv = (pc < eta) ? c_abs2(Rl[k * m + pc]) : -1.0;
+            int pi = pc;
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const double ov = __shfl_xor(v, off, 64);
-                    const int op = __shfl_xor(pi, off, 64);
-                    if (ov > v || (ov == v && op < pi)) { v = ov; pi = op; }
-                }
-                if (tid == 0) { s_piv = pi; s_pmax = v; }
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double ov = __shfl_xor(pv, off, 64);
+                const int op = __shfl_xor(pi, off, 64);
+                if (ov > pv || (ov == pv && op < pi)) { pv = ov; pi = op; }
             }
-            __syncthreads();
-            const int p = s_piv;
-            if (!(s_pmax > 0.0)) { zero = true; break; }
+            if (!(pv > 0.0)) { zero = true; break; }
+            const int p = pi;
             if (p != k + 1) {
-                for (int j = tid; j < m; j += 256) {
-                    const double2 t = Bs[(k + 1) * LDB + j];
-                    Bs[(k + 1) * LDB + j] = Bs[p * LDB + j];
-                    Bs[p * LDB + j] = t;
+                if (l < m) {
+                    const double2 t0 = Rl[(k + 1) * m + l], t1 = Rl[p * m + l];
+                    Rl[(k + 1) * m + l] = t1;
+                    Rl[p * m + l] = t0;
                 }
                 __syncthreads();
-                for (int i = tid; i < m; i += 256) {
-                    const double2 t = Bs[i * LDB + k + 1];
-                    Bs[i * LDB + k + 1] = Bs[i * LDB + p];
-                    Bs[i * LDB + p] = t;
+                if (l < eta) {
+                    const double2 t0 = Rl[l * m + k + 1], t1 = Rl[l * m + p];
+                    Rl[l * m + k + 1] = t1;
+                    Rl[l * m + p] = t0;
                 }
                 __syncthreads();
                 pfo = c_neg(pfo);
             }
-            const double2 a = Bs[k * LDB + k + 1];
+            const double2 a = Rl[k * m + k + 1];
             pfo = c_mul(pfo, a);
             const double2 ia = c_inv(a);
-            const int rem = m - k - 2;
-            // A_ij -= (A_{i,k+1} A_{k,j} - A_{i,k} A_{k+1,j}) / a on the trailing block
-            for (int e = tid; e < rem * rem; e += 256) {
-                const int i = k + 2 + e / rem, j = k + 2 + e % rem;
-                const double2 t = c_sub(c_mul(Bs[i * LDB + k + 1], Bs[k * LDB + j]),
-                                        c_mul(Bs[i * LDB + k], Bs[(k + 1) * LDB + j]));
-                Bs[i * LDB + j] = c_sub(Bs[i * LDB + j], c_mul(t, ia));
+            const double2 *r0 = Rl + k * m + eta;         // R[k][eta + .]
+            const double2 *r1 = Rl + (k + 1) * m + eta;   // R[k+1][eta + .]
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int e = l + 64 * q;
+                if (e < M2 * M2) {
+                    const int i = e / M2, j = e - i * M2;
+                    const double2 t = c_sub(c_mul(r1[i], r0[j]), c_mul(r0[i], r1[j]));
+                    Sv[q] = c_fma(t, ia, Sv[q]);
+                }
+            }
+            const int j = k + 2 + l;
+            if (k + 2 < eta && j < m) {
+                const double2 rkj = Rl[k * m + j], rk1j = Rl[(k + 1) * m + j];
+                for (int i = k + 2; i < eta; ++i) {
+                    const double2 t = c_sub(c_mul(Rl[(k + 1) * m + i], rkj), c_mul(Rl[k * m + i], rk1j));
+                    Rl[i * m + j] = c_fma(t, ia, Rl[i * m + j]);
+                }
             }
             __syncthreads();
         }
+
         const int64_t pair = (int64_t)w * Sc + sl;
         double smax = 0.0;
         double2 *Sg = Sbuf + pair * (int64_t)M2 * M2;
-        for (int e = tid; e < M2 * M2; e += 256) {
-            const double2 v = Bs[(eta + e / M2) * LDB + eta + e % M2];
-            Sg[e] = v;
-            smax = fmax(smax, c_abs2(v));
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int e = l + 64 * q;
+            if (e < M2 * M2) {
+                Sg[e] = Sv[q];
+                smax = fmax(smax, c_abs2(Sv[q]));
+            }
         }
-        const double maxS2 = block_max256(smax, red);
-        const bool flag = zero || !(maxS2 <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * maxB2);
-        if (tid == 0) {
+        smax = wave_max(smax);
+        const bool flag = zero || !(smax <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * bmax);
+        if (l == 0) {
             Pbuf[pair] = pfo;
             if (flag) {
                 const uint32_t idx = atomicAdd(fb_count, 1u);

@@ -12,18 +12,21 @@
 #include "so_common.h"
 
 // --------------------------------------------------------------------------
-// k_walker_prep: X_w (m x 2n) from Phi_w (Supp. "Matrix Definitions": the
-// selected rows of W M_phi, with the walker's orbital rotation G = [Phi | Phi_perp]).
-// Occupied orbital j:  X[j,2p] = Phi_pj/sqrt2, X[j,2p+1] = -i Phi_pj/sqrt2.
+// k_walker_prep: the walker matrix X_w (Supp. "Matrix Definitions": the
+// selected rows of W M_phi, with the walker's orbital rotation
+// G = [Phi | Phi_perp]), stored as the real d x d matrix (d = 2n)
+//   Xall = [Re X_O ; Im X_O ; X_U]
+// in MFMA A order (so_common.h).  X_O (eta x d, complex) holds the occupied
+// rows and X_U (2ne x d) the empty rows, which are real.  Occupied orbital j:
+//   X_O[j,2p] = Phi_pj/sqrt2, X_O[j,2p+1] = -i Phi_pj/sqrt2.
 // Empty orbital t with an orthonormal basis vector g of col(Phi)^perp (from a
-// Householder QR of Phi):
-//   row eta+t:         X[.,2p] = Re g_p,  X[.,2p+1] = Im g_p
-//   row eta+2ne-1-t:   X[.,2p] = -Im g_p, X[.,2p+1] = Re g_p
+// Householder QR of Phi): X_U row t = (Re g_p, Im g_p)_p and X_U row 2ne-1-t =
+// (-Im g_p, Re g_p)_p.  Row i of B is X_O row i (i < eta) or X_U row i - eta.
 // One 64-lane workgroup per walker, lane = orbital row p (n <= 32).  Block 0
 // also clears the fallback-queue counter of this call.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double2 *__restrict__ phi,
-                                                    double2 *__restrict__ X, int32_t *__restrict__ wstat,
+                                                    double *__restrict__ Xa, int32_t *__restrict__ wstat,
                                                     uint32_t *__restrict__ fb_count) {
     __shared__ double2 R[SO_NMAX][SO_NMAX];
     __shared__ double2 V[SO_NMAX][SO_NMAX];
@@ -31,11 +34,10 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
     const int w = blockIdx.x;
     const int p = threadIdx.x;
     if (w == 0 && p == 0 && fb_count) *fb_count = 0u;
-    const int m = 2 * n - eta;
     const int d = 2 * n;
     const int ne = n - eta;
+    const int T = so_tiles(n), DP = 16 * T;
     const double2 *ph = phi + (size_t)w * n * eta;
-    double2 *Xw = X + (size_t)w * m * d;
     double fro = 0.0;
     int finite = 1;
     if (p < n)
@@ -74,14 +76,7 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
             __syncthreads();
         }
     }
-    const double rs2 = 0.70710678118654752440;
-    if (p < n)
-        for (int j = 0; j < eta; ++j) {
-            double2 v = ph[p * eta + j];
-            Xw[(size_t)j * d + 2 * p] = c_scale(v, rs2);
-            Xw[(size_t)j * d + 2 * p + 1] = c_make(v.y * rs2, -v.x * rs2);
-        }
-    // g = H_0 ... H_{eta-1} e_{eta+t}
+    // g_t = H_0 ... H_{eta-1} e_{eta+t}, kept in R[t][.] (R is no longer needed)
     for (int t = 0; t < ne; ++t) {
         double2 g = c_make(p == eta + t ? 1.0 : 0.0, 0.0);
         for (int j = eta - 1; j >= 0; --j) {
@@ -91,38 +86,63 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
             double2 s = c_scale(c_make(sr, si), betas[j]);
             if (p < n) g = c_sub(g, c_mul(s, vj));
         }
-        if (p < n) {
-            const int r0 = eta + t, r1 = eta + 2 * ne - 1 - t;
-            Xw[(size_t)r0 * d + 2 * p] = c_make(g.x, 0.0);
-            Xw[(size_t)r0 * d + 2 * p + 1] = c_make(g.y, 0.0);
-            Xw[(size_t)r1 * d + 2 * p] = c_make(-g.y, 0.0);
-            Xw[(size_t)r1 * d + 2 * p + 1] = c_make(g.x, 0.0);
+        if (p < n) R[t][p] = g;
+    }
+    __syncthreads();
+    const double rs2 = 0.70710678118654752440;
+    double *Xw = Xa + (size_t)w * DP * DP;
+    for (int f = p; f < DP * DP; f += 64) {
+        int row, col;
+        ao_rowcol(f, T, row, col);
+        double val = 0.0;
+        if (row < d && col < d) {
+            const int q = col >> 1, odd = col & 1;
+            if (row < 2 * eta) {
+                const int j = row < eta ? row : row - eta;
+                const double2 v = ph[q * eta + j];
+                if (row < eta) val = odd ? v.y * rs2 : v.x * rs2;    // Re X_O
+                else val = odd ? -v.x * rs2 : v.y * rs2;            // Im X_O
+            } else {
+                const int u = row - 2 * eta;
+                if (u < ne) {
+                    const double2 g = R[u][q];
+                    val = odd ? g.y : g.x;
+                } else {
+                    const double2 g = R[2 * ne - 1 - u][q];
+                    val = odd ? g.x : -g.y;
+                }
+            }
         }
+        Xw[f] = val;
     }
     if (p == 0 && wstat) wstat[w] = (rank_ok ? 0 : SO_WSTAT_RANK) | (finite ? 0 : SO_WSTAT_NONFINITE);
 }
 
 // --------------------------------------------------------------------------
 // k_shadow_prep: C'_s = Q^T C_b Q (eq. b_mat; Supp. covariance matrix),
-// C'_{mu nu} = sum_j beta_j (Q_{2j,mu} Q_{2j+1,nu} - Q_{2j+1,mu} Q_{2j,nu}).
+// C'_{mu nu} = sum_j beta_j (Q_{2j,mu} Q_{2j+1,nu} - Q_{2j+1,mu} Q_{2j,nu}),
+// written in MFMA A order, zero-padded to DP x DP.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_shadow_prep(int n, const double *__restrict__ Q,
-                                                     const uint64_t *__restrict__ bits, double *__restrict__ Cp) {
+                                                     const uint64_t *__restrict__ bits, double *__restrict__ Ca) {
     extern __shared__ double Qs[];
     const int d = 2 * n;
+    const int T = so_tiles(n), DP = 16 * T;
     const int s = blockIdx.x;
     const double *Qg = Q + (size_t)s * d * d;
     for (int e = threadIdx.x; e < d * d; e += blockDim.x) Qs[e] = Qg[e];
     __syncthreads();
     const uint64_t b = bits[s];
-    double *Cg = Cp + (size_t)s * d * d;
-    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-        const int mu = e / d, nu = e % d;
+    double *Cg = Ca + (size_t)s * DP * DP;
+    for (int f = threadIdx.x; f < DP * DP; f += blockDim.x) {
+        int mu, nu;
+        ao_rowcol(f, T, mu, nu);
         double acc = 0.0;
-        for (int j = 0; j < n; ++j) {
-            const double beta = ((b >> j) & 1u) ? -1.0 : 1.0;
-            acc = fma(beta, Qs[(2 * j) * d + mu] * Qs[(2 * j + 1) * d + nu] - Qs[(2 * j + 1) * d + mu] * Qs[(2 * j) * d + nu], acc);
-        }
-        Cg[e] = acc;
+        if (mu < d && nu < d)
+            for (int j = 0; j < n; ++j) {
+                const double beta = ((b >> j) & 1u) ? -1.0 : 1.0;
+                acc = fma(beta, Qs[(2 * j) * d + mu] * Qs[(2 * j + 1) * d + nu] - Qs[(2 * j + 1) * d + mu] * Qs[(2 * j) * d + nu], acc);
+            }
+        Cg[f] = acc;
     }
 }
