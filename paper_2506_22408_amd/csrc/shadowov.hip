@@ -112,15 +112,13 @@ bool params_ok(const so_params *p, int *K_out) {
     return true;
 }
 
-// Node weights: Pf(A(z)) = sum_{x=0}^{l} c_x z^x with l = n - eta/2, and
+// Estimator terms: Pf(A(z)) = sum_{x=0}^{l} c_x z^x with l = n - eta/2, and
 // o = pref sum_x mu_x c_x with mu_x = C(2n,2x)/C(n,x) and
 // pref = 2 i^{eta/2} / 2^{n - eta/2} (estimator o_p, times 2 unless
-// SO_FLAG_PAPER_NORM).  Interpolation at the nodes gives o = sum_k w_k p_k,
-// w = pref V^{-T} mu, V_{kx} = z_k^x.
-void compute_weights(const so_params *p, int K, double2 *z, double2 *w) {
+// SO_FLAG_PAPER_NORM).  mu_x is filled for x < nmu (zero beyond l).
+void estimator_terms(const so_params *p, int nmu, long double *mu, cld *pref) {
     const int n = p->n, eta = p->eta, ell = n - eta / 2;
-    long double mu[SO_KMAX];
-    for (int x = 0; x < K; ++x) {
+    for (int x = 0; x < nmu; ++x) {
         if (x > ell) { mu[x] = 0.0L; continue; }
         // C(2n,2x) and C(n,x) as exact integers (n <= 32: C(64,32) < 2^64)
         unsigned long long a = 1, b = 1;
@@ -128,15 +126,22 @@ void compute_weights(const so_params *p, int K, double2 *z, double2 *w) {
         for (int t = 1; t <= x; ++t) b = b * (unsigned long long)(n - x + t) / t;
         mu[x] = (long double)a / (long double)b;
     }
-    // pref = 2 i^{eta/2} 2^{-(n-eta/2)}
     const long double mag = ldexpl((p->flags & SO_FLAG_PAPER_NORM) ? 1.0L : 2.0L, -(n - eta / 2));
-    cld pref;
     switch ((eta / 2) % 4) {
-        case 0: pref = {mag, 0.0L}; break;
-        case 1: pref = {0.0L, mag}; break;
-        case 2: pref = {-mag, 0.0L}; break;
-        default: pref = {0.0L, -mag}; break;
+        case 0: *pref = {mag, 0.0L}; break;
+        case 1: *pref = {0.0L, mag}; break;
+        case 2: *pref = {-mag, 0.0L}; break;
+        default: *pref = {0.0L, -mag}; break;
     }
+}
+
+// Node weights: interpolation at the nodes gives o = sum_k w_k p_k,
+// w = pref V^{-T} mu, V_{kx} = z_k^x.
+void compute_weights(const so_params *p, int K, double2 *z, double2 *w) {
+    const int n = p->n, eta = p->eta, ell = n - eta / 2;
+    long double mu[SO_KMAX];
+    cld pref;
+    estimator_terms(p, K, mu, &pref);
     if (p->nodes == SO_NODES_UNIT) {
         const long double two_pi = 6.283185307179586476925286766559005768L;
         for (int k = 0; k < K; ++k) {
@@ -199,13 +204,19 @@ void compute_weights(const so_params *p, int K, double2 *z, double2 *w) {
     }
 }
 
-// Node table.  The kernels hold node matrices s_k B + c_k J in the row
-// order [occupied, empty] of so_prep.h.  Unit-circle nodes use
-// B + conj(z) J = A(z)/z (|z| = 1), so Pf(A(z)) = z^{m/2} Pf(B + conj(z) J)
-// and the rows start as B itself; Chebyshev nodes use z B + J.  wf_k weighs
-// Pf(s_k B + c_k J); the Schur path computes s_k^{eta/2} pfo Pf(s_k S + c_k J)
-// for the same Pfaffian and uses w_k = wf_k s_k^{eta/2}.  Both carry the
-// sign of the permutation from the paper's selected order to the stored one.
+// Node table.  Full-size path (rare pairs, so_fallback.h): node matrices
+// s_k B + c_k J in the row order [occupied, empty] of so_prep.h.  Unit-circle
+// nodes use B + conj(z) J = A(z)/z (|z| = 1), so Pf(A(z)) = z^{m/2}
+// Pf(B + conj(z) J); Chebyshev nodes use z B + J.  wf_k weighs Pf(s_k B + c_k J).
+//
+// Reduced path (so_form.h, so_nodes.h): with Q(c) = Pf(B + c J) = sum_x A_x c^x
+// (degree ne = n - eta), Pf(J + z B) = z^{m/2} Q(1/z), so the coefficient of
+// z^y in Pf(A(z)) is A_{m/2-y} and o = pref psign sum_{x=0}^{ne} mu_{m/2-x} A_x
+// whatever the node family.  Q at the roots of unity e_j = exp(2 pi i j/(ne+1))
+// gives A_x = (1/(ne+1)) sum_j Q(e_j) e_j^{-x}, hence o = sum_j v_j Q(e_j) with
+// v_j = (pref psign/(ne+1)) sum_x mu_{m/2-x} e_j^{-x}.  Q(e_j) is
+// pfo Pf(S + e_j J).  psign is the sign of the permutation from the paper's
+// selected order to the stored one.
 void build_nodetab(const so_params *p, int K, NodeTab *t) {
     double2 z[SO_KMAX], w[SO_KMAX];
     compute_weights(p, K, z, w);
@@ -220,7 +231,6 @@ void build_nodetab(const so_params *p, int K, NodeTab *t) {
     const double psign = (inv & 1) ? -1.0 : 1.0;
     std::memset(t, 0, sizeof(*t));
     t->K = K;
-    t->unit_b = (p->nodes == SO_NODES_UNIT) ? 1 : 0;
     const long double two_pi = 6.283185307179586476925286766559005768L;
     for (int k = 0; k < K; ++k) {
         const double2 wk = make_double2(w[k].x * psign, w[k].y * psign);
@@ -230,14 +240,29 @@ void build_nodetab(const so_params *p, int K, NodeTab *t) {
             t->s[k] = make_double2(1.0, 0.0);
             t->c[k] = make_double2(z[k].x, -z[k].y);
             t->wf[k] = make_double2(wk.x * cr - wk.y * ci, wk.x * ci + wk.y * cr);
-            t->w[k] = t->wf[k];
         } else {
             t->s[k] = z[k];
             t->c[k] = make_double2(1.0, 0.0);
             t->wf[k] = wk;
-            const double zp = std::pow(z[k].x, eta / 2);   // real node
-            t->w[k] = make_double2(wk.x * zp, wk.y * zp);
         }
+    }
+    long double mu[SO_KMAX];
+    cld pref;
+    estimator_terms(p, SO_KMAX, mu, &pref);
+    const int Ke = ne + 1;
+    t->Ke = Ke;
+    for (int j = 0; j < Ke; ++j) {
+        long double sr = 0.0L, si = 0.0L;
+        for (int x = 0; x <= ne; ++x) {
+            const long double th = -two_pi * (long double)((long long)j * x % Ke) / Ke;
+            sr += mu[m / 2 - x] * cosl(th);
+            si += mu[m / 2 - x] * sinl(th);
+        }
+        sr *= psign / (long double)Ke;
+        si *= psign / (long double)Ke;
+        t->v[j] = make_double2((double)(pref.re * sr - pref.im * si), (double)(pref.re * si + pref.im * sr));
+        const long double te = two_pi * (long double)j / Ke;
+        t->e[j] = make_double2((double)cosl(te), (double)sinl(te));
     }
 }
 

@@ -88,19 +88,23 @@ __device__ __forceinline__ double2 mirror16c(double2 v) { return c_make(dpp_f64_
 __device__ __forceinline__ double2 mirror8c(double2 v) { return c_make(dpp_f64_32<0x141>(v.x), dpp_f64_32<0x141>(v.y)); }
 
 // ---- node table ---------------------------------------------------------------
-// Node matrices are s_k B + c_k J in the row order [occupied, empty] (see
-// so_prep.h).  w_k weighs pfo * Pf(s_k S + c_k J) (the Schur-complement path),
-// wf_k weighs Pf(s_k B + c_k J) (the full-size path); both carry the
-// interpolation, the inverse-channel factors, the estimator's prefactor and
-// the sign of the row permutation.
+// Node matrices are s B + c J in the row order [occupied, empty] (see
+// so_prep.h).  Q(c) = Pf(B + c J) is a polynomial of degree ne = n - eta in c
+// (J has rank 2 ne), and the estimator is a fixed linear functional of its
+// coefficients.  The reduced path therefore evaluates Q at the ne + 1 roots of
+// unity e_j, as pfo Pf(S + e_j J), with weights v_j; the full-size path
+// evaluates Pf(s_k B + c_k J) at the caller's K nodes with weights wf_k.  Both
+// weight sets carry the interpolation, the inverse-channel factors, the
+// estimator's prefactor and the sign of the row permutation.
 #define SO_KMAX 49
 struct NodeTab {
-    double2 s[SO_KMAX];
+    double2 s[SO_KMAX];    // full-size path
     double2 c[SO_KMAX];
-    double2 w[SO_KMAX];
     double2 wf[SO_KMAX];
+    double2 e[SO_KMAX];    // reduced path
+    double2 v[SO_KMAX];
     int K;
-    int unit_b;   // 1: every s_k == 1
+    int Ke;
 };
 
 #define SO_NMAX 32

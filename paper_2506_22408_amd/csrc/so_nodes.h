@@ -1,5 +1,6 @@
-// so_nodes.h -- node Pfaffians Pf(s_k S + c_k J) of the Schur complement
-// S (M2 x M2, M2 = 2(n - eta)) and the weighted node sum per pair.
+// so_nodes.h -- node Pfaffians Pf(S + e_j J) of the Schur complement
+// S (M2 x M2, M2 = 2(n - eta)) at the ne + 1 roots of unity e_j, and the
+// weighted node sum per pair (so_common.h, node table).
 //
 // In the compact order every row of S belongs to an empty orbital and J
 // pairs row t with row M2-1-t: J[t][M2-1-t] = +1, J[M2-1-t][t] = -1 (t < M2/2).
@@ -15,7 +16,7 @@
 // search and no row exchange: the data flow is static, so every broadcast
 // source is a compile-time lane and every register index a constant (each
 // step is its own template instance).  J is never stored: the registers hold
-// s_k S and the J terms are added to x and y explicitly.
+// S and the J terms are added to x and y explicitly.
 //
 // Mappings (one node matrix per 16-lane DPP row, 4 per wave):
 //   M2 <= 16: lane q owns row q (pf1_step);
@@ -195,39 +196,38 @@ __global__ __launch_bounds__(64) void k_nodes(const double2 *__restrict__ Sbuf, 
     const int lane = threadIdx.x;
     const int g = lane >> 4, q = lane & 15;
     const int64_t P0 = (int64_t)blockIdx.x * PPB;
-    const int K = tab.K;
+    const int K = tab.Ke;
     for (int r = 0; r < K; ++r) {
         const int item = r * PPB + g;
         const int pl = item / K, node = item - pl * K;
         const int64_t pair = (P0 + pl < npairs) ? P0 + pl : P0;
-        const double2 sk = tab.s[node];
         double2 pf = c_make(1, 0);
         if constexpr (M2 > 0 && RPL == 1) {
             Nd1Ctx cx;
             cx.q = q;
             cx.act = q < M2;
-            cx.ck = tab.c[node];
+            cx.ck = tab.e[node];
             const double2 *row = Sbuf + pair * (M2 * M2) + (cx.act ? q : 0) * M2;
             double2 R[M2];
 #pragma unroll
-            for (int j = 0; j < M2; ++j) R[j] = tab.unit_b ? row[j] : c_mul(row[j], sk);
+            for (int j = 0; j < M2; ++j) R[j] = row[j];
             pf1_step<M2, 0>(cx, R, pf);
         } else if constexpr (M2 > 0) {
             Nd2Ctx cx;
             cx.q = q;
             cx.act = q < M2 / 2;
-            cx.ck = tab.c[node];
+            cx.ck = tab.e[node];
             const double2 *row0 = Sbuf + pair * (M2 * M2) + (cx.act ? q : 0) * M2;
             const double2 *row1 = Sbuf + pair * (M2 * M2) + (cx.act ? M2 - 1 - q : 0) * M2;
             double2 R0[M2], R1[M2];
 #pragma unroll
             for (int j = 0; j < M2; ++j) {
-                R0[j] = tab.unit_b ? row0[j] : c_mul(row0[j], sk);
-                R1[j] = tab.unit_b ? row1[j] : c_mul(row1[j], sk);
+                R0[j] = row0[j];
+                R1[j] = row1[j];
             }
             pf2_step<M2, 0>(cx, R0, R1, pf);
         }
-        if (q == 0) vals[item] = c_mul(pf, tab.w[node]);
+        if (q == 0) vals[item] = c_mul(pf, tab.v[node]);
     }
     __syncthreads();
     if (lane < PPB) {
@@ -255,12 +255,12 @@ __global__ __launch_bounds__(64) void k_nodes_wide(int M2, const double2 *__rest
     const double2 *Sg = Sbuf + pair * (int64_t)M2 * M2;
     const int LDA = SO_MMAX + 1;
     double2 acc = c_make(0, 0);
-    for (int node = 0; node < tab.K; ++node) {
-        const double2 sk = tab.s[node], ck = tab.c[node];
+    for (int node = 0; node < tab.Ke; ++node) {
+        const double2 ck = tab.e[node];
         __syncthreads();
         if (q < M2)
             for (int j = 0; j < M2; ++j) {
-                double2 v = c_mul(Sg[q * M2 + j], sk);
+                double2 v = Sg[q * M2 + j];
                 if (j == M2 - 1 - q) v = c_add(v, c_scale(ck, q < M2 / 2 ? 1.0 : -1.0));
                 A[q * LDA + j] = v;
             }
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(64) void k_nodes_wide(int M2, const double2 *__rest
                     A[q * LDA + j] = c_fma(u, ybuf[j], c_fma(c_neg(y), c_conj(ubuf[j]), A[q * LDA + j]));
             __syncthreads();
         }
-        acc = c_fma(tab.w[node], pf, acc);
+        acc = c_fma(tab.v[node], pf, acc);
     }
     if (q == 0) {
         acc = c_mul(acc, Pbuf[pair]);
