@@ -139,8 +139,10 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
 
 /* Kernel timing for benchmarks (not for the hot path of an application).
  * so_profile_enable(1) makes every later shadow_overlap call bracket each
- * launch of its node-Pfaffian kernel (kind 0) and of its formation kernel
- * (kind 1) with HIP events recorded on the call's stream.  so_profile_read
+ * launch of its node-Pfaffian kernel (kind 0), of its formation kernel
+ * (kind 1) and of its fused pair kernel (kind 2; formation, elimination and
+ * node Pfaffians in one launch, used when n - eta is even and at most 8) with
+ * HIP events recorded on the call's stream.  so_profile_read
  * waits for the recorded events of one kind, returns their summed duration
  * in milliseconds, the number of launches and the number of walker x shadow
  * pairs those launches processed, and forgets them.  Host only; events are

@@ -108,7 +108,7 @@ def node_weights(p: SoParams):
             np.array([complex(w[i].re, w[i].im) for i in range(k)]))
 
 
-PROF_PFAFF, PROF_FORM = 0, 1
+PROF_PFAFF, PROF_FORM, PROF_PAIR = 0, 1, 2
 
 
 def profile_enable(on: bool = True) -> None:

@@ -15,6 +15,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++20", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: the fused pair kernel's later
+    # stages then reuse them instead of leaving AGPRs idle
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"),
 ]
 

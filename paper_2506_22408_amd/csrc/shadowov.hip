@@ -12,7 +12,10 @@
 // Kernels, all on the caller's stream, per call:
 //   k_walker_prep   X_w from Phi_w (so_prep.h)
 //   k_shadow_prep   C'_s = Q_s^T C_b Q_s (so_prep.h)
-//   per chunk of shadows:
+//   when ne = n - eta is even and 2 <= ne <= 8:
+//     k_pair        formation, elimination of K = O u U1 down to the pencil
+//                   M0 + c M1 + c^2 M2, node Pfaffians, weighted sum (so_pair.h)
+//   otherwise, per chunk of shadows:
 //     k_form_mfma   B_ws on the matrix cores, then the node-independent
 //                   elimination of the occupied indices: S_ws and Pf(B_OO)
 //                   (so_form.h)
@@ -29,6 +32,7 @@
 #include "so_form.h"
 #include "so_nodes.h"
 #include "so_fallback.h"
+#include "so_pair.h"
 
 // --------------------------------------------------------------------------
 // k_reduce: S_w = (1/S) sum_s o_ws, fixed order: lane l sums s = l, l+64, ...
@@ -269,6 +273,7 @@ void build_nodetab(const so_params *p, int K, NodeTab *t) {
 constexpr size_t kSChunkBytes = (size_t)512 << 20;   // budget for one chunk of S matrices
 constexpr int FB_GRID = 256;                           // blocks of the fallback kernel
 constexpr int kFormShadowsPerWave = 8;                 // shadows per formation wave
+constexpr int kPairBatchesPerWave = 2;                 // node batches per fused wave
 
 struct Layout {
     size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_fbB, total;
@@ -278,6 +283,12 @@ struct Layout {
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// the fused pair kernel covers an even ne = n - eta with 2 <= ne <= 8
+bool fused_ok(int n, int eta) {
+    const int ne = n - eta;
+    return ne >= 2 && ne <= 8 && (ne % 2) == 0;
+}
+
 Layout make_layout(int n, int eta, int64_t W, int64_t S) {
     Layout L{};
     const int m = mvalue(n, eta), DP = 16 * so_tiles(n), M2 = m - eta;
@@ -285,6 +296,7 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S) {
     int64_t Sc = (int64_t)(kSChunkBytes / per_shadow);
     if (Sc < 1) Sc = 1;
     if (Sc > S) Sc = S;
+    if (fused_ok(n, eta)) Sc = 0;   // no Schur-complement chunks
     L.Sc = (int)Sc;
     int64_t cap = W * S / 256;
     if (cap < 4096) cap = 4096;
@@ -354,6 +366,52 @@ hipError_t launch_form(const FormArgs &a, hipStream_t st) {
     }
 }
 
+// Fused pair kernel: T = ceil(2n/16), NE = ne.  The grid's y extent is
+// limited to 65535, so long shadow ranges go in several launches.
+template <int T, int NE>
+hipError_t launch_pair_tn(int n, int eta, const double2 *Xa, const double2 *Ca, int64_t W, int64_t S,
+                          const RedTab &rt, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap,
+                          int32_t *wst, hipStream_t st) {
+    constexpr int NB = 64 / (NE + 1);
+    const int spw = NB * kPairBatchesPerWave;
+    const size_t lds = pair_lds_bytes(T, n, NE);
+    const int64_t ny = (S + spw - 1) / spw;
+    for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
+        const int64_t gy = (ny - y0) < 65535 ? (ny - y0) : 65535;
+        hipLaunchKernelGGL((k_pair<T, NE>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds, st, n, eta, Xa, Ca, S,
+                           y0, spw, rt, pairs, fbc, fbl, fb_cap, wst);
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    }
+    return hipSuccess;
+}
+
+template <int T>
+hipError_t launch_pair_t(int n, int eta, const double2 *Xa, const double2 *Ca, int64_t W, int64_t S,
+                         const RedTab &rt, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
+                         hipStream_t st) {
+    switch (n - eta) {
+        case 2: return launch_pair_tn<T, 2>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 4: return launch_pair_tn<T, 4>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 6: return launch_pair_tn<T, 6>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 8: return launch_pair_tn<T, 8>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pair(int n, int eta, const double2 *Xa, const double2 *Ca, int64_t W, int64_t S,
+                       const NodeTab &tab, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
+                       hipStream_t st) {
+    RedTab rt;
+    std::memset(&rt, 0, sizeof(rt));
+    for (int j = 0; j < tab.Ke; ++j) { rt.e[j] = tab.e[j]; rt.v[j] = tab.v[j]; }
+    switch (so_tiles(n)) {
+        case 1: return launch_pair_t<1>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 2: return launch_pair_t<2>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 3: return launch_pair_t<3>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int M2>
 hipError_t launch_nodes_m(const double2 *Sb, const double2 *Pb, const NodeTab &tab, int64_t npairs,
                           int64_t S, int64_t s0, int Sc, double2 *pairs, hipStream_t st) {
@@ -383,7 +441,7 @@ hipError_t launch_nodes(int M2, const double2 *Sb, const double2 *Pb, const Node
 }
 
 // ---- optional per-kernel timing (benchmarks): HIP events around launches
-enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_NKIND = 2 };
+enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_NKIND = 3 };
 struct ProfRec { hipEvent_t a, b; int kind; int64_t units; };
 struct ProfState {
     bool on = false;
@@ -485,19 +543,28 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q,
                        bits, Ca);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
-    FormArgs fa{n, eta, reinterpret_cast<const double2 *>(Xa), reinterpret_cast<const double2 *>(Ca), S, 0, 0,
-                kFormShadowsPerWave, Sb, Pb, fbc, fbl, L.fb_cap, wst, W};
-    for (int64_t s0 = 0; s0 < S; s0 += L.Sc) {
-        const int Sc = (int)((S - s0) < L.Sc ? (S - s0) : L.Sc);
-        fa.s0 = s0;
-        fa.Sc = Sc;
-        hipEvent_t ea = nullptr, eb = nullptr;
+    if (fused_ok(n, eta)) {
+        hipEvent_t ea = nullptr;
         if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
-        if (launch_form(fa, st) != hipSuccess) return SO_ERR_HIP;
-        if (prof_end(st, ea, PROF_FORM, W * Sc) != hipSuccess) return SO_ERR_HIP;
-        if (prof_begin(st, &eb) != hipSuccess) return SO_ERR_HIP;
-        if (launch_nodes(M2, Sb, Pb, tab, W * Sc, S, s0, Sc, pairs, st) != hipSuccess) return SO_ERR_HIP;
-        if (prof_end(st, eb, PROF_PFAFF, W * Sc) != hipSuccess) return SO_ERR_HIP;
+        if (launch_pair(n, eta, reinterpret_cast<const double2 *>(Xa), reinterpret_cast<const double2 *>(Ca), W, S,
+                        tab, pairs, fbc, fbl, L.fb_cap, wst, st) != hipSuccess)
+            return SO_ERR_HIP;
+        if (prof_end(st, ea, PROF_PAIR, W * S) != hipSuccess) return SO_ERR_HIP;
+    } else {
+        FormArgs fa{n, eta, reinterpret_cast<const double2 *>(Xa), reinterpret_cast<const double2 *>(Ca), S, 0, 0,
+                    kFormShadowsPerWave, Sb, Pb, fbc, fbl, L.fb_cap, wst, W};
+        for (int64_t s0 = 0; s0 < S; s0 += L.Sc) {
+            const int Sc = (int)((S - s0) < L.Sc ? (S - s0) : L.Sc);
+            fa.s0 = s0;
+            fa.Sc = Sc;
+            hipEvent_t ea = nullptr, eb = nullptr;
+            if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
+            if (launch_form(fa, st) != hipSuccess) return SO_ERR_HIP;
+            if (prof_end(st, ea, PROF_FORM, W * Sc) != hipSuccess) return SO_ERR_HIP;
+            if (prof_begin(st, &eb) != hipSuccess) return SO_ERR_HIP;
+            if (launch_nodes(M2, Sb, Pb, tab, W * Sc, S, s0, Sc, pairs, st) != hipSuccess) return SO_ERR_HIP;
+            if (prof_end(st, eb, PROF_PFAFF, W * Sc) != hipSuccess) return SO_ERR_HIP;
+        }
     }
     hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), 0, st, n, eta, Xa, Ca, tab, fbc, fbl, L.fb_cap, S,
                        fbB, pairs);

@@ -106,6 +106,11 @@ struct NodeTab {
     int K;
     int Ke;
 };
+// the reduced-path part of the table, for kernels that need nothing else
+struct RedTab {
+    double2 e[SO_KMAX];
+    double2 v[SO_KMAX];
+};
 
 #define SO_NMAX 32
 #define SO_NMAX_SUPPORTED 24

@@ -1,0 +1,397 @@
+// so_pair.h -- the fused pair kernel: formation on the matrix cores, one
+// elimination per pair that leaves a small quadratic pencil, and the node
+// Pfaffians of that pencil, one (pair, node) per lane.
+//
+// Index sets in the stored row order (so_prep.h): O = occupied (eta), U1 =
+// the first ne empty rows, U2 = the last ne (ne = n - eta).  J pairs U1 row t
+// with U2 row ne - 1 - t and vanishes on K x K, K = O u U1.  With E the U1 x U2
+// block of J and L = U2, the Schur complement of B_KK in B + c J is
+//   M(c) = B_LL - (B_LK + c J_LK) B_KK^{-1} (B_KL + c J_KL) = M0 + c M1 + c^2 M2,
+// so Pf(B + c J) = Pf(B_KK) Pf(M(c)) with M0, M1, M2 skew ne x ne.  The three
+// come from one elimination of K in the bordered skew matrix
+//   Z = [[B_KK, B_KL, J_KL], [B_LK, B_LL, 0], [J_LK, 0, 0]]:
+// its trailing block T = [[T_LL, T_LE], [T_EL, T_EE]] gives M0 = T_LL,
+// M1 = T_LE + T_EL = T_LE - T_LE^T, M2 = T_EE.
+//
+// Elimination: pairwise (Parlett-Reid) steps over K with partial pivoting over
+// all remaining indices of K (J vanishes on K x K, so any order is valid and
+// B_KK can be well conditioned even where B_OO is not); only the rows of K are
+// stored (R, in LDS), entries below them follow by antisymmetry, and the
+// trailing T is accumulated in registers from the pivot rows, as in so_form.h.
+// Pivoting bounds the multipliers of the K columns only, so the pivot rows'
+// entries in the L and E columns are watched as well: a zero pivot, or those
+// entries or T beyond SO_SCHUR_GROWTH x max(max|B|, 1), queues the pair for
+// the full-size path (so_fallback.h).
+//
+// Nodes: Q(c) = Pf(B + c J) is evaluated at the ne + 1 roots of unity e_j and
+// weighted by v_j (node table, so_common.h).  Each lane forms M(e_j) for its
+// (pair, node) and reduces it by Householder tridiagonalisation entirely in
+// registers (static indices), so a wave runs NB = 64 / (ne + 1) pairs'
+// nodes at once.
+#pragma once
+#include "so_common.h"
+#include "so_form.h"
+
+// ---- per-lane Householder Pfaffian of an N x N complex skew matrix -----------
+// A[i][j] for i < j holds the matrix (the rest is implied).  At even step k the
+// column c_i = A[i][k] = -A[k][i] (i > k) is mapped to alpha e_{k+1}, alpha =
+// -phase(c_{k+1}) |c|; Pf gains alpha and the trailing block k+2.. gets
+// A += beta (u y^T - y u^T), y = A conj(u), beta = 1 / (|c|^2 + |c| |c_{k+1}|).
+// pf_lane_from<N, K0> runs the steps K0, K0 + 2, ... on A[K0.., K0..].
+struct HhStep {
+    double2 alpha;
+    double beta;
+};
+__device__ __forceinline__ HhStep hh_setup(double nx2, double2 x0) {
+    const double nx = sqrt(nx2);
+    const double ax = sqrt(c_abs2(x0));
+    const double rax = 1.0 / (ax > 0.0 ? ax : 1.0);
+    const double2 phs = ax > 0.0 ? c_scale(x0, rax) : c_make(1.0, 0.0);
+    HhStep h;
+    h.alpha = c_scale(phs, -nx);
+    const double den = nx2 + nx * ax;
+    h.beta = den > 0.0 ? 1.0 / den : 0.0;
+    return h;
+}
+
+template <int N, int K0>
+__device__ __forceinline__ double2 pf_lane_from(double2 (&A)[N][N]) {
+    double2 pf = c_make(1.0, 0.0);
+#pragma unroll
+    for (int k = K0; k < N; k += 2) {
+        double nx2 = 0.0;
+#pragma unroll
+        for (int i = k + 1; i < N; ++i) nx2 += c_abs2(A[k][i]);
+        const double2 x0 = c_neg(A[k][k + 1]);
+        const HhStep h = hh_setup(nx2, x0);
+        pf = c_mul(pf, h.alpha);
+        if (k + 2 < N) {
+            double2 u[N];
+            u[k + 1] = c_sub(x0, h.alpha);
+#pragma unroll
+            for (int i = k + 2; i < N; ++i) u[i] = c_neg(A[k][i]);
+            double2 y[N];
+#pragma unroll
+            for (int q = k + 2; q < N; ++q) {
+                double2 acc = c_make(0.0, 0.0);
+#pragma unroll
+                for (int j = k + 1; j < N; ++j) {
+                    if (j == q) continue;
+                    const double2 aqj = (q < j) ? A[q][j] : c_neg(A[j][q]);
+                    acc = c_fma(aqj, c_conj(u[j]), acc);
+                }
+                y[q] = c_scale(acc, h.beta);
+            }
+#pragma unroll
+            for (int q = k + 2; q < N; ++q)
+#pragma unroll
+                for (int j = q + 1; j < N; ++j) A[q][j] = c_fma(u[q], y[j], c_fma(c_neg(y[q]), u[j], A[q][j]));
+        }
+    }
+    return pf;
+}
+
+// LDS per wave: region A = max(P (DP x (DP+1) f64), R (n x (n + 2 NE) c128),
+// T (NE (2NE - 1) c128), node values), then the batch: NB slots of
+// 3 NE (NE-1)/2 + 1 complex (M0, M1, M2 upper triangles, Pf(B_KK)).
+__host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
+    const int DP = 16 * T;
+    const int NB = 64 / (NE + 1);
+    size_t a = (size_t)DP * (DP + 1) * sizeof(double);
+    const size_t r = (size_t)n * (n + 2 * NE) * sizeof(double2);
+    const size_t t = (size_t)NE * (2 * NE - 1) * sizeof(double2);
+    const size_t v = (size_t)64 * sizeof(double2);
+    if (r > a) a = r;
+    if (t > a) a = t;
+    if (v > a) a = v;
+    a = (a + 15) & ~(size_t)15;
+    return a + (size_t)NB * (3 * (NE * (NE - 1) / 2) + 1) * sizeof(double2);
+}
+
+// grid (W, ceil(S_total / spw)), one wave per block; spw is a multiple of NB.
+template <int T, int NE>
+__global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__restrict__ Xa,
+                                             const double2 *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
+                                             RedTab tab, double2 *__restrict__ pairs,
+                                             uint32_t *__restrict__ fb_count, int64_t *__restrict__ fb_list,
+                                             int64_t fb_cap, int32_t *__restrict__ wstat) {
+    constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
+    constexpr int MAT2 = DP * DP / 2;
+    constexpr int KE = NE + 1;
+    constexpr int NB = 64 / KE;
+    constexpr int NT = NE * (NE - 1) / 2;         // upper entries of one NE x NE matrix
+    constexpr int NT2 = NE * (2 * NE - 1);        // upper entries of the 2NE x 2NE trailing block
+    constexpr int NTQ = (NT2 + 63) / 64;          // trailing entries per lane
+    constexpr int SLOT = 3 * NT + 1;
+    extern __shared__ double lds[];
+    double *Pl = lds;
+    double2 *Rl = reinterpret_cast<double2 *>(lds);
+    double2 *Tl = reinterpret_cast<double2 *>(lds);
+    double2 *Vl = reinterpret_cast<double2 *>(lds);
+    size_t abytes = (size_t)DP * LDP * sizeof(double);
+    {
+        const size_t r = (size_t)n * (n + 2 * NE) * sizeof(double2);
+        const size_t t = (size_t)NT2 * sizeof(double2);
+        if (r > abytes) abytes = r;
+        if (t > abytes) abytes = t;
+        if (64 * sizeof(double2) > abytes) abytes = 64 * sizeof(double2);
+        abytes = (abytes + 15) & ~(size_t)15;
+    }
+    double2 *Bt = reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) + abytes);   // batch slots
+
+    const int l = threadIdx.x;
+    const int w = blockIdx.x;
+    const int WR = n + 2 * NE;              // columns of R: K (n), L (NE), E (NE)
+
+    // this lane's trailing entries (a < b) of the 2NE x 2NE block
+    int ta[NTQ], tb[NTQ];
+#pragma unroll
+    for (int q = 0; q < NTQ; ++q) {
+        int e = l + 64 * q, a = 0;
+        if (e >= NT2) e = 0;
+        while (e >= 2 * NE - 1 - a) { e -= 2 * NE - 1 - a; ++a; }
+        ta[q] = a;
+        tb[q] = a + 1 + e;
+    }
+
+    const double2 *Xw = Xa + (size_t)w * MAT2;
+    auto Pget = [&](int a, int b) -> double { return Pl[a * LDP + b]; };
+    // Xall rows of the real and imaginary parts of stored row i (-1: none)
+    auto rre = [&](int i) -> int { return i < eta ? i : eta + i; };
+    auto rim = [&](int i) -> int { return i < eta ? eta + i : -1; };
+    auto Bget = [&](int i, int j) -> double2 {
+        const int ir = rre(i), ii = rim(i), jr = rre(j), ji = rim(j);
+        double re = Pget(ir, jr), im = 0.0;
+        if (ii >= 0 && ji >= 0) re -= Pget(ii, ji);
+        if (ji >= 0) im += Pget(ir, ji);
+        if (ii >= 0) im += Pget(ii, jr);
+        return c_make(re, im);
+    };
+
+    const int64_t sb0 = (sy0 + blockIdx.y) * (int64_t)spw;
+    const int64_t sb1 = min(S_total, sb0 + spw);
+    for (int64_t bs = sb0; bs < sb1; bs += NB) {
+        const int nb = (int)min((int64_t)NB, sb1 - bs);
+        for (int b = 0; b < nb; ++b) {
+            const int64_t s = bs + b;
+            // ---------------- formation: P = Xall C' Xall^T
+            // operands: the walker's Xall (re-read from L2 per pair: keeping it
+            // live through the elimination and node stages costs occupancy) and C'_s
+            const double2 *Cs = Ca + (size_t)s * MAT2;
+            double xa[T][KK], ca[T][KK];
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int h = 0; h < KH; ++h) {
+                    const double2 v = Xw[(I * KH + h) * 64 + l];
+                    const double2 c = Cs[(I * KH + h) * 64 + l];
+                    xa[I][2 * h] = v.x;
+                    xa[I][2 * h + 1] = v.y;
+                    ca[I][2 * h] = c.x;
+                    ca[I][2 * h + 1] = c.y;
+                }
+            so_d4 U[T][T];
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = 0; J < T; ++J) U[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+                for (int I = 0; I < T; ++I)
+#pragma unroll
+                    for (int J = 0; J < T; ++J)
+                        U[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[I][kk], xa[J][kk], U[I][J], 0, 0, 0);
+            so_d4 P[T][T];
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = 0; J < T; ++J) P[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+                for (int I = 0; I < T; ++I)
+#pragma unroll
+                    for (int J = I; J < T; ++J)
+                        P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0,
+                                                                       0, 0);
+            __syncthreads();   // region A is free
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = I; J < T; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int a = 16 * I + 4 * r + (l >> 4), bcol = 16 * J + (l & 15);
+                        Pl[a * LDP + bcol] = P[I][J][r];
+                        if (J > I) Pl[bcol * LDP + a] = -P[I][J][r];   // P is antisymmetric
+                    }
+            __syncthreads();
+
+            // ---------------- R = rows K of Z, trailing T = [[B_LL, 0], [0, 0]]
+            constexpr int RPL = (8 * T * (8 * T + 2 * NE) + 63) / 64;   // R entries per lane (n <= 8 T)
+            // the lane index through an opaque move: the entry indices and LDS
+            // addresses below are then computed here, not hoisted out of the
+            // shadow loop where they would stay live through the other stages
+            int lr = l;
+            asm volatile("" : "+v"(lr));
+            double2 rv[RPL];
+            double bmax = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int e = lr + 64 * q;
+                rv[q] = c_make(0.0, 0.0);
+                if (e < n * WR) {
+                    const int i = e / WR, j = e - i * WR;
+                    if (j < n + NE) {
+                        rv[q] = Bget(i, j);   // K and L columns are stored indices
+                        bmax = fmax(bmax, c_abs2(rv[q]));
+                    } else {
+                        rv[q].x = (i >= eta && i - eta == NE - 1 - (j - n - NE)) ? 1.0 : 0.0;
+                    }
+                }
+                // finish this entry before the next one's loads (register pressure)
+                asm volatile("" : "+v"(rv[q].x), "+v"(rv[q].y) : : "memory");
+            }
+            double2 tv[NTQ];
+#pragma unroll
+            for (int q = 0; q < NTQ; ++q) {
+                tv[q] = c_make(0.0, 0.0);
+                if (l + 64 * q < NT2 && tb[q] < NE) {
+                    tv[q].x = Pget(2 * eta + NE + ta[q], 2 * eta + NE + tb[q]);
+                    bmax = fmax(bmax, tv[q].x * tv[q].x);
+                }
+            }
+            bmax = wave_max(bmax);
+            __syncthreads();   // P reads done
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const int e = lr + 64 * q;
+                if (e < n * WR) Rl[e] = rv[q];
+            }
+            __syncthreads();
+
+            // ---------------- pairwise elimination of K
+            double2 pfk = c_make(1.0, 0.0);
+            bool zero = false;
+            double gmax = 0.0;   // largest |entry|^2 of the pivot rows in the L and E columns
+            for (int k = 0; k < n; k += 2) {
+                const int pc = k + 1 + l;
+                double pv = (pc < n) ? c_abs2(Rl[k * WR + pc]) : -1.0;
+                int pi = pc;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    const double ov = __shfl_xor(pv, off, 64);
+                    const int op = __shfl_xor(pi, off, 64);
+                    if (ov > pv || (ov == pv && op < pi)) { pv = ov; pi = op; }
+                }
+                if (!(pv > 0.0)) { zero = true; break; }
+                const int p = pi;
+                if (p != k + 1) {
+                    if (l < WR) {
+                        const double2 t0 = Rl[(k + 1) * WR + l], t1 = Rl[p * WR + l];
+                        Rl[(k + 1) * WR + l] = t1;
+                        Rl[p * WR + l] = t0;
+                    }
+                    __syncthreads();
+                    if (l < n) {
+                        const double2 t0 = Rl[l * WR + k + 1], t1 = Rl[l * WR + p];
+                        Rl[l * WR + k + 1] = t1;
+                        Rl[l * WR + p] = t0;
+                    }
+                    __syncthreads();
+                    pfk = c_neg(pfk);
+                }
+                const double2 a = Rl[k * WR + k + 1];
+                pfk = c_mul(pfk, a);
+                const double2 ia = c_inv(a);
+                const double2 *r0 = Rl + k * WR;
+                const double2 *r1 = Rl + (k + 1) * WR;
+#pragma unroll
+                for (int q = 0; q < NTQ; ++q) {
+                    if (l + 64 * q < NT2) {
+                        const int ca_ = n + ta[q], cb_ = n + tb[q];
+                        const double2 x0a = r0[ca_], x0b = r0[cb_], x1a = r1[ca_], x1b = r1[cb_];
+                        gmax = fmax(gmax, fmax(fmax(c_abs2(x0a), c_abs2(x0b)), fmax(c_abs2(x1a), c_abs2(x1b))));
+                        const double2 t = c_sub(c_mul(x1a, x0b), c_mul(x0a, x1b));
+                        tv[q] = c_fma(t, ia, tv[q]);
+                    }
+                }
+                // rows i in [k+2, n), columns j in [k+2, WR); lane halves take alternate rows
+                const int h = l >> 5;
+                for (int j = k + 2 + (l & 31); j < WR; j += 32) {
+                    const double2 rkj = r0[j], rk1j = r1[j];
+                    for (int i = k + 2 + h; i < n; i += 2) {
+                        const double2 t = c_sub(c_mul(r1[i], rkj), c_mul(r0[i], rk1j));
+                        Rl[i * WR + j] = c_fma(t, ia, Rl[i * WR + j]);
+                    }
+                }
+                __syncthreads();
+            }
+            double tmax = 0.0;
+#pragma unroll
+            for (int q = 0; q < NTQ; ++q) tmax = fmax(tmax, c_abs2(tv[q]));
+            tmax = wave_max(fmax(tmax, gmax));
+            const bool flag = zero || !(tmax <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * fmax(bmax, 1.0));
+            if (l == 0 && flag) {
+                const uint32_t idx = atomicAdd(fb_count, 1u);
+                if ((int64_t)idx < fb_cap) fb_list[idx] = (int64_t)w * S_total + s;
+                else atomicOr(&wstat[w], SO_WSTAT_FALLBACK_LOST);
+            }
+            // ---------------- M0, M1, M2 (upper triangles) and Pf(B_KK) into the batch slot
+            __syncthreads();   // R reads done
+#pragma unroll
+            for (int q = 0; q < NTQ; ++q)
+                if (l + 64 * q < NT2) Tl[l + 64 * q] = flag ? c_make(0.0, 0.0) : tv[q];
+            __syncthreads();
+            double2 *slot = Bt + b * SLOT;
+            // upper-triangle index of (a, b), a < b < 2NE
+            auto tix = [&](int a, int bb) -> int { return a * (2 * NE - 1) - a * (a - 1) / 2 + (bb - a - 1); };
+            for (int e = l; e < NT; e += 64) {
+                int x = 0, r = e;
+                while (r >= NE - 1 - x) { r -= NE - 1 - x; ++x; }
+                const int y = x + 1 + r;
+                slot[e] = Tl[tix(x, y)];                                              // M0
+                slot[NT + e] = c_sub(Tl[tix(x, NE + y)], Tl[tix(y, NE + x)]);         // M1
+                slot[2 * NT + e] = Tl[tix(NE + x, NE + y)];                           // M2
+            }
+            if (l == 0) slot[3 * NT] = flag ? c_make(0.0, 0.0) : pfk;
+        }
+        // ---------------- node Pfaffians of the batch, one (pair, node) per lane
+        __syncthreads();
+        int ln = l;
+        asm volatile("" : "+v"(ln));   // as above: no hoisting out of the loops
+        const int pb = ln / KE, nj = ln - pb * KE;
+        double2 val = c_make(0.0, 0.0);
+        if (pb < nb) {
+            const double2 *slot = Bt + pb * SLOT;
+            const double2 cj = tab.e[nj];
+            const double2 cj2 = c_mul(cj, cj);
+            // M(c) = M0 + c M1 + c^2 M2, upper triangle, row by row
+            double2 A[NE][NE];
+            int e = 0;
+#pragma unroll
+            for (int x = 0; x < NE - 1; ++x) {
+#pragma unroll
+                for (int y = x + 1; y < NE; ++y) {
+                    A[x][y] = c_fma(cj2, slot[2 * NT + e], c_fma(cj, slot[NT + e], slot[e]));
+                    ++e;
+                }
+                // finish each row before the next row's loads are issued, so the
+                // three operands per entry are not all held at once
+#pragma unroll
+                for (int y = x + 1; y < NE; ++y) asm volatile("" : "+v"(A[x][y].x), "+v"(A[x][y].y));
+                asm volatile("" ::: "memory");
+            }
+            val = c_mul(pf_lane_from<NE, 0>(A), tab.v[nj]);
+        }
+        Vl[l] = val;
+        __syncthreads();
+        if (l < nb) {
+            double2 acc = c_make(0.0, 0.0);
+            for (int j = 0; j < KE; ++j) acc = c_add(acc, Vl[l * KE + j]);
+            acc = c_mul(acc, Bt[l * SLOT + 3 * NT]);
+            pairs[(int64_t)w * S_total + bs + l] = acc;
+        }
+    }
+}

@@ -69,11 +69,14 @@ def test_small_workload_all_pairs(B):
 
 
 @pytest.mark.parametrize("n,eta,W,S", [
-    (2, 2, 3, 4), (4, 2, 3, 5), (5, 4, 2, 7), (6, 2, 5, 9), (8, 8, 2, 3), (10, 4, 4, 11), (12, 6, 3, 13),
-    (14, 4, 2, 6), (16, 8, 5, 33), (16, 2, 2, 3), (20, 10, 3, 9), (17, 2, 2, 5), (18, 2, 2, 3),
-    (20, 4, 2, 3), (24, 12, 2, 5)])
+    # two-kernel path (ne = n - eta odd, 0 or above 8)
+    (2, 2, 3, 4), (5, 4, 2, 7), (8, 8, 2, 3), (14, 4, 2, 6), (16, 2, 2, 3), (20, 10, 3, 9), (17, 2, 2, 5),
+    (18, 2, 2, 3), (20, 4, 2, 3), (24, 12, 2, 5),
+    # fused pair kernel, every (tiles, ne) instance; S ragged against the node batches
+    (4, 2, 3, 5), (6, 2, 5, 9), (8, 2, 3, 7), (10, 4, 4, 11), (12, 6, 3, 13), (12, 8, 3, 10), (16, 14, 2, 5),
+    (16, 8, 5, 33), (18, 16, 2, 4), (20, 16, 2, 5), (22, 16, 2, 4), (24, 16, 2, 9)])
 def test_sizes_and_ragged_shapes(B, n, eta, W, S):
-    """Every compiled size class: m = 2n - eta from 2 to 36, both kernels."""
+    """Every compiled size class: m = 2n - eta from 2 to 46, both paths."""
     w = wl.make("t", n, eta, W, S, seed=1000 + 7 * n + eta, orthonormal=(n % 2 == 0))
     sg, pg, st = gpu_overlap(B, w.phi, w.Q, w.bits)
     po = oracle.overlap_pairs(w.phi, w.Q, w.bits)
@@ -221,17 +224,24 @@ def test_occupied_elimination_growth_and_fallback(B):
     assert np.all(err <= 1e-10 * np.maximum(np.abs(po), 1e-3 * scale)), err / np.maximum(np.abs(po), 1e-3 * scale)
 
 
-def test_fallback_queue_overflow_is_reported(B):
-    """Every pair needs the full-size path (pair-preserving shadows) and the
-    queue holds 4096 entries: the walkers whose pairs were dropped are
-    flagged; a walker without the flag has every pair exact."""
-    n, eta, W, S = 8, 4, 48, 100
+@pytest.mark.parametrize("n,eta", [(8, 4), (9, 4)])     # fused pair kernel; two-kernel path
+def test_fallback_queue_overflow_is_reported(B, n, eta):
+    """Walkers whose orbitals are single modes, with the identity shadow and
+    b = 0, make the occupied rows of B exactly zero (every product that could
+    contribute has a zero factor), so every pair meets a zero pivot and needs
+    the full-size path; the queue holds 4096 of the 4800 pairs.  The walkers
+    whose pairs were dropped are flagged; a walker without the flag has every
+    pair exact (the overlap of a pair-preserving shadow is zero)."""
+    W, S = 48, 100
     rng = np.random.default_rng(5)
-    phi = wl.walkers(rng, W, n, eta)
+    phi = np.zeros((W, n, eta), complex)
+    for w in range(W):
+        phi[w, rng.choice(n, eta, replace=False), np.arange(eta)] = 1.0
     Q = np.broadcast_to(np.eye(2 * n), (S, 2 * n, 2 * n)).copy()
-    bits = wl.even_bits(rng, S, n)
+    bits = np.zeros(S, np.uint64)
     sg, pg, st = gpu_overlap(B, phi, Q, bits)
     lost = (st & B.SO_WSTAT_FALLBACK_LOST) != 0
     assert lost.any()
+    assert not (st & ~B.SO_WSTAT_FALLBACK_LOST).any()
     if (~lost).any():
         assert np.abs(pg[~lost]).max() < 1e-13
