@@ -84,6 +84,38 @@ __device__ __forceinline__ double sum16(double v) {
     return v;
 }
 // lane 15-i of the row (row_mirror) and lane 7-i of each half row (row_half_mirror)
+// 1/x for finite x != 0: the hardware reciprocal refined by two Newton steps
+// (each squares the relative error), so the result is within an ulp or two.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+// 1/a for a != 0, scaled so that |a|^2 cannot overflow or underflow
+__device__ __forceinline__ double2 c_inv_nr(double2 a) {
+    const double rs = rcp_nr(fmax(fabs(a.x), fabs(a.y)));
+    const double2 b = c_scale(a, rs);          // largest component +-1
+    return c_scale(c_conj(b), rcp_nr(c_abs2(b)) * rs);
+}
+
+// wave-wide maximum of unsigned keys, returned uniformly: DPP within each
+// 16-lane row (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror leave every lane of a row with the row's maximum), then the four
+// rows on the scalar unit
+__device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xf, 0xf, false));
+    const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+    const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+    const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+    const unsigned d = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(a, b), max(c, d));
+}
+
 __device__ __forceinline__ double2 mirror16c(double2 v) { return c_make(dpp_f64_32<0x140>(v.x), dpp_f64_32<0x140>(v.y)); }
 __device__ __forceinline__ double2 mirror8c(double2 v) { return c_make(dpp_f64_32<0x141>(v.x), dpp_f64_32<0x141>(v.y)); }
 

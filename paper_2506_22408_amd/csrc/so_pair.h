@@ -91,13 +91,13 @@ __device__ __forceinline__ double2 pf_lane_from(double2 (&A)[N][N]) {
     return pf;
 }
 
-// LDS per wave: region A = max(P (DP x (DP+1) f64), R (n x (n + 2 NE) c128),
+// LDS per wave: region A = max(P ((DP+1) x (DP+1) f64), R (n x (n + 2 NE) c128),
 // T (NE (2NE - 1) c128), node values), then the batch: NB slots of
 // 3 NE (NE-1)/2 + 1 complex (M0, M1, M2 upper triangles, Pf(B_KK)).
 __host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
     const int DP = 16 * T;
     const int NB = 64 / (NE + 1);
-    size_t a = (size_t)DP * (DP + 1) * sizeof(double);
+    size_t a = (size_t)(DP + 1) * (DP + 1) * sizeof(double);
     const size_t r = (size_t)n * (n + 2 * NE) * sizeof(double2);
     const size_t t = (size_t)NE * (2 * NE - 1) * sizeof(double2);
     const size_t v = (size_t)64 * sizeof(double2);
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
     double2 *Rl = reinterpret_cast<double2 *>(lds);
     double2 *Tl = reinterpret_cast<double2 *>(lds);
     double2 *Vl = reinterpret_cast<double2 *>(lds);
-    size_t abytes = (size_t)DP * LDP * sizeof(double);
+    size_t abytes = (size_t)(DP + 1) * LDP * sizeof(double);
     {
         const size_t r = (size_t)n * (n + 2 * NE) * sizeof(double2);
         const size_t t = (size_t)NT2 * sizeof(double2);
@@ -156,16 +156,13 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
 
     const double2 *Xw = Xa + (size_t)w * MAT2;
     auto Pget = [&](int a, int b) -> double { return Pl[a * LDP + b]; };
-    // Xall rows of the real and imaginary parts of stored row i (-1: none)
+    // Xall rows of the real and imaginary parts of stored row i; an empty
+    // orbital's row is real, and its imaginary part points at the zero row DP
     auto rre = [&](int i) -> int { return i < eta ? i : eta + i; };
-    auto rim = [&](int i) -> int { return i < eta ? eta + i : -1; };
+    auto rim = [&](int i) -> int { return i < eta ? eta + i : DP; };
     auto Bget = [&](int i, int j) -> double2 {
-        const int ir = rre(i), ii = rim(i), jr = rre(j), ji = rim(j);
-        double re = Pget(ir, jr), im = 0.0;
-        if (ii >= 0 && ji >= 0) re -= Pget(ii, ji);
-        if (ji >= 0) im += Pget(ir, ji);
-        if (ii >= 0) im += Pget(ii, jr);
-        return c_make(re, im);
+        const int ir = rre(i) * LDP, ii = rim(i) * LDP, jr = rre(j), ji = rim(j);
+        return c_make(Pl[ir + jr] - Pl[ii + ji], Pl[ir + ji] + Pl[ii + jr]);
     };
 
     const int64_t sb0 = (sy0 + blockIdx.y) * (int64_t)spw;
@@ -226,29 +223,34 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
                         Pl[a * LDP + bcol] = P[I][J][r];
                         if (J > I) Pl[bcol * LDP + a] = -P[I][J][r];   // P is antisymmetric
                     }
+            // row and column DP are zero (R overlays them, so they are rewritten per pair)
+            for (int c = l; c <= DP; c += 64) {
+                Pl[DP * LDP + c] = 0.0;
+                Pl[c * LDP + DP] = 0.0;
+            }
             __syncthreads();
 
             // ---------------- R = rows K of Z, trailing T = [[B_LL, 0], [0, 0]]
-            constexpr int RPL = (8 * T * (8 * T + 2 * NE) + 63) / 64;   // R entries per lane (n <= 8 T)
+            constexpr int RPL = (8 * T * (8 * T + NE) + 63) / 64;   // B entries of R per lane (n <= 8 T)
             // the lane index through an opaque move: the entry indices and LDS
             // addresses below are then computed here, not hoisted out of the
             // shadow loop where they would stay live through the other stages
             int lr = l;
             asm volatile("" : "+v"(lr));
+            const int WB = n + NE;                    // B columns of R: K and L
+            const float rWB = 1.0f / (float)WB;
             double2 rv[RPL];
             double bmax = 0.0;
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
                 const int e = lr + 64 * q;
                 rv[q] = c_make(0.0, 0.0);
-                if (e < n * WR) {
-                    const int i = e / WR, j = e - i * WR;
-                    if (j < n + NE) {
-                        rv[q] = Bget(i, j);   // K and L columns are stored indices
-                        bmax = fmax(bmax, c_abs2(rv[q]));
-                    } else {
-                        rv[q].x = (i >= eta && i - eta == NE - 1 - (j - n - NE)) ? 1.0 : 0.0;
-                    }
+                if (e < n * WB) {
+                    // e / WB through a float reciprocal: e < 2^10, so the
+                    // quotient's fractional part stays clear of the rounding
+                    const int i = (int)(((float)e + 0.5f) * rWB), j = e - i * WB;
+                    rv[q] = Bget(i, j);               // K and L columns are stored indices
+                    bmax = fmax(bmax, c_abs2(rv[q]));
                 }
                 // finish this entry before the next one's loads (register pressure)
                 asm volatile("" : "+v"(rv[q].x), "+v"(rv[q].y) : : "memory");
@@ -263,30 +265,43 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
                 }
             }
             bmax = wave_max(bmax);
+            const double rbmax = rcp_nr(fmax(bmax, 1e-300));
             __syncthreads();   // P reads done
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
                 const int e = lr + 64 * q;
-                if (e < n * WR) Rl[e] = rv[q];
+                if (e < n * WB) {
+                    const int i = (int)(((float)e + 0.5f) * rWB), j = e - i * WB;
+                    Rl[i * WR + j] = rv[q];
+                }
+            }
+            // E columns: J's U1 x U2 block, J[eta + t][eta + 2ne - 1 - t] = +1
+            for (int e = lr; e < n * NE; e += 64) {
+                const int i = e / NE, v = e - i * NE;
+                Rl[i * WR + n + NE + v] = c_make((i >= eta && i - eta == NE - 1 - v) ? 1.0 : 0.0, 0.0);
             }
             __syncthreads();
 
             // ---------------- pairwise elimination of K
             double2 pfk = c_make(1.0, 0.0);
             bool zero = false;
-            double gmax = 0.0;   // largest |entry|^2 of the pivot rows in the L and E columns
             for (int k = 0; k < n; k += 2) {
+                // partner: the largest |R[k][p]|, p in (k, n), smallest p on near-ties.
+                // The key is |R[k][p]|^2 / max|B|^2 in single precision with its 6 low
+                // bits replaced by 63 - lane; non-negative floats order as unsigned
+                // integers, so one maximum gives both; non-candidates hold 0.
                 const int pc = k + 1 + l;
-                double pv = (pc < n) ? c_abs2(Rl[k * WR + pc]) : -1.0;
-                int pi = pc;
-#pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) {
-                    const double ov = __shfl_xor(pv, off, 64);
-                    const int op = __shfl_xor(pi, off, 64);
-                    if (ov > pv || (ov == pv && op < pi)) { pv = ov; pi = op; }
+                unsigned key = 0u;
+                if (pc < n) {
+                    const float f = (float)(c_abs2(Rl[k * WR + pc]) * rbmax);
+                    key = (__float_as_uint(f) & ~63u) | (unsigned)(63 - l);
                 }
-                if (!(pv > 0.0)) { zero = true; break; }
-                const int p = pi;
+                const unsigned kmax = wave_max_u32(key);
+                // below 64: every candidate is zero relative to max|B| (or underflows
+                // single precision there); otherwise the low bits name a candidate
+                // lane (a NaN candidate included), so p < n
+                if (kmax < 64u) { zero = true; break; }
+                const int p = k + 1 + (63 - (int)(kmax & 63u));
                 if (p != k + 1) {
                     if (l < WR) {
                         const double2 t0 = Rl[(k + 1) * WR + l], t1 = Rl[p * WR + l];
@@ -304,29 +319,36 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
                 }
                 const double2 a = Rl[k * WR + k + 1];
                 pfk = c_mul(pfk, a);
-                const double2 ia = c_inv(a);
+                const double2 ia = c_inv_nr(a);
                 const double2 *r0 = Rl + k * WR;
                 const double2 *r1 = Rl + (k + 1) * WR;
 #pragma unroll
                 for (int q = 0; q < NTQ; ++q) {
                     if (l + 64 * q < NT2) {
                         const int ca_ = n + ta[q], cb_ = n + tb[q];
-                        const double2 x0a = r0[ca_], x0b = r0[cb_], x1a = r1[ca_], x1b = r1[cb_];
-                        gmax = fmax(gmax, fmax(fmax(c_abs2(x0a), c_abs2(x0b)), fmax(c_abs2(x1a), c_abs2(x1b))));
-                        const double2 t = c_sub(c_mul(x1a, x0b), c_mul(x0a, x1b));
+                        const double2 t = c_sub(c_mul(r1[ca_], r0[cb_]), c_mul(r0[ca_], r1[cb_]));
                         tv[q] = c_fma(t, ia, tv[q]);
                     }
                 }
-                // rows i in [k+2, n), columns j in [k+2, WR); lane halves take alternate rows
+                // rows i in [k+2, n), columns j in [k+2, WR); lane halves take alternate
+                // rows: R[i][j] += R[k+1][i] tau_j - R[k][i] sigma_j with the scaled
+                // pivot rows tau = R[k] / a, sigma = R[k+1] / a
                 const int h = l >> 5;
                 for (int j = k + 2 + (l & 31); j < WR; j += 32) {
-                    const double2 rkj = r0[j], rk1j = r1[j];
+                    const double2 tau = c_mul(r0[j], ia), nsig = c_neg(c_mul(r1[j], ia));
                     for (int i = k + 2 + h; i < n; i += 2) {
-                        const double2 t = c_sub(c_mul(r1[i], rkj), c_mul(r0[i], rk1j));
-                        Rl[i * WR + j] = c_fma(t, ia, Rl[i * WR + j]);
+                        double2 *rij = Rl + i * WR + j;
+                        *rij = c_fma(r1[i], tau, c_fma(r0[i], nsig, *rij));
                     }
                 }
                 __syncthreads();
+            }
+            // growth of the unpivoted columns: at the end every row of R is the pivot
+            // row it was when it was used, so its L and E entries are all there is to watch
+            double gmax = 0.0;
+            for (int e = l; e < n * 2 * NE; e += 64) {
+                const int i = e / (2 * NE), c = e - i * (2 * NE);
+                gmax = fmax(gmax, c_abs2(Rl[i * WR + n + c]));
             }
             double tmax = 0.0;
 #pragma unroll
