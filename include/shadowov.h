@@ -83,6 +83,10 @@ typedef struct {
 #define SO_WSTAT_FALLBACK_LOST 8 /* a pair needed the full-size path but its queue
                                     was full: that pair's estimate may carry the
                                     rounding of an ill-conditioned elimination */
+#define SO_WSTAT_SINGULAR 16 /* shadow_overlap_grad: a node matrix B + c J of some
+                                pair was exactly singular, where the derivative by
+                                inverses is undefined: dlog and green for w are
+                                not reliable */
 
 /* Largest supported n (and the supported (n, eta) pairs are those with
  * m = 2n - eta in the compiled set; see so_supported). */
@@ -131,7 +135,10 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
  *   green     [n_walkers][n][n] complex128 out, or NULL: mixed Green's function
  *             G_pq = <Psi_T|a_p^dag a_q|phi>/<Psi_T|phi> = (D_w Phi_w^T)_pq
  *   other arguments as in shadow_overlap (workspace from with_grad = 1).
- * Walkers with S_w == 0 get SO_WSTAT_ZERO and NaN derivatives. */
+ * Walkers with S_w == 0 get SO_WSTAT_ZERO and NaN derivatives.
+ * Supported shapes: n - eta even with 2 <= n - eta <= 8 and n <= 16 (the
+ * paper's N = 16, eta = 8 included); others return SO_ERR_UNSUPPORTED.
+ * Deterministic (fixed reduction order). */
 so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_walkers,
                               const double *Q, const uint64_t *bits, int64_t n_shadows,
                               so_c64 *overlap, so_c64 *dlog, so_c64 *green, int32_t *status,
@@ -141,7 +148,8 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
  * so_profile_enable(1) makes every later shadow_overlap call bracket each
  * launch of its node-Pfaffian kernel (kind 0), of its formation kernel
  * (kind 1) and of its fused pair kernel (kind 2; formation, elimination and
- * node Pfaffians in one launch, used when n - eta is even and at most 8) with
+ * node Pfaffians in one launch, used when n - eta is even and at most 8), and
+ * every shadow_overlap_grad call its per-pair adjoint kernel (kind 3), with
  * HIP events recorded on the call's stream.  so_profile_read
  * waits for the recorded events of one kind, returns their summed duration
  * in milliseconds, the number of launches and the number of walker x shadow

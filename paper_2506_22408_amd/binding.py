@@ -21,7 +21,7 @@ SO_OK, SO_ERR_ARG, SO_ERR_UNSUPPORTED, SO_ERR_HIP, SO_ERR_WORKSPACE = 0, -1, -2,
 SO_NODES = {"unit": 0, "chebyshev": 1}
 SO_PREC = {"fp64": 0, "mixed": 1}
 SO_FLAG_PAPER_NORM = 1
-SO_WSTAT_RANK, SO_WSTAT_NONFINITE, SO_WSTAT_ZERO, SO_WSTAT_FALLBACK_LOST = 1, 2, 4, 8
+SO_WSTAT_RANK, SO_WSTAT_NONFINITE, SO_WSTAT_ZERO, SO_WSTAT_FALLBACK_LOST, SO_WSTAT_SINGULAR = 1, 2, 4, 8, 16
 
 
 class ShadowOvError(RuntimeError):
@@ -108,7 +108,7 @@ def node_weights(p: SoParams):
             np.array([complex(w[i].re, w[i].im) for i in range(k)]))
 
 
-PROF_PFAFF, PROF_FORM, PROF_PAIR = 0, 1, 2
+PROF_PFAFF, PROF_FORM, PROF_PAIR, PROF_GRAD = 0, 1, 2, 3
 
 
 def profile_enable(on: bool = True) -> None:

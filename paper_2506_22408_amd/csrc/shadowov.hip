@@ -22,6 +22,10 @@
 //     k_nodes       node Pfaffians Pf(s_k S + c_k J), weighted sum (so_nodes.h)
 //   k_fallback      full-size path for the rare pairs flagged above (so_fallback.h)
 //   k_reduce        S_w = (1/S) sum_s o_ws, fixed order (deterministic)
+// and for the derivative (shadow_overlap_grad), after the two prep kernels:
+//   k_grad_pair     per (walker, shadow range): Abar per pair and the partial
+//                   sums of F = C' X^T Abar and of o (so_grad.h)
+//   k_grad_walker   per walker: sums, gather, D_w, G_w, S_w (so_grad.h)
 #include "shadowov.h"
 
 #include <cstdlib>
@@ -33,6 +37,7 @@
 #include "so_nodes.h"
 #include "so_fallback.h"
 #include "so_pair.h"
+#include "so_grad.h"
 
 // --------------------------------------------------------------------------
 // k_reduce: S_w = (1/S) sum_s o_ws, fixed order: lane l sums s = l, l+64, ...
@@ -276,9 +281,10 @@ constexpr int kFormShadowsPerWave = 8;                 // shadows per formation 
 constexpr int kPairBatchesPerWave = 2;                 // node batches per fused wave
 
 struct Layout {
-    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_fbB, total;
+    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_fbB, off_F, off_O, total;
     int Sc;
     int64_t fb_cap;
+    int Gy;   // shadow ranges per walker of the derivative kernel
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -289,7 +295,17 @@ bool fused_ok(int n, int eta) {
     return ne >= 2 && ne <= 8 && (ne % 2) == 0;
 }
 
-Layout make_layout(int n, int eta, int64_t W, int64_t S) {
+// shadow ranges per walker for k_grad_pair: enough waves to fill the chip
+int grad_ranges(int64_t W, int64_t S) {
+    int64_t gy = (8192 + W - 1) / W;
+    if (gy > S) gy = S;
+    if (gy < 1) gy = 1;
+    return (int)gy;
+}
+
+bool grad_ok(int n, int eta) { return fused_ok(n, eta) && so_tiles(n) <= 2; }
+
+Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false) {
     Layout L{};
     const int m = mvalue(n, eta), DP = 16 * so_tiles(n), M2 = m - eta;
     const size_t per_shadow = (size_t)W * ((size_t)M2 * M2 + 1) * sizeof(double2);
@@ -312,6 +328,13 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S) {
     L.off_fbc = o; o = align_up(o + sizeof(uint32_t));
     L.off_fbl = o; o = align_up(o + (size_t)cap * sizeof(int64_t));
     L.off_fbB = o; o = align_up(o + (size_t)FB_GRID * m * m * sizeof(double2));
+    L.Gy = 0;
+    L.off_F = L.off_O = o;
+    if (with_grad) {
+        L.Gy = grad_ranges(W, S);
+        L.off_F = o; o = align_up(o + (size_t)W * L.Gy * 2 * n * m * sizeof(double2));
+        L.off_O = o; o = align_up(o + (size_t)W * L.Gy * sizeof(double2));
+    }
     L.total = o;
     return L;
 }
@@ -441,7 +464,7 @@ hipError_t launch_nodes(int M2, const double2 *Sb, const double2 *Pb, const Node
 }
 
 // ---- optional per-kernel timing (benchmarks): HIP events around launches
-enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_NKIND = 3 };
+enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_GRAD = 3, PROF_NKIND = 4 };
 struct ProfRec { hipEvent_t a, b; int kind; int64_t units; };
 struct ProfState {
     bool on = false;
@@ -492,8 +515,7 @@ so_status so_workspace_size(const so_params *p, int64_t n_walkers, int64_t n_sha
     int K;
     if (!bytes || !params_ok(p, &K) || n_walkers < 1 || n_shadows < 1) return SO_ERR_ARG;
     if (!so_supported(p->n, p->eta)) return SO_ERR_UNSUPPORTED;
-    (void)with_grad;
-    *bytes = make_layout(p->n, p->eta, n_walkers, n_shadows).total;
+    *bytes = make_layout(p->n, p->eta, n_walkers, n_shadows, with_grad != 0).total;
     return SO_OK;
 }
 
@@ -579,9 +601,64 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
                               const uint64_t *bits, int64_t n_shadows, so_c64 *overlap, so_c64 *dlog,
                               so_c64 *green, int32_t *status, void *workspace, size_t workspace_bytes,
                               void *stream) {
-    (void)p; (void)phi; (void)n_walkers; (void)Q; (void)bits; (void)n_shadows; (void)overlap;
-    (void)dlog; (void)green; (void)status; (void)workspace; (void)workspace_bytes; (void)stream;
-    return SO_ERR_UNSUPPORTED;
+    int K;
+    if (!params_ok(p, &K) || !phi || !Q || !bits || !overlap || !dlog || n_walkers < 1 || n_shadows < 1)
+        return SO_ERR_ARG;
+    if (!so_supported(p->n, p->eta) || !grad_ok(p->n, p->eta)) return SO_ERR_UNSUPPORTED;
+    if (p->precision != SO_PREC_FP64) return SO_ERR_UNSUPPORTED;
+    if (n_walkers > (int64_t)INT32_MAX || n_shadows > (int64_t)INT32_MAX) return SO_ERR_ARG;
+    const int n = p->n, eta = p->eta, d = 2 * n, NE = n - eta, T = so_tiles(n);
+    const int64_t W = n_walkers, S = n_shadows;
+    Layout L = make_layout(n, eta, W, S, true);
+    if (!workspace || workspace_bytes < L.total) return SO_ERR_WORKSPACE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char *ws = static_cast<char *>(workspace);
+    double *Xa = reinterpret_cast<double *>(ws + L.off_X);
+    double *Ca = reinterpret_cast<double *>(ws + L.off_C);
+    int32_t *wst = status ? status : reinterpret_cast<int32_t *>(ws + L.off_stat);
+    uint32_t *fbc = reinterpret_cast<uint32_t *>(ws + L.off_fbc);
+    double2 *Fp = reinterpret_cast<double2 *>(ws + L.off_F);
+    double2 *Op = reinterpret_cast<double2 *>(ws + L.off_O);
+    NodeTab tab;
+    build_nodetab(p, K, &tab);
+    RedTab rt;
+    std::memset(&rt, 0, sizeof(rt));
+    for (int j = 0; j < tab.Ke; ++j) { rt.e[j] = tab.e[j]; rt.v[j] = tab.v[j]; }
+
+    hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
+                       reinterpret_cast<const double2 *>(phi), Xa, wst, fbc);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q,
+                       bits, Ca);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    const int spw = (int)((S + L.Gy - 1) / L.Gy);
+    hipEvent_t ea = nullptr;
+    if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
+    const dim3 grid((unsigned)W, (unsigned)L.Gy);
+    const size_t lds = grad_lds(T, n, NE).total;
+    const double2 *Xc = reinterpret_cast<const double2 *>(Xa);
+    const double2 *Cc = reinterpret_cast<const double2 *>(Ca);
+#define SO_GRAD_LAUNCH(TT, NN)                                                                              \
+    hipLaunchKernelGGL((k_grad_pair<TT, NN>), grid, dim3(64), lds, st, n, eta, Xc, Cc, S, spw, rt, Fp, Op, wst)
+    switch (T * 16 + NE) {
+        case 16 + 2: SO_GRAD_LAUNCH(1, 2); break;
+        case 16 + 4: SO_GRAD_LAUNCH(1, 4); break;
+        case 16 + 6: SO_GRAD_LAUNCH(1, 6); break;
+        case 32 + 2: SO_GRAD_LAUNCH(2, 2); break;
+        case 32 + 4: SO_GRAD_LAUNCH(2, 4); break;
+        case 32 + 6: SO_GRAD_LAUNCH(2, 6); break;
+        case 32 + 8: SO_GRAD_LAUNCH(2, 8); break;
+        default: return SO_ERR_UNSUPPORTED;
+    }
+#undef SO_GRAD_LAUNCH
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    if (prof_end(st, ea, PROF_GRAD, W * S) != hipSuccess) return SO_ERR_HIP;
+    hipLaunchKernelGGL(k_grad_walker, dim3((unsigned)W), dim3(64), 0, st, n, eta,
+                       reinterpret_cast<const double2 *>(phi), Xa, Fp, Op, L.Gy, S,
+                       reinterpret_cast<double2 *>(overlap), reinterpret_cast<double2 *>(dlog),
+                       reinterpret_cast<double2 *>(green), wst);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    return SO_OK;
 }
 
 so_status so_profile_enable(int on) {

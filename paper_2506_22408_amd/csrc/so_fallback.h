@@ -15,6 +15,42 @@ __device__ __forceinline__ double2 fb_xrow(const double *Xw, int i, int col, int
     return c_make(Xw[ao_index(eta + i, col, T)], 0.0);
 }
 
+// Pfaffian of the m x m complex skew matrix in LDS (row stride lda; the
+// upper and lower triangles both present) by Householder tridiagonalisation,
+// lane q = row; destroys the matrix.  ubuf, ybuf: m complex of LDS scratch.
+// Returns the same value in every lane.  Starts and ends with a barrier.
+__device__ __forceinline__ double2 hh_pf_lds(double2 *A, int lda, int m, double2 *ubuf, double2 *ybuf, int q) {
+    __syncthreads();
+    double2 pf = c_make(1, 0);
+    for (int k = 0; k < m; k += 2) {
+        const double2 x = (q > k && q < m) ? A[q * lda + k] : c_make(0, 0);
+        const double nx2 = grp_sum<64>(c_abs2(x));
+        const double2 xf = grp_bcast<64>(x, k + 1);
+        const double nx = sqrt(nx2);
+        const double ax = sqrt(c_abs2(xf));
+        const double2 phs = ax > 0.0 ? c_scale(xf, 1.0 / ax) : c_make(1, 0);
+        const double2 alpha = c_scale(phs, -nx);
+        pf = c_mul(pf, alpha);
+        if (k + 2 >= m) break;
+        const double beta = nx > 0.0 ? 1.0 / (nx2 + nx * ax) : 0.0;
+        const double2 u = (q == k + 1) ? c_sub(xf, alpha) : x;
+        if (q >= k + 1 && q < m) ubuf[q] = c_conj(u);
+        __syncthreads();
+        double2 y = c_make(0, 0);
+        if (q >= k + 2 && q < m)
+            for (int j = k + 1; j < m; ++j) y = c_fma(A[q * lda + j], ubuf[j], y);
+        y = c_scale(y, beta);
+        if (q >= k + 2 && q < m) ybuf[q] = y;
+        __syncthreads();
+        if (q >= k + 2 && q < m)
+            for (int j = k + 2; j < m; ++j)
+                A[q * lda + j] = c_fma(u, ybuf[j], c_fma(c_neg(y), c_conj(ubuf[j]), A[q * lda + j]));
+        __syncthreads();
+    }
+    __syncthreads();
+    return pf;
+}
+
 // grid FB_GRID, 64 threads; Bscratch holds FB_GRID matrices of m x m.
 __global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double *__restrict__ Xa,
                                                  const double *__restrict__ Ca, NodeTab tab,
@@ -67,32 +103,7 @@ __global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double *_
                     A[q * LDA + j] = v;
                 }
             __syncthreads();
-            double2 pf = c_make(1, 0);
-            for (int k = 0; k < m; k += 2) {
-                const double2 x = (q > k && q < m) ? A[q * LDA + k] : c_make(0, 0);
-                const double nx2 = grp_sum<64>(c_abs2(x));
-                const double2 xf = grp_bcast<64>(x, k + 1);
-                const double nx = sqrt(nx2);
-                const double ax = sqrt(c_abs2(xf));
-                const double2 phs = ax > 0.0 ? c_scale(xf, 1.0 / ax) : c_make(1, 0);
-                const double2 alpha = c_scale(phs, -nx);
-                pf = c_mul(pf, alpha);
-                if (k + 2 >= m) break;
-                const double beta = nx > 0.0 ? 1.0 / (nx2 + nx * ax) : 0.0;
-                const double2 u = (q == k + 1) ? c_sub(xf, alpha) : x;
-                if (q >= k + 1 && q < m) ubuf[q] = c_conj(u);
-                __syncthreads();
-                double2 y = c_make(0, 0);
-                if (q >= k + 2 && q < m)
-                    for (int j = k + 1; j < m; ++j) y = c_fma(A[q * LDA + j], ubuf[j], y);
-                y = c_scale(y, beta);
-                if (q >= k + 2 && q < m) ybuf[q] = y;
-                __syncthreads();
-                if (q >= k + 2 && q < m)
-                    for (int j = k + 2; j < m; ++j)
-                        A[q * LDA + j] = c_fma(u, ybuf[j], c_fma(c_neg(y), c_conj(ubuf[j]), A[q * LDA + j]));
-                __syncthreads();
-            }
+            const double2 pf = hh_pf_lds(A, LDA, m, ubuf, ybuf, q);
             o = c_fma(tab.wf[node], pf, o);
         }
         if (q == 0) pairs[w * S_total + s] = o;

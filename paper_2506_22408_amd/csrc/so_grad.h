@@ -1,0 +1,556 @@
+// so_grad.h -- first derivative of the overlap with respect to the walker
+// ("Force bias and local energy": d Pf(A) = Pf(A)/2 Tr(A^{-1} dA)).
+//
+// Per pair, o = sum_j v_j Q(e_j) with Q(c) = Pf(B + c J) (node table,
+// so_common.h), so
+//   d o = 1/2 Tr(Abar dB) = Tr(Abar dX C' X^T),  Abar = sum_j v_j Q(e_j) (B + e_j J)^{-1}.
+// Q(c) (B + c J)^{-1} is a polynomial of degree <= ne in c as well (its
+// entries are Pfaffians of minors), so the same ne + 1 points are exact.
+// With K = O u U1, L = U2 and the pencil of so_pair.h, the block inverse of
+// B + c J gives, for Y(c) = B_KK^{-1} (B_KL + c J_KL) = Y0 + c Y1 and
+// N(c) = M(c)^{-1}:
+//   (B + cJ)^{-1} = [[B_KK^{-1} + Y N Y^T, -Y N], [-N Y^T, N]],
+// hence, with A_p = sum_j v_j Pf(M_j) e_j^p N_j (p = 0, 1, 2) and pfk = Pf(B_KK),
+//   Abar_LL = pfk A_0,
+//   Abar_KL = -pfk Z,        Z  = Y0 A_0 + Y1 A_1,
+//   Abar_LK =  pfk Z^T,
+//   Abar_KK = o B_KK^{-1} + pfk (Z Y0^T + Z' Y1^T),   Z' = Y0 A_1 + Y1 A_2.
+// Y0, Y1 and B_KK^{-1} come from one Gauss-Jordan pass over
+// [B_KK | B_KL | J_KL | I]; the N_j from Gauss-Jordan passes over [M_j | I].
+// A pair whose elimination is flagged (so_pair.h) takes the full-size route:
+// Pf and inverse of every B + e_j J.
+//
+// The pair then contributes F = C' X^T Abar (2n x m) to its walker's sum; the
+// per-walker gather (k_grad_walker) turns sum_s F into d(sum_s o)/d Phi
+// through X's dependence on Phi: the occupied rows are linear in Phi, the
+// empty ones depend on it through G^{-1}, G = [Phi | Phi_perp] (the general
+// walker matrix, which is holomorphic in Phi and equals X at the point).
+#pragma once
+#include "so_common.h"
+#include "so_fallback.h"
+#include "so_pair.h"
+
+// shapes of the derivative path: n <= 16 (two MFMA tiles), m = n + ne <= 24
+#define SO_GRAD_NMAX 16
+#define SO_GRAD_MMAX 24
+
+// ---- Gauss-Jordan with partial pivoting on the first nr columns of the
+// nr x nc system G (row-major, LDS), one column per lane (nc <= 64).  Leaves
+// [I | G^{-1} rhs].  Returns false on an exactly zero pivot column.  The
+// pivot key is the high word of |G[r][k]|^2 with its low 6 bits replaced by
+// 63 - lane (the high word of a non-negative double orders like the value).
+__device__ __forceinline__ bool gj_wave(double2 *G, int nr, int nc, int l) {
+    for (int k = 0; k < nr; ++k) {
+        const int r = k + l;
+        unsigned key = 0u;
+        if (r < nr) {
+            const unsigned hw = (unsigned)(__double_as_longlong(c_abs2(G[r * nc + k])) >> 32);
+            key = (hw & ~63u) | (unsigned)(63 - l);
+        }
+        const unsigned kmax = wave_max_u32(key);
+        if (kmax < 64u) return false;
+        const int p = k + (63 - (int)(kmax & 63u));
+        if (p != k) {
+            if (l < nc) {
+                const double2 t0 = G[k * nc + l], t1 = G[p * nc + l];
+                G[k * nc + l] = t1;
+                G[p * nc + l] = t0;
+            }
+            __syncthreads();
+        }
+        const double2 ip = c_inv_nr(G[k * nc + k]);
+        __syncthreads();
+        if (l < nc) G[k * nc + l] = c_mul(G[k * nc + l], ip);
+        __syncthreads();
+        if (l < nc) {
+            const double2 gk = G[k * nc + l];
+            for (int rr = 0; rr < nr; ++rr) {
+                if (rr == k) continue;
+                const double2 f = G[rr * nc + k];
+                G[rr * nc + l] = c_fma(c_neg(f), gk, G[rr * nc + l]);
+            }
+        }
+        __syncthreads();
+    }
+    return true;
+}
+
+// The same for four independent NE x 2NE systems, one per 16-lane row (system
+// g at G0 + g * stride).  A system whose pivot column is zero sets *sing.
+template <int NE>
+__device__ __forceinline__ void gj_rows16(double2 *G0, int stride, int l, bool *sing) {
+    constexpr int NC = 2 * NE;
+    const int g = l >> 4, c = l & 15;
+    double2 *G = G0 + g * stride;
+    for (int k = 0; k < NE; ++k) {
+        const int r = k + c;
+        unsigned key = 0u;
+        if (r < NE) {
+            const unsigned hw = (unsigned)(__double_as_longlong(c_abs2(G[r * NC + k])) >> 32);
+            key = (hw & ~63u) | (unsigned)(63 - c);
+        }
+        // row maximum (every lane of the 16-lane row gets it)
+        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0xB1, 0xf, 0xf, false));
+        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x4E, 0xf, 0xf, false));
+        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x141, 0xf, 0xf, false));
+        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x140, 0xf, 0xf, false));
+        if (key < 64u) *sing = true;
+        // a zero column still names a valid row (c = 0 has the largest index bits)
+        const int p = k + (63 - (int)(key & 63u));
+        if (p != k && c < NC) {
+            const double2 t0 = G[k * NC + c], t1 = G[p * NC + c];
+            G[k * NC + c] = t1;
+            G[p * NC + c] = t0;
+        }
+        __syncthreads();
+        const double2 ip = c_inv_nr(G[k * NC + k]);
+        __syncthreads();
+        if (c < NC) G[k * NC + c] = c_mul(G[k * NC + c], ip);
+        __syncthreads();
+        if (c < NC) {
+            const double2 gk = G[k * NC + c];
+            for (int rr = 0; rr < NE; ++rr) {
+                if (rr == k) continue;
+                const double2 f = G[rr * NC + k];
+                G[rr * NC + c] = c_fma(c_neg(f), gk, G[rr * NC + c]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// LDS regions of k_grad_pair (bytes), in order RP, RX, RB, RR, RG, RA, RS.
+struct GradLds {
+    size_t rp, rx, rb, rr, rg, ra, rs, total;
+};
+__host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
+    const int DP = 16 * T, LDP = DP + 1, m = n + NE, d = 2 * n;
+    GradLds g;
+    auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
+    g.rp = al((size_t)(DP + 1) * LDP * sizeof(double));
+    g.rx = g.rp;
+    g.rb = al((size_t)m * m * sizeof(double2));
+    size_t rr = (size_t)n * (n + 2 * NE);
+    if ((size_t)4 * NE * 2 * NE > rr) rr = (size_t)4 * NE * 2 * NE;
+    if ((size_t)NE * (2 * NE - 1) > rr) rr = (size_t)NE * (2 * NE - 1);
+    if ((size_t)2 * n * NE > rr) rr = (size_t)2 * n * NE;
+    g.rr = al(rr * sizeof(double2));
+    size_t rg = (size_t)n * (2 * n + 2 * NE);
+    if ((size_t)d * m > rg) rg = (size_t)d * m;
+    // the full-size route's [B + cJ | I] (m x 2m) spans RR and RG
+    if ((size_t)2 * m * m * sizeof(double2) > g.rr + rg * sizeof(double2))
+        rg = ((size_t)2 * m * m * sizeof(double2) - g.rr + sizeof(double2) - 1) / sizeof(double2);
+    g.rg = al(rg * sizeof(double2));
+    g.ra = g.rb;
+    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + 3 * NE * NE + (NE + 1) + 2 * m + 4) * sizeof(double2));
+    g.total = g.rp + g.rx + g.rb + g.rr + g.rg + g.ra + g.rs;
+    return g;
+}
+
+// grid (W, Gy), one wave per block: walker blockIdx.x, shadows
+// [blockIdx.y spw, ...).  Writes its partial sums of F (2n x m, row-major)
+// and of o to Fpart[(w Gy + gy) 2nm ...] and Opart[w Gy + gy].
+template <int T, int NE>
+__global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 *__restrict__ Xa,
+                                                  const double2 *__restrict__ Ca, int64_t S_total, int spw,
+                                                  RedTab tab, double2 *__restrict__ Fpart,
+                                                  double2 *__restrict__ Opart, int32_t *__restrict__ wstat) {
+    constexpr int DP = 16 * T, LDP = DP + 1, MAT2 = DP * DP / 2;
+    constexpr int KE = NE + 1;
+    constexpr int NT = NE * (NE - 1) / 2;
+    constexpr int NT2 = NE * (2 * NE - 1);
+    constexpr int NTQ = (NT2 + 63) / 64;
+    constexpr int FQ = (16 * T * (8 * T + NE) + 63) / 64;   // F entries per lane (2n x m, n <= 8T)
+    const int m = n + NE, d = 2 * n, WR = n + 2 * NE, GW = 2 * n + 2 * NE;
+    const int l = threadIdx.x, w = blockIdx.x;
+    extern __shared__ double lds[];
+    const GradLds L = grad_lds(T, n, NE);
+    char *base = reinterpret_cast<char *>(lds);
+    double *RP = reinterpret_cast<double *>(base);
+    double *RX = reinterpret_cast<double *>(base + L.rp);
+    double2 *RB = reinterpret_cast<double2 *>(base + L.rp + L.rx);
+    double2 *RR = reinterpret_cast<double2 *>(base + L.rp + L.rx + L.rb);
+    double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.rx + L.rb + L.rr);
+    double2 *RA = reinterpret_cast<double2 *>(base + L.rp + L.rx + L.rb + L.rr + L.rg);
+    double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.rx + L.rb + L.rr + L.rg + L.ra);
+    double2 *Mup = RS;                       // M0, M1, M2 upper triangles
+    double2 *Ahat = RS + 3 * NT;             // A_0, A_1, A_2 (NE x NE each)
+    double2 *pfm = Ahat + 3 * NE * NE;       // Pf(M_j)
+    double2 *ubuf = pfm + KE;                // Householder scratch (m each)
+    double2 *ybuf = ubuf + m;
+
+    // trailing entries (a < b) of the 2NE x 2NE block handled by this lane
+    int ta[NTQ], tb[NTQ];
+#pragma unroll
+    for (int q = 0; q < NTQ; ++q) {
+        int e = l + 64 * q, a = 0;
+        if (e >= NT2) e = 0;
+        while (e >= 2 * NE - 1 - a) { e -= 2 * NE - 1 - a; ++a; }
+        ta[q] = a;
+        tb[q] = a + 1 + e;
+    }
+    // the walker's Xall, row-major, with a zero row DP
+    const double2 *Xw = Xa + (size_t)w * MAT2;
+    {
+        const double *Xd = reinterpret_cast<const double *>(Xw);
+        for (int f = l; f < DP * DP; f += 64) {
+            int row, col;
+            ao_rowcol(f, T, row, col);
+            RX[row * LDP + col] = Xd[f];
+        }
+        for (int c = l; c <= DP; c += 64) RX[DP * LDP + c] = 0.0;
+    }
+    auto rre = [&](int i) -> int { return i < eta ? i : eta + i; };
+    auto rim = [&](int i) -> int { return i < eta ? eta + i : DP; };
+    // J of the stored order: +1 at (eta+t, eta+2ne-1-t), -1 at the transpose
+    auto Jel = [&](int i, int j) -> double {
+        if (i < eta || j < eta) return 0.0;
+        const int u = i - eta, v = j - eta;
+        return (u + v == 2 * NE - 1) ? (u < NE ? 1.0 : -1.0) : 0.0;
+    };
+
+    double2 facc[FQ];
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) facc[q] = c_make(0.0, 0.0);
+    double2 oacc = c_make(0.0, 0.0);
+    int32_t wflags = 0;
+
+    const int64_t s0 = (int64_t)blockIdx.y * spw;
+    const int64_t s1 = min(S_total, s0 + spw);
+    for (int64_t s = s0; s < s1; ++s) {
+        const double2 *Cs = Ca + (size_t)s * MAT2;
+        pair_formation<T>(Xw, Cs, RP, l);
+
+        // ---------------- B (m x m), then R = rows K of Z, G = [B_KK | B_KL | J_KL | I]
+        double bmax = 0.0;
+        for (int e = l; e < m * m; e += 64) {
+            const int i = e / m, j = e - i * m;
+            const int ir = rre(i) * LDP, ii = rim(i) * LDP, jr = rre(j), ji = rim(j);
+            const double2 v = c_make(RP[ir + jr] - RP[ii + ji], RP[ir + ji] + RP[ii + jr]);
+            RB[e] = v;
+            bmax = fmax(bmax, c_abs2(v));
+        }
+        bmax = wave_max(bmax);
+        const double rbmax = rcp_nr(fmax(bmax, 1e-300));
+        __syncthreads();
+        for (int e = l; e < n * WR; e += 64) {
+            const int i = e / WR, j = e - i * WR;
+            RR[e] = (j < m) ? RB[i * m + j] : c_make(Jel(i, n + (j - m)), 0.0);
+        }
+        for (int e = l; e < n * GW; e += 64) {
+            const int i = e / GW, c = e - i * GW;
+            double2 v;
+            if (c < m) v = RB[i * m + c];
+            else if (c < m + NE) v = c_make(Jel(i, n + (c - m)), 0.0);
+            else v = c_make((c - m - NE == i) ? 1.0 : 0.0, 0.0);
+            RG[e] = v;
+        }
+        double2 tv[NTQ];
+#pragma unroll
+        for (int q = 0; q < NTQ; ++q) {
+            tv[q] = c_make(0.0, 0.0);
+            if (l + 64 * q < NT2 && tb[q] < NE) tv[q] = RB[(n + ta[q]) * m + n + tb[q]];
+        }
+        __syncthreads();
+
+        // ---------------- elimination of K, pencil, node Pfaffians
+        double2 pfk;
+        bool flag = elim_bordered<NE, NTQ>(n, WR, RR, ta, tb, tv, bmax, rbmax, l, pfk);
+        double2 o = c_make(0.0, 0.0);
+        if (!flag) {
+#pragma unroll
+            for (int q = 0; q < NTQ; ++q)
+                if (l + 64 * q < NT2) RR[l + 64 * q] = tv[q];
+            __syncthreads();
+            auto tix = [&](int a, int bb) -> int { return a * (2 * NE - 1) - a * (a - 1) / 2 + (bb - a - 1); };
+            for (int e = l; e < NT; e += 64) {
+                int x = 0, r = e;
+                while (r >= NE - 1 - x) { r -= NE - 1 - x; ++x; }
+                const int y = x + 1 + r;
+                Mup[e] = RR[tix(x, y)];
+                Mup[NT + e] = c_sub(RR[tix(x, NE + y)], RR[tix(y, NE + x)]);
+                Mup[2 * NT + e] = RR[tix(NE + x, NE + y)];
+            }
+            __syncthreads();
+            if (l < KE) {
+                const double2 cj = tab.e[l], cj2 = c_mul(cj, cj);
+                double2 A[NE][NE];
+                int e = 0;
+#pragma unroll
+                for (int x = 0; x < NE; ++x)
+#pragma unroll
+                    for (int y = x + 1; y < NE; ++y) {
+                        A[x][y] = c_fma(cj2, Mup[2 * NT + e], c_fma(cj, Mup[NT + e], Mup[e]));
+                        ++e;
+                    }
+                pfm[l] = pf_lane_from<NE, 0>(A);
+            }
+            __syncthreads();
+            for (int j = 0; j < KE; ++j) o = c_fma(tab.v[j], pfm[j], o);
+            o = c_mul(o, pfk);
+            // ---------------- Y0, Y1, B_KK^{-1}
+            if (!gj_wave(RG, n, GW, l)) flag = true;
+        }
+        if (!flag) {
+            // ---------------- A_p from the node inverses, four nodes at a time
+            double2 ah0 = c_make(0, 0), ah1 = c_make(0, 0), ah2 = c_make(0, 0);
+            bool sing = false;
+            for (int g0 = 0; g0 < KE; g0 += 4) {
+                for (int e = l; e < 4 * NE * 2 * NE; e += 64) {
+                    const int g = e / (NE * 2 * NE), rc = e - g * (NE * 2 * NE);
+                    const int x = rc / (2 * NE), c = rc - x * (2 * NE);
+                    const int j = min(g0 + g, KE - 1);
+                    double2 v;
+                    if (c < NE) {
+                        if (x == c) {
+                            v = c_make(0.0, 0.0);
+                        } else {
+                            const int a = min(x, c), b = max(x, c);
+                            const int ei = a * (2 * NE - 1 - a) / 2 + (b - a - 1);
+                            const double2 cj = tab.e[j];
+                            v = c_fma(c_mul(cj, cj), Mup[2 * NT + ei], c_fma(cj, Mup[NT + ei], Mup[ei]));
+                            if (x > c) v = c_neg(v);
+                        }
+                    } else {
+                        v = c_make((c - NE == x) ? 1.0 : 0.0, 0.0);
+                    }
+                    RR[e] = v;
+                }
+                __syncthreads();
+                gj_rows16<NE>(RR, NE * 2 * NE, l, &sing);
+                if (l < NE * NE) {
+                    const int x = l / NE, y = l - x * NE;
+                    for (int g = 0; g < 4 && g0 + g < KE; ++g) {
+                        const int j = g0 + g;
+                        const double2 nv = RR[g * NE * 2 * NE + x * 2 * NE + NE + y];
+                        const double2 c0 = c_mul(tab.v[j], pfm[j]);
+                        const double2 c1 = c_mul(c0, tab.e[j]);
+                        const double2 c2 = c_mul(c1, tab.e[j]);
+                        ah0 = c_fma(c0, nv, ah0);
+                        ah1 = c_fma(c1, nv, ah1);
+                        ah2 = c_fma(c2, nv, ah2);
+                    }
+                }
+                __syncthreads();
+            }
+            if (__any(sing)) wflags |= SO_WSTAT_SINGULAR;
+            if (l < NE * NE) {
+                Ahat[l] = ah0;
+                Ahat[NE * NE + l] = ah1;
+                Ahat[2 * NE * NE + l] = ah2;
+            }
+            __syncthreads();
+            // ---------------- Z, Z' (n x NE) into RR
+            // Y0 = RG[:, n:m], Y1 = RG[:, m:m+NE], B_KK^{-1} = RG[:, m+NE:m+NE+n]
+            for (int e = l; e < n * NE; e += 64) {
+                const int i = e / NE, x = e - i * NE;
+                double2 z = c_make(0, 0), zp = c_make(0, 0);
+                for (int y = 0; y < NE; ++y) {
+                    const double2 y0 = RG[i * GW + n + y], y1 = RG[i * GW + m + y];
+                    z = c_fma(y0, Ahat[y * NE + x], c_fma(y1, Ahat[NE * NE + y * NE + x], z));
+                    zp = c_fma(y0, Ahat[NE * NE + y * NE + x], c_fma(y1, Ahat[2 * NE * NE + y * NE + x], zp));
+                }
+                RR[e] = z;
+                RR[n * NE + e] = zp;
+            }
+            __syncthreads();
+            // ---------------- Abar (m x m) into RA
+            for (int e = l; e < m * m; e += 64) {
+                const int i = e / m, j = e - i * m;
+                double2 v;
+                if (i < n && j < n) {
+                    double2 acc = c_make(0, 0);
+                    for (int x = 0; x < NE; ++x)
+                        acc = c_fma(RR[i * NE + x], RG[j * GW + n + x],
+                                    c_fma(RR[n * NE + i * NE + x], RG[j * GW + m + x], acc));
+                    v = c_fma(o, RG[i * GW + m + NE + j], c_mul(pfk, acc));
+                } else if (i < n) {
+                    v = c_neg(c_mul(pfk, RR[i * NE + (j - n)]));
+                } else if (j < n) {
+                    v = c_mul(pfk, RR[j * NE + (i - n)]);
+                } else {
+                    v = c_mul(pfk, Ahat[(i - n) * NE + (j - n)]);
+                }
+                RA[e] = v;
+            }
+            __syncthreads();
+        } else {
+            // ---------------- full-size route: Pf and inverse of every B + e_j J
+            o = c_make(0.0, 0.0);
+            for (int e = l; e < m * m; e += 64) RA[e] = c_make(0.0, 0.0);
+            double2 *Aug = RR;   // m x 2m over RR and RG
+            const int AW = 2 * m;
+            for (int j = 0; j < KE; ++j) {
+                const double2 cj = tab.e[j];
+                __syncthreads();
+                for (int e = l; e < m * m; e += 64) {
+                    const int i = e / m, c = e - i * m;
+                    Aug[i * AW + c] = c_add(RB[e], c_scale(cj, Jel(i, c)));
+                }
+                const double2 qj = hh_pf_lds(Aug, AW, m, ubuf, ybuf, l);
+                for (int e = l; e < m * AW; e += 64) {
+                    const int i = e / AW, c = e - i * AW;
+                    Aug[e] = (c < m) ? c_add(RB[i * m + c], c_scale(cj, Jel(i, c)))
+                                     : c_make((c - m == i) ? 1.0 : 0.0, 0.0);
+                }
+                __syncthreads();
+                if (!gj_wave(Aug, m, AW, l)) wflags |= SO_WSTAT_SINGULAR;
+                const double2 f = c_mul(tab.v[j], qj);
+                o = c_fma(tab.v[j], qj, o);
+                for (int e = l; e < m * m; e += 64) {
+                    const int i = e / m, c = e - i * m;
+                    RA[e] = c_fma(f, Aug[i * AW + m + c], RA[e]);
+                }
+            }
+            __syncthreads();
+        }
+        oacc = c_add(oacc, o);
+
+        // ---------------- F += C' X^T Abar: H = X^T Abar into RG, C' into RP
+        for (int e = l; e < d * m; e += 64) {
+            const int mu = e / m, r = e - mu * m;
+            double2 h = c_make(0, 0);
+            for (int i = 0; i < m; ++i) {
+                const double xr = RX[rre(i) * LDP + mu], xi = RX[rim(i) * LDP + mu];
+                const double2 a = RA[i * m + r];
+                h = c_fma(c_make(xr, xi), a, h);
+            }
+            RG[e] = h;
+        }
+        {
+            const double *Cd = reinterpret_cast<const double *>(Cs);
+            for (int f = l; f < DP * DP; f += 64) {
+                int row, col;
+                ao_rowcol(f, T, row, col);
+                RP[row * LDP + col] = Cd[f];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < FQ; ++q) {
+            const int e = l + 64 * q;
+            if (e < d * m) {
+                const int mu = e / m, r = e - mu * m;
+                double2 acc = facc[q];
+                for (int nu = 0; nu < d; ++nu) acc = c_fma(c_make(RP[mu * LDP + nu], 0.0), RG[nu * m + r], acc);
+                facc[q] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t part = (int64_t)w * gridDim.y + blockIdx.y;
+#pragma unroll
+    for (int q = 0; q < FQ; ++q) {
+        const int e = l + 64 * q;
+        if (e < d * m) Fpart[part * (int64_t)(d * m) + e] = facc[q];
+    }
+    if (l == 0) {
+        Opart[part] = oacc;
+        if (wflags) atomicOr(&wstat[w], wflags);
+    }
+}
+
+// One workgroup of 64 per walker: F = sum over the walker's partials (fixed
+// order), o = sum_s o_ws, then the gather
+//   d o / d Phi_pj = (F[2p][j] - i F[2p+1][j]) / sqrt2
+//                  - sum_t conj(g_t[p]) sum_q Phi+_jq h_t[q],
+//   h_t[q] = (F[2q][r0] + i F[2q+1][r0] - i F[2q][r1] + F[2q+1][r1]) / 2,
+// with r0 = eta + t, r1 = eta + 2ne - 1 - t the stored rows of empty orbital t,
+// g_t its complement vector ((G^{-1})_{eta+t, p} = conj(g_t[p])) and
+// Phi+ = (Phi^H Phi)^{-1} Phi^H the first eta rows of G^{-1}.  Then
+// D = (d sum_s o / d Phi) / sum_s o, G = D Phi^T, S_w = sum_s o / S.
+__global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double2 *__restrict__ phi,
+                                                    const double *__restrict__ Xa, const double2 *__restrict__ Fpart,
+                                                    const double2 *__restrict__ Opart, int Gy, int64_t S_total,
+                                                    double2 *__restrict__ overlap, double2 *__restrict__ dlog,
+                                                    double2 *__restrict__ green, int32_t *__restrict__ wstat) {
+    __shared__ double2 Fs[2 * SO_GRAD_NMAX * SO_GRAD_MMAX];
+    __shared__ double2 Ph[SO_GRAD_NMAX * SO_GRAD_NMAX];        // Phi (n x eta)
+    __shared__ double2 Gm[SO_GRAD_NMAX * 2 * SO_GRAD_NMAX];    // [Phi^H Phi | I] (eta x 2 eta)
+    __shared__ double2 Pp[SO_GRAD_NMAX * SO_GRAD_NMAX];        // Phi+ (eta x n)
+    __shared__ double2 Hh[SO_GRAD_NMAX * SO_GRAD_NMAX];        // h_t[q] (ne x n)
+    __shared__ double2 Vv[SO_GRAD_NMAX * SO_GRAD_NMAX];        // V[j][t] (eta x ne)
+    __shared__ double2 Dd[SO_GRAD_NMAX * SO_GRAD_NMAX];        // D (n x eta)
+    const int l = threadIdx.x, w = blockIdx.x;
+    const int ne = n - eta, m = 2 * n - eta, d = 2 * n, T = so_tiles(n), DP = 16 * T;
+    const int dm = d * m;
+    for (int e = l; e < dm; e += 64) {
+        double2 acc = c_make(0, 0);
+        for (int g = 0; g < Gy; ++g) acc = c_add(acc, Fpart[((int64_t)w * Gy + g) * dm + e]);
+        Fs[e] = acc;
+    }
+    double2 osum = c_make(0, 0);
+    for (int g = 0; g < Gy; ++g) osum = c_add(osum, Opart[(int64_t)w * Gy + g]);
+    const double2 *pw = phi + (size_t)w * n * eta;
+    for (int e = l; e < n * eta; e += 64) Ph[e] = pw[e];
+    __syncthreads();
+    // [Phi^H Phi | I] -> [I | (Phi^H Phi)^{-1}]
+    const int gw = 2 * eta;
+    for (int e = l; e < eta * gw; e += 64) {
+        const int a = e / gw, c = e - a * gw;
+        double2 v = c_make(0, 0);
+        if (c < eta)
+            for (int p = 0; p < n; ++p) v = c_fma(c_conj(Ph[p * eta + a]), Ph[p * eta + c], v);
+        else
+            v = c_make((c - eta == a) ? 1.0 : 0.0, 0.0);
+        Gm[e] = v;
+    }
+    __syncthreads();
+    const bool ok = gj_wave(Gm, eta, gw, l);
+    for (int e = l; e < eta * n; e += 64) {
+        const int j = e / n, q = e - j * n;
+        double2 v = c_make(0, 0);
+        for (int a = 0; a < eta; ++a) v = c_fma(Gm[j * gw + eta + a], c_conj(Ph[q * eta + a]), v);
+        Pp[e] = v;
+    }
+    for (int e = l; e < ne * n; e += 64) {
+        const int t = e / n, q = e - t * n;
+        const int r0 = eta + t, r1 = eta + 2 * ne - 1 - t;
+        const double2 a = Fs[(2 * q) * m + r0], b = Fs[(2 * q + 1) * m + r0];
+        const double2 c = Fs[(2 * q) * m + r1], dd = Fs[(2 * q + 1) * m + r1];
+        // (a + i b - i c + dd) / 2
+        Hh[e] = c_scale(c_make(a.x - b.y + c.y + dd.x, a.y + b.x - c.x + dd.y), 0.5);
+    }
+    __syncthreads();
+    for (int e = l; e < eta * ne; e += 64) {
+        const int j = e / ne, t = e - j * ne;
+        double2 v = c_make(0, 0);
+        for (int q = 0; q < n; ++q) v = c_fma(Pp[j * n + q], Hh[t * n + q], v);
+        Vv[e] = v;
+    }
+    __syncthreads();
+    const double *Xw = Xa + (size_t)w * DP * DP;
+    const double rs2 = 0.70710678118654752440;
+    const bool zero = (osum.x == 0.0 && osum.y == 0.0);
+    const double2 rinv = zero ? c_make(0, 0) : c_inv(osum);
+    for (int e = l; e < n * eta; e += 64) {
+        const int p = e / eta, j = e - p * eta;
+        const double2 f0 = Fs[(2 * p) * m + j], f1 = Fs[(2 * p + 1) * m + j];
+        double2 gv = c_scale(c_make(f0.x + f1.y, f0.y - f1.x), rs2);   // (f0 - i f1) / sqrt2
+        for (int t = 0; t < ne; ++t) {
+            const double2 gt = c_make(Xw[ao_index(2 * eta + t, 2 * p, T)], Xw[ao_index(2 * eta + t, 2 * p + 1, T)]);
+            gv = c_sub(gv, c_mul(c_conj(gt), Vv[j * ne + t]));
+        }
+        const double2 dv = zero ? c_make(NAN, NAN) : c_mul(gv, rinv);
+        Dd[e] = dv;
+        dlog[(size_t)w * n * eta + e] = dv;
+    }
+    __syncthreads();
+    if (green)
+        for (int e = l; e < n * n; e += 64) {
+            const int p = e / n, q = e - p * n;
+            double2 v = c_make(0, 0);
+            for (int j = 0; j < eta; ++j) v = c_fma(Dd[p * eta + j], Ph[q * eta + j], v);
+            green[(size_t)w * n * n + e] = v;
+        }
+    if (l == 0) {
+        int32_t st = wstat[w];
+        double2 r = c_scale(osum, 1.0 / (double)S_total);
+        if (st & SO_WSTAT_RANK) r = c_make(NAN, NAN);
+        if (zero) st |= SO_WSTAT_ZERO;
+        if (!ok) st |= SO_WSTAT_RANK;
+        if (!isfinite(r.x) || !isfinite(r.y)) st |= SO_WSTAT_NONFINITE;
+        overlap[w] = r;
+        wstat[w] = st;
+    }
+}

@@ -91,6 +91,157 @@ __device__ __forceinline__ double2 pf_lane_from(double2 (&A)[N][N]) {
     return pf;
 }
 
+// ---- formation: P = Xall C'_s Xall^T into LDS -------------------------------
+// Pl is (DP + 1) x LDP doubles, row-major; both triangles of P are written and
+// row and column DP are zeroed (an empty orbital's missing imaginary part
+// points there).  Ends with a barrier.
+template <int T>
+__device__ __forceinline__ void pair_formation(const double2 *__restrict__ Xw, const double2 *__restrict__ Cs,
+                                               double *Pl, int l) {
+    constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
+    // operands: the walker's Xall (re-read from L2 per pair: keeping it
+    // live through the elimination and node stages costs occupancy) and C'_s
+    double xa[T][KK], ca[T][KK];
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int h = 0; h < KH; ++h) {
+            const double2 v = Xw[(I * KH + h) * 64 + l];
+            const double2 c = Cs[(I * KH + h) * 64 + l];
+            xa[I][2 * h] = v.x;
+            xa[I][2 * h + 1] = v.y;
+            ca[I][2 * h] = c.x;
+            ca[I][2 * h + 1] = c.y;
+        }
+    so_d4 U[T][T];
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J) U[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = 0; J < T; ++J)
+                U[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[I][kk], xa[J][kk], U[I][J], 0, 0, 0);
+    so_d4 P[T][T];
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J) P[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = I; J < T; ++J)
+                P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0,
+                                                               0, 0);
+    __syncthreads();   // region A is free
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = I; J < T; ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int a = 16 * I + 4 * r + (l >> 4), bcol = 16 * J + (l & 15);
+                Pl[a * LDP + bcol] = P[I][J][r];
+                if (J > I) Pl[bcol * LDP + a] = -P[I][J][r];   // P is antisymmetric
+            }
+    // row and column DP are zero (R overlays them, so they are rewritten per pair)
+    for (int c = l; c <= DP; c += 64) {
+        Pl[DP * LDP + c] = 0.0;
+        Pl[c * LDP + DP] = 0.0;
+    }
+    __syncthreads();
+
+}
+
+// ---- pairwise elimination of K in the bordered rows ---------------------------
+// Rl: the rows K of Z (n x WR complex, LDS); tv: this lane's trailing entries
+// (ta < tb) of the 2NE x 2NE block, updated in place; rbmax = 1 / max|B|^2.
+// Returns true when the pair needs the full-size path (zero pivot or growth);
+// pfk = Pf(B_KK).  Ends with a barrier.
+template <int NE, int NTQ>
+__device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const int (&ta)[NTQ], const int (&tb)[NTQ],
+                                              double2 (&tv)[NTQ], double bmax, double rbmax, int l, double2 &pfk) {
+    constexpr int NT2 = NE * (2 * NE - 1);
+    pfk = c_make(1.0, 0.0);
+    bool zero = false;
+    for (int k = 0; k < n; k += 2) {
+        // partner: the largest |R[k][p]|, p in (k, n), smallest p on near-ties.
+        // The key is |R[k][p]|^2 / max|B|^2 in single precision with its 6 low
+        // bits replaced by 63 - lane; non-negative floats order as unsigned
+        // integers, so one maximum gives both; non-candidates hold 0.
+        const int pc = k + 1 + l;
+        unsigned key = 0u;
+        if (pc < n) {
+            const float f = (float)(c_abs2(Rl[k * WR + pc]) * rbmax);
+            key = (__float_as_uint(f) & ~63u) | (unsigned)(63 - l);
+        }
+        const unsigned kmax = wave_max_u32(key);
+        // below 64: every candidate is zero relative to max|B| (or underflows
+        // single precision there); otherwise the low bits name a candidate
+        // lane (a NaN candidate included), so p < n
+        if (kmax < 64u) { zero = true; break; }
+        const int p = k + 1 + (63 - (int)(kmax & 63u));
+        if (p != k + 1) {
+            if (l < WR) {
+                const double2 t0 = Rl[(k + 1) * WR + l], t1 = Rl[p * WR + l];
+                Rl[(k + 1) * WR + l] = t1;
+                Rl[p * WR + l] = t0;
+            }
+            __syncthreads();
+            if (l < n) {
+                const double2 t0 = Rl[l * WR + k + 1], t1 = Rl[l * WR + p];
+                Rl[l * WR + k + 1] = t1;
+                Rl[l * WR + p] = t0;
+            }
+            __syncthreads();
+            pfk = c_neg(pfk);
+        }
+        const double2 a = Rl[k * WR + k + 1];
+        pfk = c_mul(pfk, a);
+        const double2 ia = c_inv_nr(a);
+        const double2 *r0 = Rl + k * WR;
+        const double2 *r1 = Rl + (k + 1) * WR;
+#pragma unroll
+        for (int q = 0; q < NTQ; ++q) {
+            if (l + 64 * q < NT2) {
+                const int ca_ = n + ta[q], cb_ = n + tb[q];
+                const double2 t = c_sub(c_mul(r1[ca_], r0[cb_]), c_mul(r0[ca_], r1[cb_]));
+                tv[q] = c_fma(t, ia, tv[q]);
+            }
+        }
+        // rows i in [k+2, n), columns j in [k+2, WR); lane halves take alternate
+        // rows: R[i][j] += R[k+1][i] tau_j - R[k][i] sigma_j with the scaled
+        // pivot rows tau = R[k] / a, sigma = R[k+1] / a
+        const int h = l >> 5;
+        for (int j = k + 2 + (l & 31); j < WR; j += 32) {
+            const double2 tau = c_mul(r0[j], ia), nsig = c_neg(c_mul(r1[j], ia));
+            for (int i = k + 2 + h; i < n; i += 2) {
+                double2 *rij = Rl + i * WR + j;
+                *rij = c_fma(r1[i], tau, c_fma(r0[i], nsig, *rij));
+            }
+        }
+        __syncthreads();
+    }
+    // growth of the unpivoted columns: at the end every row of R is the pivot
+    // row it was when it was used, so its L and E entries are all there is to watch
+    double gmax = 0.0;
+    for (int e = l; e < n * 2 * NE; e += 64) {
+        const int i = e / (2 * NE), c = e - i * (2 * NE);
+        gmax = fmax(gmax, c_abs2(Rl[i * WR + n + c]));
+    }
+    double tmax = 0.0;
+#pragma unroll
+    for (int q = 0; q < NTQ; ++q) tmax = fmax(tmax, c_abs2(tv[q]));
+    tmax = wave_max(fmax(tmax, gmax));
+    const bool flag = zero || !(tmax <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * fmax(bmax, 1.0));
+    return flag;
+}
+
 // LDS per wave: region A = max(P ((DP+1) x (DP+1) f64), R (n x (n + 2 NE) c128),
 // T (NE (2NE - 1) c128), node values), then the batch: NB slots of
 // 3 NE (NE-1)/2 + 1 complex (M0, M1, M2 upper triangles, Pf(B_KK)).
@@ -172,63 +323,7 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
         for (int b = 0; b < nb; ++b) {
             const int64_t s = bs + b;
             // ---------------- formation: P = Xall C' Xall^T
-            // operands: the walker's Xall (re-read from L2 per pair: keeping it
-            // live through the elimination and node stages costs occupancy) and C'_s
-            const double2 *Cs = Ca + (size_t)s * MAT2;
-            double xa[T][KK], ca[T][KK];
-#pragma unroll
-            for (int I = 0; I < T; ++I)
-#pragma unroll
-                for (int h = 0; h < KH; ++h) {
-                    const double2 v = Xw[(I * KH + h) * 64 + l];
-                    const double2 c = Cs[(I * KH + h) * 64 + l];
-                    xa[I][2 * h] = v.x;
-                    xa[I][2 * h + 1] = v.y;
-                    ca[I][2 * h] = c.x;
-                    ca[I][2 * h + 1] = c.y;
-                }
-            so_d4 U[T][T];
-#pragma unroll
-            for (int I = 0; I < T; ++I)
-#pragma unroll
-                for (int J = 0; J < T; ++J) U[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-                for (int I = 0; I < T; ++I)
-#pragma unroll
-                    for (int J = 0; J < T; ++J)
-                        U[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[I][kk], xa[J][kk], U[I][J], 0, 0, 0);
-            so_d4 P[T][T];
-#pragma unroll
-            for (int I = 0; I < T; ++I)
-#pragma unroll
-                for (int J = 0; J < T; ++J) P[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-                for (int I = 0; I < T; ++I)
-#pragma unroll
-                    for (int J = I; J < T; ++J)
-                        P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0,
-                                                                       0, 0);
-            __syncthreads();   // region A is free
-#pragma unroll
-            for (int I = 0; I < T; ++I)
-#pragma unroll
-                for (int J = I; J < T; ++J)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int a = 16 * I + 4 * r + (l >> 4), bcol = 16 * J + (l & 15);
-                        Pl[a * LDP + bcol] = P[I][J][r];
-                        if (J > I) Pl[bcol * LDP + a] = -P[I][J][r];   // P is antisymmetric
-                    }
-            // row and column DP are zero (R overlays them, so they are rewritten per pair)
-            for (int c = l; c <= DP; c += 64) {
-                Pl[DP * LDP + c] = 0.0;
-                Pl[c * LDP + DP] = 0.0;
-            }
-            __syncthreads();
+            pair_formation<T>(Xw, Ca + (size_t)s * MAT2, Pl, l);
 
             // ---------------- R = rows K of Z, trailing T = [[B_LL, 0], [0, 0]]
             constexpr int RPL = (8 * T * (8 * T + NE) + 63) / 64;   // B entries of R per lane (n <= 8 T)
@@ -283,78 +378,8 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
             __syncthreads();
 
             // ---------------- pairwise elimination of K
-            double2 pfk = c_make(1.0, 0.0);
-            bool zero = false;
-            for (int k = 0; k < n; k += 2) {
-                // partner: the largest |R[k][p]|, p in (k, n), smallest p on near-ties.
-                // The key is |R[k][p]|^2 / max|B|^2 in single precision with its 6 low
-                // bits replaced by 63 - lane; non-negative floats order as unsigned
-                // integers, so one maximum gives both; non-candidates hold 0.
-                const int pc = k + 1 + l;
-                unsigned key = 0u;
-                if (pc < n) {
-                    const float f = (float)(c_abs2(Rl[k * WR + pc]) * rbmax);
-                    key = (__float_as_uint(f) & ~63u) | (unsigned)(63 - l);
-                }
-                const unsigned kmax = wave_max_u32(key);
-                // below 64: every candidate is zero relative to max|B| (or underflows
-                // single precision there); otherwise the low bits name a candidate
-                // lane (a NaN candidate included), so p < n
-                if (kmax < 64u) { zero = true; break; }
-                const int p = k + 1 + (63 - (int)(kmax & 63u));
-                if (p != k + 1) {
-                    if (l < WR) {
-                        const double2 t0 = Rl[(k + 1) * WR + l], t1 = Rl[p * WR + l];
-                        Rl[(k + 1) * WR + l] = t1;
-                        Rl[p * WR + l] = t0;
-                    }
-                    __syncthreads();
-                    if (l < n) {
-                        const double2 t0 = Rl[l * WR + k + 1], t1 = Rl[l * WR + p];
-                        Rl[l * WR + k + 1] = t1;
-                        Rl[l * WR + p] = t0;
-                    }
-                    __syncthreads();
-                    pfk = c_neg(pfk);
-                }
-                const double2 a = Rl[k * WR + k + 1];
-                pfk = c_mul(pfk, a);
-                const double2 ia = c_inv_nr(a);
-                const double2 *r0 = Rl + k * WR;
-                const double2 *r1 = Rl + (k + 1) * WR;
-#pragma unroll
-                for (int q = 0; q < NTQ; ++q) {
-                    if (l + 64 * q < NT2) {
-                        const int ca_ = n + ta[q], cb_ = n + tb[q];
-                        const double2 t = c_sub(c_mul(r1[ca_], r0[cb_]), c_mul(r0[ca_], r1[cb_]));
-                        tv[q] = c_fma(t, ia, tv[q]);
-                    }
-                }
-                // rows i in [k+2, n), columns j in [k+2, WR); lane halves take alternate
-                // rows: R[i][j] += R[k+1][i] tau_j - R[k][i] sigma_j with the scaled
-                // pivot rows tau = R[k] / a, sigma = R[k+1] / a
-                const int h = l >> 5;
-                for (int j = k + 2 + (l & 31); j < WR; j += 32) {
-                    const double2 tau = c_mul(r0[j], ia), nsig = c_neg(c_mul(r1[j], ia));
-                    for (int i = k + 2 + h; i < n; i += 2) {
-                        double2 *rij = Rl + i * WR + j;
-                        *rij = c_fma(r1[i], tau, c_fma(r0[i], nsig, *rij));
-                    }
-                }
-                __syncthreads();
-            }
-            // growth of the unpivoted columns: at the end every row of R is the pivot
-            // row it was when it was used, so its L and E entries are all there is to watch
-            double gmax = 0.0;
-            for (int e = l; e < n * 2 * NE; e += 64) {
-                const int i = e / (2 * NE), c = e - i * (2 * NE);
-                gmax = fmax(gmax, c_abs2(Rl[i * WR + n + c]));
-            }
-            double tmax = 0.0;
-#pragma unroll
-            for (int q = 0; q < NTQ; ++q) tmax = fmax(tmax, c_abs2(tv[q]));
-            tmax = wave_max(fmax(tmax, gmax));
-            const bool flag = zero || !(tmax <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * fmax(bmax, 1.0));
+            double2 pfk;
+            const bool flag = elim_bordered<NE, NTQ>(n, WR, Rl, ta, tb, tv, bmax, rbmax, l, pfk);
             if (l == 0 && flag) {
                 const uint32_t idx = atomicAdd(fb_count, 1u);
                 if ((int64_t)idx < fb_cap) fb_list[idx] = (int64_t)w * S_total + s;

@@ -1,0 +1,118 @@
+"""Parity of the HIP adjoint (shadow_overlap_grad, through the C ABI) with the
+CPU oracle's gradient, and with central finite differences of the HIP
+forward itself.
+
+Tolerances: S_w as in the forward (1e-10 relative); D_w and G_w per walker
+|x_gpu - x_oracle| <= 1e-9 max|x_oracle| (the derivative goes through matrix
+inverses, whose rounding is amplified by their condition number, on both
+sides); finite differences (h = 1e-6, central) to 1e-6 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_22408_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2506_22408_amd import binding
+    return binding
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def to_dev(phi, Q, bits):
+    return (torch.from_numpy(np.ascontiguousarray(phi)).to(dev()),
+            torch.from_numpy(np.ascontiguousarray(Q)).to(dev()),
+            torch.from_numpy(np.ascontiguousarray(bits).view(np.int64)).to(dev()))
+
+
+def gpu_grad(B, phi, Q, bits):
+    out, dlog, green, status = B.shadow_overlap_grad(*to_dev(phi, Q, bits))
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), dlog.cpu().numpy(), green.cpu().numpy(), status.cpu().numpy()
+
+
+def close_per_walker(a, b, rtol):
+    for w in range(a.shape[0]):
+        scale = np.abs(b[w]).max()
+        err = np.abs(a[w] - b[w]).max()
+        assert err <= rtol * scale, f"walker {w}: err {err:.3e} vs scale {scale:.3e}"
+
+
+@pytest.mark.parametrize("n,eta,W,S", [
+    (4, 2, 3, 7), (6, 2, 2, 5), (8, 4, 4, 9), (8, 2, 2, 4),            # one tile, ne = 2, 4, 6
+    (10, 8, 3, 6), (12, 8, 2, 5), (10, 4, 3, 7), (16, 8, 3, 11)])      # two tiles, ne = 2, 4, 6, 8
+def test_grad_matches_oracle(B, n, eta, W, S):
+    w = wl.make("g", n, eta, W, S, seed=500 + 3 * n + eta)
+    sg, dg, gg, st = gpu_grad(B, w.phi, w.Q, w.bits)
+    so, do, go = oracle.grad(w.phi, w.Q, w.bits)
+    assert not st.any()
+    assert np.all(np.abs(sg - so) <= 1e-10 * np.abs(so))
+    close_per_walker(dg, do, 1e-9)
+    close_per_walker(gg, go, 1e-9)
+
+
+def test_grad_finite_differences_of_the_gpu_forward(B):
+    """Central differences of the HIP forward S_w along Phi_pj (holomorphic
+    derivative: a real step h on the complex entry) against D_w S_w."""
+    n, eta = 16, 8
+    w = wl.make("fd", n, eta, 2, 40, seed=77)
+    sg, dg, _, _ = gpu_grad(B, w.phi, w.Q, w.bits)
+    rng = np.random.default_rng(3)
+    h = 1e-6
+    for _ in range(6):
+        p, j = int(rng.integers(n)), int(rng.integers(eta))
+        for step in (h, 1j * h):
+            ph = w.phi.copy()
+            ph[:, p, j] += step
+            sp, _, _ = B.shadow_overlap(*to_dev(ph, w.Q, w.bits))
+            ph[:, p, j] -= 2 * step
+            sm, _, _ = B.shadow_overlap(*to_dev(ph, w.Q, w.bits))
+            fd = (sp.cpu().numpy() - sm.cpu().numpy()) / (2 * step)
+            an = dg[:, p, j] * sg
+            assert np.all(np.abs(fd - an) <= 1e-6 * np.abs(an) + 1e-12), (p, j, step, fd, an)
+
+
+def test_grad_full_size_route(B):
+    """Shadows near a pair-preserving rotation make the elimination of K
+    ill conditioned, so those pairs take the full-size route (Pf and inverse
+    of every B + e_j J); all must still match the oracle."""
+    import scipy.linalg as sla
+    n, eta = 8, 4
+    rng = np.random.default_rng(41)
+    phi = wl.walkers(rng, 3, n, eta)
+    Qs = []
+    for eps in (3e-1, 1e-2, 1e-4, 1e-6):
+        hm = rng.standard_normal((2 * n, 2 * n))
+        Qs.append(sla.expm(eps * (hm - hm.T)))
+    Qs = np.array(Qs)
+    bits = wl.even_bits(rng, len(Qs), n)
+    sg, dg, gg, st = gpu_grad(B, phi, Qs, bits)
+    so, do, go = oracle.grad(phi, Qs, bits)
+    assert not (st & ~B.SO_WSTAT_SINGULAR).any()
+    assert np.all(np.abs(sg - so) <= 1e-9 * np.abs(so))
+    close_per_walker(dg, do, 1e-7)
+    close_per_walker(gg, go, 1e-7)
+
+
+def test_grad_unsupported_shapes_are_refused(B):
+    for n, eta in ((16, 2), (20, 16), (9, 4)):       # ne = 14; n > 16; ne odd
+        w = wl.make("u", n, eta, 2, 3, seed=1)
+        with pytest.raises(B.ShadowOvError) as e:
+            B.shadow_overlap_grad(*to_dev(w.phi, w.Q, w.bits))
+        assert e.value.code == B.SO_ERR_UNSUPPORTED
+
+
+def test_grad_deterministic(B):
+    w = wl.make("d", 16, 8, 3, 25, seed=12)
+    a = gpu_grad(B, w.phi, w.Q, w.bits)
+    b = gpu_grad(B, w.phi, w.Q, w.bits)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
