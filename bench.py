@@ -86,6 +86,58 @@ def cpu_baseline(w, target_s=24.0):
             "sample": f"all {w.W} walkers x first {s} of {w.S} shadows ({w.W * s} pairs, {dt:.1f} s)"}
 
 
+def grad_leg(args, B, wl, torch, np):
+    """The derivative workload (N = 16, eta = 8, 1,024 walkers x 10,000
+    shadows, 200 Cholesky-like vectors): one step = shadow_overlap_grad
+    (S_w, d log S_w / d Phi_w, G_w) plus the force bias.  Reported as walker x
+    shadow adjoint contributions per second, with walkers per second."""
+    g = wl.config("grad_n16")
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(g.phi).to(dev)
+    Q = torch.from_numpy(g.Q).to(dev)
+    bits = torch.from_numpy(g.bits.view(np.int64)).to(dev)
+    L = torch.from_numpy(g.L).to(dev)
+    B.shadow_overlap_grad(phi, Q, bits)
+    torch.cuda.synchronize()
+    B.profile_enable(True)
+    B.profile_read(B.PROF_GRAD)
+    t0 = time.perf_counter()
+    for _ in range(args.grad_steps):
+        out, dlog, green, status = B.shadow_overlap_grad(phi, Q, bits)
+        xbar = B.force_bias(green, L, 0.01)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gms, glaunch, gpairs = B.profile_read(B.PROF_GRAD)
+    B.profile_enable(False)
+    if int(status.abs().sum()) != 0 or not bool(torch.isfinite(xbar.real).all()):
+        raise RuntimeError("derivative run reported a numerical status")
+    per = (t1 - t0) / args.grad_steps
+    return {"metric": "grad evals/s", "value": g.W * g.S / per, "unit": "walker x shadow adjoint contributions/s",
+            "walkers_per_s": g.W / per, "ms_per_step": per * 1e3, "steps": args.grad_steps,
+            "config": {"workload": "grad_n16", "n": g.n, "eta": g.eta, "walkers": g.W, "shadows": g.S,
+                       "n_gamma": g.L.shape[1]},
+            "kernels": {"k_grad_pair": {"ms_per_step": gms / args.grad_steps}}}
+
+
+def cpu_grad_baseline(wl, target_s=20.0):
+    """The oracle's gradient on 16 walkers (one per host thread on the GPU
+    host) x the first few shadows; the pilot overestimates, so the sample
+    lands near 10 s."""
+    import oracle
+    g = wl.config("grad_n16")
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    Wb = 16
+    t = time.perf_counter()
+    oracle.grad(g.phi[:Wb], g.Q[:4], g.bits[:4], nthreads=nthreads)
+    pilot = max(time.perf_counter() - t, 1e-3) / (4 * Wb)
+    s = int(max(4, min(g.S, target_s / (pilot * Wb))))
+    t = time.perf_counter()
+    oracle.grad(g.phi[:Wb], g.Q[:s], g.bits[:s], nthreads=nthreads)
+    dt = time.perf_counter() - t
+    return {"value": Wb * s / dt, "unit": "walker x shadow adjoint contributions/s", "cores": nthreads,
+            "kind": "oracle", "sample": f"{Wb} walkers x first {s} of {g.S} shadows ({Wb * s} pairs, {dt:.1f} s)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +145,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="paper_n16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grad", action="store_true", help="skip the derivative leg")
+    ap.add_argument("--grad-steps", type=int, default=2)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -181,8 +235,12 @@ def main():
         "path": {"flops_per_pair": pf_flops + fm_flops, "tflops": (pf_flops + fm_flops) * value / 1e12,
                  "frac": (pf_flops + fm_flops) * value / 1e12 / PEAK_FP64_TFLOPS},
     }
+    if not args.no_grad:
+        rec["grad"] = grad_leg(args, B, wl, torch, np)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
+        if "grad" in rec:
+            rec["grad"]["cpu_baseline"] = cpu_grad_baseline(wl)
     print(json.dumps(rec), flush=True)
 
 

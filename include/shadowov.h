@@ -144,6 +144,16 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
                               so_c64 *overlap, so_c64 *dlog, so_c64 *green, int32_t *status,
                               void *workspace, size_t workspace_bytes, void *stream);
 
+/* Force bias of every walker ("Force bias and local energy", eq. force_bias,
+ * with the Cholesky vectors L^gamma of eq. cholesky_vec):
+ *   xbar[w][gamma] = -sqrt(dt) i sum_pq L[p n + q][gamma] G_w[p][q].
+ *   green   [n_walkers][n][n] complex128 (device), e.g. from shadow_overlap_grad
+ *   L       [n n][n_gamma] float64 (device), real
+ *   xbar    [n_walkers][n_gamma] complex128 out (device)
+ * n <= 32, dt >= 0.  Enqueued on `stream`; the caller owns all memory. */
+so_status so_force_bias(const so_c64 *green, int64_t n_walkers, int n, const double *L, int64_t n_gamma,
+                        double dt, so_c64 *xbar, void *stream);
+
 /* Kernel timing for benchmarks (not for the hot path of an application).
  * so_profile_enable(1) makes every later shadow_overlap call bracket each
  * launch of its node-Pfaffian kernel (kind 0), of its formation kernel

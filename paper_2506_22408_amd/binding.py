@@ -57,6 +57,9 @@ def _load():
     lib.shadow_overlap_grad.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, P, P, P,
                                         c.c_size_t, P]
     lib.shadow_overlap_grad.restype = c.c_int
+    lib.so_force_bias.argtypes = [c.c_void_p, c.c_int64, c.c_int, c.c_void_p, c.c_int64, c.c_double, c.c_void_p,
+                                  c.c_void_p]
+    lib.so_force_bias.restype = c.c_int
     lib.so_profile_enable.argtypes = [c.c_int]
     lib.so_profile_enable.restype = c.c_int
     lib.so_profile_read.argtypes = [c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
@@ -203,3 +206,47 @@ def shadow_overlap_grad(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, 
     if st != SO_OK:
         raise ShadowOvError(st, "shadow_overlap_grad")
     return out, dlog, green, status
+
+
+def force_bias(green: torch.Tensor, L: torch.Tensor, dt: float = 0.01) -> torch.Tensor:
+    """xbar [W, n_gamma] = -sqrt(dt) i sum_pq L[pq, gamma] G[w, p, q] (so_force_bias)."""
+    if green.dtype != torch.complex128 or L.dtype != torch.float64:
+        raise TypeError("green must be complex128 and L float64")
+    if not green.is_cuda or not L.is_cuda:
+        raise ValueError("green and L must be device tensors")
+    W, n, n2 = green.shape
+    if n2 != n or L.dim() != 2 or L.shape[0] != n * n:
+        raise ValueError("green must be [W, n, n] and L [n*n, n_gamma]")
+    green, L = green.contiguous(), L.contiguous()
+    xbar = torch.empty((W, L.shape[1]), dtype=torch.complex128, device=green.device)
+    stream = torch.cuda.current_stream(green.device).cuda_stream
+    st = lib.so_force_bias(_dev_ptr(green), W, n, _dev_ptr(L), L.shape[1], float(dt), _dev_ptr(xbar),
+                           ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_force_bias")
+    return xbar
+
+
+class ShadowLogOverlap(torch.autograd.Function):
+    """log S_w(Phi_w) for every walker, differentiable in Phi.  S_w is a
+    polynomial (holomorphic) in Phi_w, so the backward pass is PyTorch's
+    conjugate-Wirtinger rule for a holomorphic map: grad_phi = conj(D_w) grad_out,
+    with D_w = d log S_w / d Phi_w from shadow_overlap_grad."""
+
+    @staticmethod
+    def forward(ctx, phi, Q, bits, n_nodes=0, nodes="unit"):
+        out, dlog, _, status = shadow_overlap_grad(phi.detach(), Q, bits, n_nodes=n_nodes, nodes=nodes,
+                                                   with_green=False)
+        ctx.save_for_backward(dlog)
+        ctx.mark_non_differentiable(status)
+        return torch.log(out), status
+
+    @staticmethod
+    def backward(ctx, grad_out, grad_status):
+        (dlog,) = ctx.saved_tensors
+        return torch.conj(dlog) * grad_out[:, None, None], None, None, None, None
+
+
+def log_overlap(phi, Q, bits, **kw):
+    """(log S_w [W], status [W]) with autograd support in phi."""
+    return ShadowLogOverlap.apply(phi, Q, bits, kw.get("n_nodes", 0), kw.get("nodes", "unit"))

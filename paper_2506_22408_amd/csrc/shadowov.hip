@@ -28,6 +28,7 @@
 //   k_grad_walker   per walker: sums, gather, D_w, G_w, S_w (so_grad.h)
 #include "shadowov.h"
 
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 
@@ -38,6 +39,7 @@
 #include "so_fallback.h"
 #include "so_pair.h"
 #include "so_grad.h"
+#include "so_force.h"
 
 // --------------------------------------------------------------------------
 // k_reduce: S_w = (1/S) sum_s o_ws, fixed order: lane l sums s = l, l+64, ...
@@ -659,6 +661,18 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
                        reinterpret_cast<double2 *>(green), wst);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     return SO_OK;
+}
+
+so_status so_force_bias(const so_c64 *green, int64_t n_walkers, int n, const double *L, int64_t n_gamma,
+                        double dt, so_c64 *xbar, void *stream) {
+    if (!green || !L || !xbar || n_walkers < 1 || n_gamma < 1 || n < 1 || n > SO_NMAX || !(dt >= 0.0))
+        return SO_ERR_ARG;
+    if (n_walkers > (int64_t)INT32_MAX) return SO_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_force_bias, dim3((unsigned)n_walkers), dim3(256), 0, st,
+                       reinterpret_cast<const double2 *>(green), n, L, n_gamma, std::sqrt(dt),
+                       reinterpret_cast<double2 *>(xbar));
+    return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
 }
 
 so_status so_profile_enable(int on) {

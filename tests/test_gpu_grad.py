@@ -63,7 +63,7 @@ def test_grad_finite_differences_of_the_gpu_forward(B):
     """Central differences of the HIP forward S_w along Phi_pj (holomorphic
     derivative: a real step h on the complex entry) against D_w S_w."""
     n, eta = 16, 8
-    w = wl.make("fd", n, eta, 2, 40, seed=77)
+    w = wl.make("fd", n, eta, 8, 40, seed=77)
     sg, dg, _, _ = gpu_grad(B, w.phi, w.Q, w.bits)
     rng = np.random.default_rng(3)
     h = 1e-6
@@ -108,6 +108,51 @@ def test_grad_unsupported_shapes_are_refused(B):
         with pytest.raises(B.ShadowOvError) as e:
             B.shadow_overlap_grad(*to_dev(w.phi, w.Q, w.bits))
         assert e.value.code == B.SO_ERR_UNSUPPORTED
+
+
+def test_force_bias_matches_oracle(B):
+    """x_bar from the GPU Green's function with 200 Cholesky-like vectors
+    (the gradient workload's shapes) against the oracle's definition."""
+    w = wl.config("grad_n16", W=8, S=30)
+    _, _, gg, st = gpu_grad(B, w.phi, w.Q, w.bits)
+    assert not st.any()
+    xb = B.force_bias(torch.from_numpy(gg).to(dev()), torch.from_numpy(w.L).to(dev()), 0.01).cpu().numpy()
+    ref = oracle.force_bias(gg, w.L, 0.01)
+    assert xb.shape == (8, 200)
+    assert np.all(np.abs(xb - ref) <= 1e-13 * np.abs(ref).max())
+
+
+def test_autograd_log_overlap(B):
+    """loss = Re sum_w c_w log S_w; phi.grad from the autograd function
+    against central differences of the loss in Re and Im of Phi entries."""
+    n, eta = 8, 4
+    w = wl.make("ag", n, eta, 3, 12, seed=21)
+    phi = torch.from_numpy(w.phi).to(dev()).requires_grad_(True)
+    Qd = torch.from_numpy(w.Q).to(dev())
+    bd = torch.from_numpy(w.bits.view(np.int64)).to(dev())
+    c = torch.tensor([0.3 - 0.7j, -1.1 + 0.2j, 0.5 + 0.5j], dtype=torch.complex128, device=dev())
+    logs, st = B.log_overlap(phi, Qd, bd)
+    assert not st.any()
+    (c * logs).real.sum().backward()
+    g = phi.grad.cpu().numpy()
+
+    def loss(ph):
+        s, _, _ = B.shadow_overlap(torch.from_numpy(ph).to(dev()), Qd, bd)
+        return float((c * torch.log(s)).real.sum())
+
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    for _ in range(5):
+        wi, p, j = int(rng.integers(3)), int(rng.integers(n)), int(rng.integers(eta))
+        num = 0j
+        for step, unit in ((h, 1.0), (1j * h, 1j)):
+            ph = w.phi.copy()
+            ph[wi, p, j] += step
+            lp = loss(ph)
+            ph[wi, p, j] -= 2 * step
+            lm = loss(ph)
+            num += unit * (lp - lm) / (2 * h)
+        assert abs(num - g[wi, p, j]) <= 1e-6 * max(abs(g[wi, p, j]), 1e-3), (wi, p, j, num, g[wi, p, j])
 
 
 def test_grad_deterministic(B):
