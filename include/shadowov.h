@@ -144,6 +144,50 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
                               so_c64 *overlap, so_c64 *dlog, so_c64 *green, int32_t *status,
                               void *workspace, size_t workspace_bytes, void *stream);
 
+/* One problem of a batch: the arguments of shadow_overlap, plus two tuning
+ * knobs for problems on the fused pair kernel (n - eta even, 2..8):
+ *   shadows_per_item  shadows per work item of the persistent kernel
+ *                     (rounded up to a multiple of the node batch 64/(ne+1));
+ *                     0 = library default
+ *   waves_per_cu      persistent waves per compute unit; 0 = default
+ * so_autotune fills both. */
+typedef struct {
+    so_params params;
+    const so_c64 *phi;
+    int64_t n_walkers;
+    const double *Q;
+    const uint64_t *bits;
+    int64_t n_shadows;
+    so_c64 *overlap;
+    so_c64 *pair_out;
+    int32_t *status;
+    int shadows_per_item;
+    int waves_per_cu;
+} so_problem;
+
+/* Workspace bytes for shadow_overlap_batched over these problems (1..16). */
+so_status so_batch_workspace_size(const so_problem *probs, int n_probs, size_t *bytes);
+
+/* Several independent problems -- e.g. walker and shadow sets of several
+ * geometries with different orbital counts -- in one call: the overlaps of
+ * shadow_overlap for each, bit for bit the same values.  Problems on the
+ * fused pair kernel share persistent launches per kernel class (same MFMA
+ * tile count and n - eta), whose work items (walker, shadow range) are taken
+ * from a queue in longest-processing-time order; the other problems use the
+ * two-kernel path.  Everything is enqueued on `stream` with no allocation,
+ * no memset and no host synchronisation, so the call may be captured into a
+ * hipGraph and replayed (the workspace and outputs must then stay fixed). */
+so_status shadow_overlap_batched(const so_problem *probs, int n_probs, void *workspace, size_t workspace_bytes,
+                                 void *stream);
+
+/* Autotuner: times the persistent fused kernel of this problem on a sample
+ * of its own inputs (about 2^21 pairs) over shadows_per_item in {1, 2, 4, 8}
+ * node batches and waves_per_cu in {4, 8, 16}, and writes the fastest pair
+ * into *prob (zeros for problems on the two-kernel path).  Synchronises the
+ * stream (not capturable); the caller's outputs are not written.  Workspace:
+ * so_batch_workspace_size(prob, 1). */
+so_status so_autotune(so_problem *prob, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Force bias of every walker ("Force bias and local energy", eq. force_bias,
  * with the Cholesky vectors L^gamma of eq. cholesky_vec):
  *   xbar[w][gamma] = -sqrt(dt) i sum_pq L[p n + q][gamma] G_w[p][q].

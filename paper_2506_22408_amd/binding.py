@@ -39,6 +39,13 @@ class SoC64(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
 
 
+class SoProblem(ctypes.Structure):
+    _fields_ = [("params", SoParams), ("phi", ctypes.c_void_p), ("n_walkers", ctypes.c_int64),
+                ("Q", ctypes.c_void_p), ("bits", ctypes.c_void_p), ("n_shadows", ctypes.c_int64),
+                ("overlap", ctypes.c_void_p), ("pair_out", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("shadows_per_item", ctypes.c_int), ("waves_per_cu", ctypes.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
@@ -57,6 +64,12 @@ def _load():
     lib.shadow_overlap_grad.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, P, P, P,
                                         c.c_size_t, P]
     lib.shadow_overlap_grad.restype = c.c_int
+    lib.so_batch_workspace_size.argtypes = [c.POINTER(SoProblem), c.c_int, c.POINTER(c.c_size_t)]
+    lib.so_batch_workspace_size.restype = c.c_int
+    lib.shadow_overlap_batched.argtypes = [c.POINTER(SoProblem), c.c_int, P, c.c_size_t, P]
+    lib.shadow_overlap_batched.restype = c.c_int
+    lib.so_autotune.argtypes = [c.POINTER(SoProblem), P, c.c_size_t, P]
+    lib.so_autotune.restype = c.c_int
     lib.so_force_bias.argtypes = [c.c_void_p, c.c_int64, c.c_int, c.c_void_p, c.c_int64, c.c_double, c.c_void_p,
                                   c.c_void_p]
     lib.so_force_bias.restype = c.c_int
@@ -250,3 +263,72 @@ class ShadowLogOverlap(torch.autograd.Function):
 def log_overlap(phi, Q, bits, **kw):
     """(log S_w [W], status [W]) with autograd support in phi."""
     return ShadowLogOverlap.apply(phi, Q, bits, kw.get("n_nodes", 0), kw.get("nodes", "unit"))
+
+
+class Batch:
+    """A batch of problems for shadow_overlap_batched with every output and
+    the workspace allocated up front, so that ``run`` allocates nothing and
+    may be captured into a graph.  ``problems`` is a list of dicts with keys
+    phi, Q, bits (device tensors) and optionally n_nodes, nodes, paper_norm,
+    return_pairs, shadows_per_item, waves_per_cu.  After ``run`` (and a
+    synchronisation) ``overlap[k]``, ``status[k]`` and ``pairs[k]`` hold
+    problem k's results."""
+
+    def __init__(self, problems):
+        if not 1 <= len(problems) <= 16:
+            raise ValueError("1 to 16 problems")
+        self.keep, self.overlap, self.status, self.pairs = [], [], [], []
+        arr = (SoProblem * len(problems))()
+        dev = None
+        for k, pr in enumerate(problems):
+            phi, Q, bits = pr["phi"].contiguous(), pr["Q"].contiguous(), pr["bits"].contiguous()
+            W, n, eta, S = _check_inputs(phi, Q, bits)
+            dev = phi.device
+            out = torch.empty(W, dtype=torch.complex128, device=dev)
+            st = torch.zeros(W, dtype=torch.int32, device=dev)
+            pairs = torch.empty((W, S), dtype=torch.complex128, device=dev) if pr.get("return_pairs") else None
+            self.keep += [phi, Q, bits]
+            self.overlap.append(out)
+            self.status.append(st)
+            self.pairs.append(pairs)
+            a = arr[k]
+            a.params = make_params(n, eta, pr.get("n_nodes", 0), pr.get("nodes", "unit"), "fp64",
+                                   pr.get("paper_norm", False))
+            a.phi, a.n_walkers, a.Q, a.bits, a.n_shadows = phi.data_ptr(), W, Q.data_ptr(), bits.data_ptr(), S
+            a.overlap, a.status = out.data_ptr(), st.data_ptr()
+            a.pair_out = pairs.data_ptr() if pairs is not None else None
+            a.shadows_per_item = int(pr.get("shadows_per_item", 0))
+            a.waves_per_cu = int(pr.get("waves_per_cu", 0))
+        self.arr, self.n = arr, len(problems)
+        nbytes = ctypes.c_size_t(0)
+        st = lib.so_batch_workspace_size(arr, self.n, ctypes.byref(nbytes))
+        if st != SO_OK:
+            raise ShadowOvError(st, "so_batch_workspace_size")
+        self.workspace = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=dev)
+
+    def run(self):
+        stream = torch.cuda.current_stream(self.workspace.device).cuda_stream
+        st = lib.shadow_overlap_batched(self.arr, self.n, _dev_ptr(self.workspace), self.workspace.numel(),
+                                        ctypes.c_void_p(stream))
+        if st != SO_OK:
+            raise ShadowOvError(st, "shadow_overlap_batched")
+
+    def autotune(self):
+        """Run so_autotune on every problem and keep the chosen knobs; returns
+        [(shadows_per_item, waves_per_cu)] per problem."""
+        stream = torch.cuda.current_stream(self.workspace.device).cuda_stream
+        out = []
+        for k in range(self.n):
+            one = (SoProblem * 1)(self.arr[k])
+            nbytes = ctypes.c_size_t(0)
+            st = lib.so_batch_workspace_size(one, 1, ctypes.byref(nbytes))
+            if st != SO_OK:
+                raise ShadowOvError(st, "so_batch_workspace_size")
+            ws = torch.empty(max(int(nbytes.value), 1), dtype=torch.uint8, device=self.workspace.device)
+            st = lib.so_autotune(one, _dev_ptr(ws), ws.numel(), ctypes.c_void_p(stream))
+            if st != SO_OK:
+                raise ShadowOvError(st, "so_autotune")
+            self.arr[k].shadows_per_item = one[0].shadows_per_item
+            self.arr[k].waves_per_cu = one[0].waves_per_cu
+            out.append((one[0].shadows_per_item, one[0].waves_per_cu))
+        return out

@@ -20,6 +20,7 @@
 //                   elimination of the occupied indices: S_ws and Pf(B_OO)
 //                   (so_form.h)
 //     k_nodes       node Pfaffians Pf(s_k S + c_k J), weighted sum (so_nodes.h)
+//   (shadow_overlap_batched: k_pair_persistent per kernel class, so_batch.h)
 //   k_fallback      full-size path for the rare pairs flagged above (so_fallback.h)
 //   k_reduce        S_w = (1/S) sum_s o_ws, fixed order (deterministic)
 // and for the derivative (shadow_overlap_grad), after the two prep kernels:
@@ -40,6 +41,7 @@
 #include "so_pair.h"
 #include "so_grad.h"
 #include "so_force.h"
+#include "so_batch.h"
 
 // --------------------------------------------------------------------------
 // k_reduce: S_w = (1/S) sum_s o_ws, fixed order: lane l sums s = l, l+64, ...
@@ -498,6 +500,226 @@ hipError_t prof_end(hipStream_t st, hipEvent_t a, int kind, int64_t units) {
     return hipSuccess;
 }
 
+// ---- one problem's plan: validated sizes, workspace pointers, node table
+struct ProbPlan {
+    int n, eta, m, d, M2, K;
+    int64_t W, S;
+    Layout L;
+    NodeTab tab;
+    const double2 *phi;
+    const double *Q;
+    const uint64_t *bits;
+    double2 *overlap, *pairs, *Sb, *Pb, *fbB;
+    const double2 *Xa, *Ca;
+    double *Xw, *Cw;
+    int32_t *wst;
+    uint32_t *fbc;
+    int64_t *fbl;
+};
+
+so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const double *Q, const uint64_t *bits,
+                       int64_t S, so_c64 *overlap, so_c64 *pair_out, int32_t *status, char *ws, size_t bytes,
+                       ProbPlan *P) {
+    int K;
+    if (!params_ok(p, &K) || !phi || !Q || !bits || !overlap || W < 1 || S < 1) return SO_ERR_ARG;
+    if (!so_supported(p->n, p->eta)) return SO_ERR_UNSUPPORTED;
+    if (p->precision != SO_PREC_FP64) return SO_ERR_UNSUPPORTED;
+    if (W > (int64_t)INT32_MAX || S > (int64_t)INT32_MAX) return SO_ERR_ARG;
+    P->n = p->n;
+    P->eta = p->eta;
+    P->m = mvalue(p->n, p->eta);
+    P->d = 2 * p->n;
+    P->M2 = P->m - p->eta;
+    P->K = K;
+    P->W = W;
+    P->S = S;
+    P->L = make_layout(p->n, p->eta, W, S);
+    if (!ws || bytes < P->L.total) return SO_ERR_WORKSPACE;
+    build_nodetab(p, K, &P->tab);
+    P->phi = reinterpret_cast<const double2 *>(phi);
+    P->Q = Q;
+    P->bits = bits;
+    P->overlap = reinterpret_cast<double2 *>(overlap);
+    P->Xw = reinterpret_cast<double *>(ws + P->L.off_X);
+    P->Cw = reinterpret_cast<double *>(ws + P->L.off_C);
+    P->Xa = reinterpret_cast<const double2 *>(P->Xw);
+    P->Ca = reinterpret_cast<const double2 *>(P->Cw);
+    P->Sb = reinterpret_cast<double2 *>(ws + P->L.off_S);
+    P->Pb = reinterpret_cast<double2 *>(ws + P->L.off_P);
+    P->pairs = pair_out ? reinterpret_cast<double2 *>(pair_out) : reinterpret_cast<double2 *>(ws + P->L.off_pairs);
+    P->wst = status ? status : reinterpret_cast<int32_t *>(ws + P->L.off_stat);
+    P->fbc = reinterpret_cast<uint32_t *>(ws + P->L.off_fbc);
+    P->fbl = reinterpret_cast<int64_t *>(ws + P->L.off_fbl);
+    P->fbB = reinterpret_cast<double2 *>(ws + P->L.off_fbB);
+    return SO_OK;
+}
+
+// walker and shadow preparation (X_w, C'_s; clears the fallback queue)
+hipError_t enqueue_prep(const ProbPlan &P, hipStream_t st) {
+    hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)P.W), dim3(64), 0, st, P.n, P.eta, P.phi, P.Xw, P.wst, P.fbc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)P.S), dim3(256), (size_t)P.d * P.d * sizeof(double), st, P.n,
+                       P.Q, P.bits, P.Cw);
+    return hipGetLastError();
+}
+
+// the two-kernel path (n - eta odd, 0 or above 8): formation + Schur
+// complement per chunk of shadows, then the node Pfaffians of the chunk
+hipError_t enqueue_two_kernel(const ProbPlan &P, hipStream_t st) {
+    FormArgs fa{P.n, P.eta, P.Xa, P.Ca, P.S, 0, 0, kFormShadowsPerWave, P.Sb, P.Pb, P.fbc, P.fbl, P.L.fb_cap,
+                P.wst, P.W};
+    for (int64_t s0 = 0; s0 < P.S; s0 += P.L.Sc) {
+        const int Sc = (int)((P.S - s0) < P.L.Sc ? (P.S - s0) : P.L.Sc);
+        fa.s0 = s0;
+        fa.Sc = Sc;
+        hipEvent_t ea = nullptr, eb = nullptr;
+        hipError_t e = prof_begin(st, &ea);
+        if (e == hipSuccess) e = launch_form(fa, st);
+        if (e == hipSuccess) e = prof_end(st, ea, PROF_FORM, P.W * Sc);
+        if (e == hipSuccess) e = prof_begin(st, &eb);
+        if (e == hipSuccess) e = launch_nodes(P.M2, P.Sb, P.Pb, P.tab, P.W * Sc, P.S, s0, Sc, P.pairs, st);
+        if (e == hipSuccess) e = prof_end(st, eb, PROF_PFAFF, P.W * Sc);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// the full-size path for the flagged pairs, then S_w
+hipError_t enqueue_finish(const ProbPlan &P, hipStream_t st) {
+    hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), 0, st, P.n, P.eta, P.Xw, P.Cw, P.tab, P.fbc, P.fbl,
+                       P.L.fb_cap, P.S, P.fbB, P.pairs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)P.W), dim3(64), 0, st, P.pairs, P.S, P.overlap, P.wst);
+    return hipGetLastError();
+}
+
+// ---- batches: persistent fused launches, LPT order, tuning knobs
+constexpr int kBatchMax = 16;
+constexpr int kDefaultWavesPerCU = 8;
+
+int device_cus() {
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 256;
+    }
+    return cached;
+}
+
+// node batch of the fused kernel (pairs whose nodes run together)
+int node_batch(int ne) { return 64 / (ne + 1); }
+
+int item_shadows(const so_problem &pr, int ne) {
+    const int nb = node_batch(ne);
+    int spw = pr.shadows_per_item > 0 ? pr.shadows_per_item : nb * kPairBatchesPerWave;
+    spw = ((spw + nb - 1) / nb) * nb;
+    return spw;
+}
+
+// relative cost of one pair (formation + elimination + node Pfaffians)
+double pair_cost(int n, int eta) {
+    const double ne = n - eta, m = 2.0 * n - eta;
+    return 16.0 * n * n * m + 8.0 * n * m * m + 8.0 * (n * n * (n + 2 * ne)) + (ne + 1) * 8.0 * ne * ne * ne;
+}
+
+template <int T, int NE>
+hipError_t launch_persistent_tn(const PairJobs &J, int grid, size_t lds, uint32_t *counter, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_pair_persistent<T, NE>), dim3((unsigned)grid), dim3(64), lds, st, J, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent(int T, int NE, const PairJobs &J, int grid, size_t lds, uint32_t *counter,
+                             hipStream_t st) {
+    switch (T * 16 + NE) {
+#define SO_PCASE(TT, NN) case TT * 16 + NN: return launch_persistent_tn<TT, NN>(J, grid, lds, counter, st);
+        SO_PCASE(1, 2) SO_PCASE(1, 4) SO_PCASE(1, 6) SO_PCASE(1, 8)
+        SO_PCASE(2, 2) SO_PCASE(2, 4) SO_PCASE(2, 6) SO_PCASE(2, 8)
+        SO_PCASE(3, 2) SO_PCASE(3, 4) SO_PCASE(3, 6) SO_PCASE(3, 8)
+#undef SO_PCASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// the jobs of one persistent launch: plans ix[0..nj) (one kernel class, in
+// LPT order), shadows [0, S_limit) of each (S_limit <= 0: all)
+PairJobs make_jobs(const ProbPlan *plans, const so_problem *probs, const int *ix, int nj, int64_t S_limit) {
+    PairJobs J;
+    std::memset(&J, 0, sizeof(J));
+    J.njobs = nj;
+    int64_t item = 0;
+    for (int k = 0; k < nj; ++k) {
+        const ProbPlan &P = plans[ix[k]];
+        PairJob &jb = J.job[k];
+        const int64_t S = (S_limit > 0 && S_limit < P.S) ? S_limit : P.S;
+        jb.Xa = P.Xa;
+        jb.Ca = P.Ca;
+        jb.pairs = P.pairs;
+        jb.fb_count = P.fbc;
+        jb.fb_list = P.fbl;
+        jb.wstat = P.wst;
+        jb.fb_cap = P.L.fb_cap;
+        jb.S = P.S;
+        jb.n = P.n;
+        jb.eta = P.eta;
+        jb.W = (int)P.W;
+        jb.spw = item_shadows(probs[ix[k]], P.n - P.eta);
+        jb.item0 = item;
+        jb.nitems = P.W * ((S + jb.spw - 1) / jb.spw);
+        item += jb.nitems;
+        for (int j = 0; j < P.tab.Ke; ++j) { J.tab[k].e[j] = P.tab.e[j]; J.tab[k].v[j] = P.tab.v[j]; }
+    }
+    J.total = item;
+    return J;
+}
+
+hipError_t launch_jobs(const ProbPlan *plans, const so_problem *probs, const int *ix, int nj, int64_t S_limit,
+                       int waves_per_cu, uint32_t *counter, hipStream_t st) {
+    const ProbPlan &P0 = plans[ix[0]];
+    const int T = so_tiles(P0.n), NE = P0.n - P0.eta;
+    const PairJobs J = make_jobs(plans, probs, ix, nj, S_limit);
+    size_t lds = 0;
+    for (int k = 0; k < nj; ++k) {
+        const size_t b = pair_lds_bytes(T, plans[ix[k]].n, NE);
+        if (b > lds) lds = b;
+    }
+    int64_t grid = (int64_t)device_cus() * (waves_per_cu > 0 ? waves_per_cu : kDefaultWavesPerCU);
+    if (grid > J.total) grid = J.total;
+    if (grid < 1) grid = 1;
+    int64_t pairs = 0;
+    for (int k = 0; k < nj; ++k) pairs += plans[ix[k]].W * plans[ix[k]].S;
+    hipEvent_t ea = nullptr;
+    hipError_t e = prof_begin(st, &ea);
+    if (e == hipSuccess) e = launch_persistent(T, NE, J, (int)grid, lds, counter, st);
+    if (e == hipSuccess) e = prof_end(st, ea, PROF_PAIR, pairs);
+    return e;
+}
+
+size_t batch_layout(const so_problem *probs, int n_probs, size_t *offs) {
+    size_t o = 0;
+    for (int k = 0; k < n_probs; ++k) {
+        offs[k] = o;
+        o = align_up(o + make_layout(probs[k].params.n, probs[k].params.eta, probs[k].n_walkers,
+                                     probs[k].n_shadows).total);
+    }
+    offs[n_probs] = o;                                   // launch counters
+    return align_up(o + (size_t)kBatchMax * sizeof(uint32_t));
+}
+
+bool problem_ok(const so_problem &pr) {
+    int K;
+    return params_ok(&pr.params, &K) && pr.n_walkers >= 1 && pr.n_shadows >= 1 && pr.phi && pr.Q && pr.bits &&
+           pr.overlap;
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -537,65 +759,23 @@ so_status so_node_weights(const so_params *p, so_c64 *nodes, so_c64 *weights, in
 so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walkers, const double *Q,
                          const uint64_t *bits, int64_t n_shadows, so_c64 *overlap, so_c64 *pair_out,
                          int32_t *status, void *workspace, size_t workspace_bytes, void *stream) {
-    int K;
-    if (!params_ok(p, &K) || !phi || !Q || !bits || !overlap || n_walkers < 1 || n_shadows < 1)
-        return SO_ERR_ARG;
-    if (!so_supported(p->n, p->eta)) return SO_ERR_UNSUPPORTED;
-    if (p->precision != SO_PREC_FP64) return SO_ERR_UNSUPPORTED;
-    if (n_walkers > (int64_t)INT32_MAX || n_shadows > (int64_t)INT32_MAX) return SO_ERR_ARG;
-    const int n = p->n, eta = p->eta, m = mvalue(n, eta), d = 2 * n, M2 = m - eta;
-    const int64_t W = n_walkers, S = n_shadows;
-    Layout L = make_layout(n, eta, W, S);
-    if (!workspace || workspace_bytes < L.total) return SO_ERR_WORKSPACE;
+    ProbPlan P;
+    const so_status sv = plan_problem(p, phi, n_walkers, Q, bits, n_shadows, overlap, pair_out, status,
+                                      static_cast<char *>(workspace), workspace_bytes, &P);
+    if (sv != SO_OK) return sv;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    char *ws = static_cast<char *>(workspace);
-    double *Xa = reinterpret_cast<double *>(ws + L.off_X);
-    double *Ca = reinterpret_cast<double *>(ws + L.off_C);
-    double2 *Sb = reinterpret_cast<double2 *>(ws + L.off_S);
-    double2 *Pb = reinterpret_cast<double2 *>(ws + L.off_P);
-    double2 *pairs = pair_out ? reinterpret_cast<double2 *>(pair_out) : reinterpret_cast<double2 *>(ws + L.off_pairs);
-    int32_t *wst = status ? status : reinterpret_cast<int32_t *>(ws + L.off_stat);
-    uint32_t *fbc = reinterpret_cast<uint32_t *>(ws + L.off_fbc);
-    int64_t *fbl = reinterpret_cast<int64_t *>(ws + L.off_fbl);
-    double2 *fbB = reinterpret_cast<double2 *>(ws + L.off_fbB);
-    NodeTab tab;
-    build_nodetab(p, K, &tab);
-
-    hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
-                       reinterpret_cast<const double2 *>(phi), Xa, wst, fbc);
-    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
-    hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q,
-                       bits, Ca);
-    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
-    if (fused_ok(n, eta)) {
+    if (enqueue_prep(P, st) != hipSuccess) return SO_ERR_HIP;
+    if (fused_ok(P.n, P.eta)) {
         hipEvent_t ea = nullptr;
         if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
-        if (launch_pair(n, eta, reinterpret_cast<const double2 *>(Xa), reinterpret_cast<const double2 *>(Ca), W, S,
-                        tab, pairs, fbc, fbl, L.fb_cap, wst, st) != hipSuccess)
+        if (launch_pair(P.n, P.eta, P.Xa, P.Ca, P.W, P.S, P.tab, P.pairs, P.fbc, P.fbl, P.L.fb_cap, P.wst, st) !=
+            hipSuccess)
             return SO_ERR_HIP;
-        if (prof_end(st, ea, PROF_PAIR, W * S) != hipSuccess) return SO_ERR_HIP;
-    } else {
-        FormArgs fa{n, eta, reinterpret_cast<const double2 *>(Xa), reinterpret_cast<const double2 *>(Ca), S, 0, 0,
-                    kFormShadowsPerWave, Sb, Pb, fbc, fbl, L.fb_cap, wst, W};
-        for (int64_t s0 = 0; s0 < S; s0 += L.Sc) {
-            const int Sc = (int)((S - s0) < L.Sc ? (S - s0) : L.Sc);
-            fa.s0 = s0;
-            fa.Sc = Sc;
-            hipEvent_t ea = nullptr, eb = nullptr;
-            if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
-            if (launch_form(fa, st) != hipSuccess) return SO_ERR_HIP;
-            if (prof_end(st, ea, PROF_FORM, W * Sc) != hipSuccess) return SO_ERR_HIP;
-            if (prof_begin(st, &eb) != hipSuccess) return SO_ERR_HIP;
-            if (launch_nodes(M2, Sb, Pb, tab, W * Sc, S, s0, Sc, pairs, st) != hipSuccess) return SO_ERR_HIP;
-            if (prof_end(st, eb, PROF_PFAFF, W * Sc) != hipSuccess) return SO_ERR_HIP;
-        }
+        if (prof_end(st, ea, PROF_PAIR, P.W * P.S) != hipSuccess) return SO_ERR_HIP;
+    } else if (enqueue_two_kernel(P, st) != hipSuccess) {
+        return SO_ERR_HIP;
     }
-    hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), 0, st, n, eta, Xa, Ca, tab, fbc, fbl, L.fb_cap, S,
-                       fbB, pairs);
-    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)W), dim3(64), 0, st, pairs, S,
-                       reinterpret_cast<double2 *>(overlap), wst);
-    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    if (enqueue_finish(P, st) != hipSuccess) return SO_ERR_HIP;
     return SO_OK;
 }
 
@@ -673,6 +853,131 @@ so_status so_force_bias(const so_c64 *green, int64_t n_walkers, int n, const dou
                        reinterpret_cast<const double2 *>(green), n, L, n_gamma, std::sqrt(dt),
                        reinterpret_cast<double2 *>(xbar));
     return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
+}
+
+so_status so_batch_workspace_size(const so_problem *probs, int n_probs, size_t *bytes) {
+    if (!probs || !bytes || n_probs < 1 || n_probs > kBatchMax) return SO_ERR_ARG;
+    for (int k = 0; k < n_probs; ++k) {
+        if (!problem_ok(probs[k])) return SO_ERR_ARG;
+        if (!so_supported(probs[k].params.n, probs[k].params.eta)) return SO_ERR_UNSUPPORTED;
+    }
+    size_t offs[kBatchMax + 1];
+    *bytes = batch_layout(probs, n_probs, offs);
+    return SO_OK;
+}
+
+so_status shadow_overlap_batched(const so_problem *probs, int n_probs, void *workspace, size_t workspace_bytes,
+                                 void *stream) {
+    size_t need = 0;
+    so_status sv = so_batch_workspace_size(probs, n_probs, &need);
+    if (sv != SO_OK) return sv;
+    if (!workspace || workspace_bytes < need) return SO_ERR_WORKSPACE;
+    size_t offs[kBatchMax + 1];
+    batch_layout(probs, n_probs, offs);
+    char *ws = static_cast<char *>(workspace);
+    uint32_t *counters = reinterpret_cast<uint32_t *>(ws + offs[n_probs]);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    ProbPlan plans[kBatchMax];
+    for (int k = 0; k < n_probs; ++k) {
+        const so_problem &pr = probs[k];
+        sv = plan_problem(&pr.params, pr.phi, pr.n_walkers, pr.Q, pr.bits, pr.n_shadows, pr.overlap, pr.pair_out,
+                          pr.status, ws + offs[k], offs[k + 1] - offs[k], &plans[k]);
+        if (sv != SO_OK) return sv;
+    }
+    for (int k = 0; k < n_probs; ++k)
+        if (enqueue_prep(plans[k], st) != hipSuccess) return SO_ERR_HIP;
+    // fused problems in longest-processing-time order, grouped by kernel class
+    int order[kBatchMax], nf = 0;
+    double cost[kBatchMax];
+    for (int k = 0; k < n_probs; ++k)
+        if (fused_ok(plans[k].n, plans[k].eta)) {
+            cost[k] = pair_cost(plans[k].n, plans[k].eta) * item_shadows(probs[k], plans[k].n - plans[k].eta);
+            order[nf++] = k;
+        }
+    for (int a = 1; a < nf; ++a)
+        for (int b = a; b > 0 && cost[order[b]] > cost[order[b - 1]]; --b) std::swap(order[b], order[b - 1]);
+    bool used[kBatchMax] = {false};
+    int launch = 0;
+    for (int a = 0; a < nf; ++a) {
+        if (used[a]) continue;
+        const int ka = order[a];
+        const int T = so_tiles(plans[ka].n), NE = plans[ka].n - plans[ka].eta;
+        int ix[SO_JOBS_PER_LAUNCH], nj = 0;
+        for (int b = a; b < nf && nj < SO_JOBS_PER_LAUNCH; ++b) {
+            const int kb = order[b];
+            if (used[b] || so_tiles(plans[kb].n) != T || plans[kb].n - plans[kb].eta != NE) continue;
+            used[b] = true;
+            ix[nj++] = kb;
+        }
+        if (launch_jobs(plans, probs, ix, nj, 0, probs[ix[0]].waves_per_cu, counters + launch, st) != hipSuccess)
+            return SO_ERR_HIP;
+        ++launch;
+    }
+    for (int k = 0; k < n_probs; ++k)
+        if (!fused_ok(plans[k].n, plans[k].eta) && enqueue_two_kernel(plans[k], st) != hipSuccess) return SO_ERR_HIP;
+    for (int k = 0; k < n_probs; ++k)
+        if (enqueue_finish(plans[k], st) != hipSuccess) return SO_ERR_HIP;
+    return SO_OK;
+}
+
+so_status so_autotune(so_problem *prob, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!prob) return SO_ERR_ARG;
+    size_t need = 0;
+    so_status sv = so_batch_workspace_size(prob, 1, &need);
+    if (sv != SO_OK) return sv;
+    if (!workspace || workspace_bytes < need) return SO_ERR_WORKSPACE;
+    size_t offs[2];
+    batch_layout(prob, 1, offs);
+    char *ws = static_cast<char *>(workspace);
+    uint32_t *counter = reinterpret_cast<uint32_t *>(ws + offs[1]);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    ProbPlan P;
+    // pair values go to the workspace: the caller's outputs are not touched
+    sv = plan_problem(&prob->params, prob->phi, prob->n_walkers, prob->Q, prob->bits, prob->n_shadows,
+                      prob->overlap, nullptr, nullptr, ws, offs[1], &P);
+    if (sv != SO_OK) return sv;
+    if (!fused_ok(P.n, P.eta)) {
+        prob->shadows_per_item = 0;
+        prob->waves_per_cu = 0;
+        return SO_OK;
+    }
+    if (enqueue_prep(P, st) != hipSuccess) return SO_ERR_HIP;
+    const int nb = node_batch(P.n - P.eta);
+    // a sample of about 2^21 pairs: enough to fill the machine for a few ms
+    int64_t Ss = ((int64_t)1 << 21) / P.W;
+    if (Ss < 8 * nb) Ss = 8 * nb;
+    if (Ss > P.S) Ss = P.S;
+    const int mults[4] = {1, 2, 4, 8};
+    const int wpcs[3] = {4, 8, 16};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SO_ERR_HIP;
+    float best = 1e30f;
+    int best_spw = nb * kPairBatchesPerWave, best_wpc = kDefaultWavesPerCU;
+    so_problem trial = *prob;
+    const int ix[1] = {0};
+    for (int mi = 0; mi < 4; ++mi)
+        for (int wi = 0; wi < 3; ++wi) {
+            trial.shadows_per_item = nb * mults[mi];
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                if (hipEventRecord(e0, st) != hipSuccess) return SO_ERR_HIP;
+                if (launch_jobs(&P, &trial, ix, 1, Ss, wpcs[wi], counter, st) != hipSuccess) return SO_ERR_HIP;
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return SO_ERR_HIP;
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return SO_ERR_HIP;
+                if (ms < tmin) tmin = ms;
+            }
+            if (tmin < best) {
+                best = tmin;
+                best_spw = trial.shadows_per_item;
+                best_wpc = wpcs[wi];
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    prob->shadows_per_item = best_spw;
+    prob->waves_per_cu = best_wpc;
+    return SO_OK;
 }
 
 so_status so_profile_enable(int on) {

@@ -259,13 +259,15 @@ __host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
     return a + (size_t)NB * (3 * (NE * (NE - 1) / 2) + 1) * sizeof(double2);
 }
 
-// grid (W, ceil(S_total / spw)), one wave per block; spw is a multiple of NB.
+// One walker w over the shadows [sb0, sb1): formation, elimination, node
+// Pfaffians and the pair values pairs[w S_total + s].  One wave; the LDS
+// layout is pair_lds_bytes(T, n, NE).
 template <int T, int NE>
-__global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__restrict__ Xa,
-                                             const double2 *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
-                                             RedTab tab, double2 *__restrict__ pairs,
-                                             uint32_t *__restrict__ fb_count, int64_t *__restrict__ fb_list,
-                                             int64_t fb_cap, int32_t *__restrict__ wstat) {
+__device__ __forceinline__ void pair_range(int n, int eta, const double2 *__restrict__ Xa,
+                                           const double2 *__restrict__ Ca, int64_t S_total, const RedTab &tab,
+                                           double2 *__restrict__ pairs, uint32_t *__restrict__ fb_count,
+                                           int64_t *__restrict__ fb_list, int64_t fb_cap,
+                                           int32_t *__restrict__ wstat, int w, int64_t sb0, int64_t sb1) {
     constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
     constexpr int MAT2 = DP * DP / 2;
     constexpr int KE = NE + 1;
@@ -291,7 +293,6 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
     double2 *Bt = reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) + abytes);   // batch slots
 
     const int l = threadIdx.x;
-    const int w = blockIdx.x;
     const int WR = n + 2 * NE;              // columns of R: K (n), L (NE), E (NE)
 
     // this lane's trailing entries (a < b) of the 2NE x 2NE block
@@ -316,8 +317,6 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
         return c_make(Pl[ir + jr] - Pl[ii + ji], Pl[ir + ji] + Pl[ii + jr]);
     };
 
-    const int64_t sb0 = (sy0 + blockIdx.y) * (int64_t)spw;
-    const int64_t sb1 = min(S_total, sb0 + spw);
     for (int64_t bs = sb0; bs < sb1; bs += NB) {
         const int nb = (int)min((int64_t)NB, sb1 - bs);
         for (int b = 0; b < nb; ++b) {
@@ -441,4 +440,18 @@ __global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__re
             pairs[(int64_t)w * S_total + bs + l] = acc;
         }
     }
+}
+
+// grid (W, ceil(S_total / spw)) from shadow group sy0, one wave per block;
+// spw is a multiple of 64 / (NE + 1).
+template <int T, int NE>
+__global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__restrict__ Xa,
+                                             const double2 *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
+                                             RedTab tab, double2 *__restrict__ pairs,
+                                             uint32_t *__restrict__ fb_count, int64_t *__restrict__ fb_list,
+                                             int64_t fb_cap, int32_t *__restrict__ wstat) {
+    const int64_t sb0 = (sy0 + blockIdx.y) * (int64_t)spw;
+    const int64_t sb1 = min(S_total, sb0 + spw);
+    pair_range<T, NE>(n, eta, Xa, Ca, S_total, tab, pairs, fb_count, fb_list, fb_cap, wstat, (int)blockIdx.x, sb0,
+                      sb1);
 }

@@ -1,0 +1,128 @@
+"""Batched problems (shadow_overlap_batched through the C ABI): a miniature of
+the uneven reaction-path workload (N = 8, 12, 16, 20 qubits, eta = N/2, one
+problem per geometry) must give exactly the bits of separate shadow_overlap
+calls (same kernels, same node tables, same fixed-order reduction), whatever
+the tuning knobs, also when captured into a graph and replayed."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2506_22408_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2506_22408_amd import binding
+    return binding
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def dev_problem(w, **kw):
+    d = dict(phi=torch.from_numpy(np.ascontiguousarray(w.phi)).to(dev()),
+             Q=torch.from_numpy(np.ascontiguousarray(w.Q)).to(dev()),
+             bits=torch.from_numpy(np.ascontiguousarray(w.bits).view(np.int64)).to(dev()),
+             return_pairs=True)
+    d.update(kw)
+    return d
+
+
+def mini_uneven():
+    """n = 8, 12, 16, 20 (eta = n/2): fused kernel classes (1, 4), (2, 6),
+    (2, 8) and the two-kernel path for ne = 10; plus a second (2, 8) problem
+    so that one persistent launch serves two problems."""
+    shapes = [(8, 4, 9, 23), (12, 6, 6, 31), (16, 8, 5, 45), (20, 10, 3, 17), (16, 8, 4, 29)]
+    return [wl.make(f"u{k}", n, eta, W, S, seed=900 + k) for k, (n, eta, W, S) in enumerate(shapes)]
+
+
+def single(B, pr):
+    out, pairs, st = B.shadow_overlap(pr["phi"], pr["Q"], pr["bits"], return_pairs=True)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), pairs.cpu().numpy(), st.cpu().numpy()
+
+
+def batch_results(bt):
+    torch.cuda.synchronize()
+    return [(bt.overlap[k].cpu().numpy(), bt.pairs[k].cpu().numpy(), bt.status[k].cpu().numpy())
+            for k in range(bt.n)]
+
+
+def assert_same(a, b):
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_batched_matches_individual_calls(B):
+    probs = [dev_problem(w) for w in mini_uneven()]
+    bt = B.Batch(probs)
+    bt.run()
+    got = batch_results(bt)
+    for k, pr in enumerate(probs):
+        assert_same(got[k], single(B, pr))
+        assert not got[k][2].any()
+
+
+def test_tuning_knobs_do_not_change_results(B):
+    ws = mini_uneven()
+    ref = batch_results(_run(B.Batch([dev_problem(w) for w in ws])))
+    for spi, wpc in ((7, 4), (28, 16), (56, 2)):
+        got = batch_results(_run(B.Batch([dev_problem(w, shadows_per_item=spi, waves_per_cu=wpc) for w in ws])))
+        for a, b in zip(got, ref):
+            assert_same(a, b)
+
+
+def _run(bt):
+    bt.run()
+    return bt
+
+
+def test_autotune_returns_valid_knobs(B):
+    ws = mini_uneven()
+    bt = B.Batch([dev_problem(w) for w in ws])
+    knobs = bt.autotune()
+    for w, (spi, wpc) in zip(ws, knobs):
+        ne = w.n - w.eta
+        if ne % 2 == 0 and 2 <= ne <= 8:
+            nb = 64 // (ne + 1)
+            assert spi % nb == 0 and spi // nb in (1, 2, 4, 8) and wpc in (4, 8, 16)
+        else:
+            assert (spi, wpc) == (0, 0)
+    bt.run()
+    for k, got in enumerate(batch_results(bt)):
+        assert_same(got, single(B, dict(phi=bt.keep[3 * k], Q=bt.keep[3 * k + 1], bits=bt.keep[3 * k + 2])))
+
+
+def test_graph_capture_and_replay(B):
+    ws = mini_uneven()
+    probs = [dev_problem(w) for w in ws]
+    bt = B.Batch(probs)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bt.run()
+    torch.cuda.current_stream().wait_stream(side)
+    eager = batch_results(bt)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bt.run()
+    other = mini_uneven()[2]
+    for rep in range(3):
+        for k in range(bt.n):                      # scribble over the outputs first
+            bt.overlap[k].fill_(0)
+            bt.pairs[k].fill_(0)
+        g.replay()
+        for a, b in zip(batch_results(bt), eager):
+            assert_same(a, b)
+        single(B, dev_problem(other))              # eager work between replays
+    # the graph reads its inputs at replay time: change a walker in place
+    bt.keep[0][0].mul_(1.5)
+    g.replay()
+    got = batch_results(bt)
+    ref0 = single(B, dict(phi=bt.keep[0], Q=bt.keep[1], bits=bt.keep[2]))
+    assert_same(got[0], ref0)
+    for a, b in zip(got[1:], eager[1:]):
+        assert_same(a, b)
