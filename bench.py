@@ -119,6 +119,58 @@ def grad_leg(args, B, wl, torch, np):
             "kernels": {"k_grad_pair": {"ms_per_step": gms / args.grad_steps}}}
 
 
+def uneven_leg(args, B, wl, torch, np):
+    """Four reaction-path geometries (N = 8, 12, 16, 20, eta = N/2, walkers
+    4096/2048/1024/512, shadows 2000/5000/10000/20000) in one batched call,
+    autotuned, captured into a graph and replayed: total walker x shadow
+    overlaps per second.  The same four problems as separate plain calls are
+    timed beside it."""
+    dev = torch.device("cuda:0")
+    probs = []
+    for c in wl.UNEVEN:
+        w = wl.make("uneven", c["n"], c["eta"], c["W"], c["S"], seed=c["seed"])
+        probs.append(dict(phi=torch.from_numpy(w.phi).to(dev), Q=torch.from_numpy(w.Q).to(dev),
+                          bits=torch.from_numpy(w.bits.view(np.int64)).to(dev)))
+    pairs = sum(c["W"] * c["S"] for c in wl.UNEVEN)
+    bt = B.Batch(probs)
+    knobs = bt.autotune()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bt.run()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bt.run()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.uneven_steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.uneven_steps
+    for pr in probs:
+        B.shadow_overlap(pr["phi"], pr["Q"], pr["bits"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.uneven_steps):
+        for pr in probs:
+            B.shadow_overlap(pr["phi"], pr["Q"], pr["bits"])
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.uneven_steps
+    for st in bt.status:
+        if int(st.abs().sum()) != 0:
+            raise RuntimeError("uneven batch reported a numerical status")
+    return {"metric": "walker x shadow overlaps/s, uneven batch", "value": pairs / t_graph, "unit": "overlaps/s",
+            "ms_per_step": t_graph * 1e3, "steps": args.uneven_steps, "pairs_per_step": pairs,
+            "plain_calls": {"value": pairs / t_plain, "ms_per_step": t_plain * 1e3},
+            "tuning": [{"n": c["n"], "shadows_per_item": k[0], "waves_per_cu": k[1]}
+                       for c, k in zip(wl.UNEVEN, knobs)],
+            "config": {"workload": "uneven_4_geometries", "n": [c["n"] for c in wl.UNEVEN],
+                       "walkers": [c["W"] for c in wl.UNEVEN], "shadows": [c["S"] for c in wl.UNEVEN],
+                       "graph": True}}
+
+
 def cpu_grad_baseline(wl, target_s=20.0):
     """The oracle's gradient on 16 walkers (one per host thread on the GPU
     host) x the first few shadows; the pilot overestimates, so the sample
@@ -147,6 +199,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-grad", action="store_true", help="skip the derivative leg")
     ap.add_argument("--grad-steps", type=int, default=2)
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--uneven-steps", type=int, default=3)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -237,6 +291,8 @@ def main():
     }
     if not args.no_grad:
         rec["grad"] = grad_leg(args, B, wl, torch, np)
+    if not args.no_uneven:
+        rec["uneven"] = uneven_leg(args, B, wl, torch, np)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
         if "grad" in rec:
