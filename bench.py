@@ -171,6 +171,78 @@ def uneven_leg(args, B, wl, torch, np):
                        "graph": True}}
 
 
+def mixed_n16_leg(args, B, torch, phi, Q, bits, pairs_per_step, out64):
+    """The main workload with the formation in single precision (precision
+    "mixed"): overlaps per second, and the largest |S_w - S_w^FP64| / |S_w|."""
+    B.shadow_overlap(phi, Q, bits, precision="mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out, _, status = B.shadow_overlap(phi, Q, bits, precision="mixed")
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / args.steps
+    if int(status.abs().sum()) != 0:
+        raise RuntimeError("mixed-precision run reported a numerical status")
+    rel = ((out - out64).abs() / out64.abs()).max().item()
+    return {"value": pairs_per_step / per, "unit": "overlaps/s", "ms_per_step": per * 1e3, "steps": args.steps,
+            "precision": "mixed", "max_rel_diff_S_w_vs_fp64": rel}
+
+
+def precision_leg(args, B, wl, torch, np):
+    """The precision workload (N = 24, eta = 12, 2,048 walkers x 50,000 Haar
+    SO(48) shadows): one step in FP64 and in the mixed mode, and the relative
+    pair error of both against the FP64 oracle on a seeded sample of pairs
+    (--precision-sample pairs; 1% of the workload is 1,024,000)."""
+    import oracle
+    w = wl.config("precision_n24")
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(w.phi).to(dev)
+    Q = torch.from_numpy(w.Q).to(dev)
+    bits = torch.from_numpy(w.bits.view(np.int64)).to(dev)
+    res = {"metric": "walker x shadow overlaps/s, n=24", "unit": "overlaps/s",
+           "config": {"workload": "precision_n24", "n": w.n, "eta": w.eta, "walkers": w.W, "shadows": w.S,
+                      "nodes": w.n + 1}}
+    rng = np.random.default_rng(2024)
+    ns = int(min(args.precision_sample, w.W * w.S))
+    flat = rng.choice(w.W * w.S, size=ns, replace=False)
+    sw, ss = flat // w.S, flat % w.S
+    sample = {}
+    for prec in ("fp64", "mixed"):
+        B.shadow_overlap(phi, Q, bits, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.precision_steps):
+            out, _, status = B.shadow_overlap(phi, Q, bits, precision=prec)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / args.precision_steps
+        if int(status.abs().sum()) != 0:
+            raise RuntimeError(f"n=24 {prec} run reported a numerical status")
+        res[prec] = {"value": w.W * w.S / per, "ms_per_step": per * 1e3, "steps": args.precision_steps}
+        _, pairs, _ = B.shadow_overlap(phi, Q, bits, precision=prec, return_pairs=True)
+        sample[prec] = pairs[torch.from_numpy(sw).to(dev), torch.from_numpy(ss).to(dev)].cpu().numpy()
+        del pairs
+        torch.cuda.empty_cache()
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    ref = np.empty(ns, np.complex128)
+    chunk = 20000
+    t0 = time.perf_counter()
+    for a in range(0, ns, chunk):
+        b = min(ns, a + chunk)
+        ref[a:b] = oracle.overlap_pairs(w.phi, w.Q, w.bits, pairs=np.stack([sw[a:b], ss[a:b]], 1),
+                                        nthreads=nthreads)
+        if ns > chunk:
+            print(f"precision leg: oracle {b}/{ns} pairs, {time.perf_counter() - t0:.0f} s", file=sys.stderr,
+                  flush=True)
+    for prec in ("fp64", "mixed"):
+        rel = np.abs(sample[prec] - ref) / np.abs(ref)
+        res[prec]["pair_rel_err"] = {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
+                                     "max": float(rel.max()), "frac_le_1e-6": float(np.mean(rel <= 1e-6))}
+    res["sample"] = f"{ns} pairs drawn uniformly without replacement (seed 2024) of {w.W * w.S}"
+    res["value"] = res["mixed"]["value"]
+    res["speedup_mixed_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+    return res
+
+
 def cpu_grad_baseline(wl, target_s=20.0):
     """The oracle's gradient on 16 walkers (one per host thread on the GPU
     host) x the first few shadows; the pilot overestimates, so the sample
@@ -201,6 +273,10 @@ def main():
     ap.add_argument("--grad-steps", type=int, default=2)
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--uneven-steps", type=int, default=3)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--precision-steps", type=int, default=2)
+    ap.add_argument("--precision-sample", type=int, default=2000,
+                    help="pairs of the n=24 workload checked against the oracle")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -289,6 +365,9 @@ def main():
         "path": {"flops_per_pair": pf_flops + fm_flops, "tflops": (pf_flops + fm_flops) * value / 1e12,
                  "frac": (pf_flops + fm_flops) * value / 1e12 / PEAK_FP64_TFLOPS},
     }
+    if not args.no_mixed:
+        rec["mixed"] = mixed_n16_leg(args, B, torch, phi, Q, bits, pairs_per_step, out)
+        rec["precision_n24"] = precision_leg(args, B, wl, torch, np)
     if not args.no_grad:
         rec["grad"] = grad_leg(args, B, wl, torch, np)
     if not args.no_uneven:

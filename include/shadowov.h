@@ -60,9 +60,18 @@ typedef enum {
  * printed in the paper (ill-conditioned for large n). */
 enum { SO_NODES_UNIT = 0, SO_NODES_CHEBYSHEV = 1 };
 
-/* Arithmetic of the pair formation B = X C' X^T.  FP64: everything in FP64.
- * MIXED: B formed with complex-FP32 MFMA and FP32 accumulation; Pfaffians,
- * interpolation and reductions stay FP64. */
+/* Arithmetic of the pair formation B = X C' X^T (eq. b_mat).  FP64:
+ * everything in FP64.  MIXED: X_w and C'_s are rounded to single precision
+ * and B is formed on the FP32 matrix cores with FP32 accumulation, then
+ * widened; pivoting, the Pfaffians, the node weights and the reduction over
+ * shadows stay FP64, and pairs flagged for the full-size path are redone in
+ * FP64 there.  The rounding of B (relative ~1e-7) reaches o_ws amplified by
+ * the conditioning of its Pfaffians: typically a few 1e-7 relative, 1e-5 for
+ * the worst pairs of Haar-random shadows at n = 24, and S_w (an average over
+ * shadows) within ~1e-6 of |S_w| + mean |o_ws|.  shadow_overlap and
+ * shadow_overlap_batched accept both; shadow_overlap_grad only FP64
+ * (SO_ERR_UNSUPPORTED otherwise).  MIXED adds 4 (W + S) DP^2 bytes of
+ * workspace (DP = 16 ceil(2n / 16)). */
 enum { SO_PREC_FP64 = 0, SO_PREC_MIXED = 1 };
 
 #define SO_FLAG_PAPER_NORM 1u /* omit the factor 2 (paper's o_p as printed) */

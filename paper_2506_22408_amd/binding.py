@@ -269,8 +269,8 @@ class Batch:
     """A batch of problems for shadow_overlap_batched with every output and
     the workspace allocated up front, so that ``run`` allocates nothing and
     may be captured into a graph.  ``problems`` is a list of dicts with keys
-    phi, Q, bits (device tensors) and optionally n_nodes, nodes, paper_norm,
-    return_pairs, shadows_per_item, waves_per_cu.  After ``run`` (and a
+    phi, Q, bits (device tensors) and optionally n_nodes, nodes, precision,
+    paper_norm, return_pairs, shadows_per_item, waves_per_cu.  After ``run`` (and a
     synchronisation) ``overlap[k]``, ``status[k]`` and ``pairs[k]`` hold
     problem k's results."""
 
@@ -292,8 +292,8 @@ class Batch:
             self.status.append(st)
             self.pairs.append(pairs)
             a = arr[k]
-            a.params = make_params(n, eta, pr.get("n_nodes", 0), pr.get("nodes", "unit"), "fp64",
-                                   pr.get("paper_norm", False))
+            a.params = make_params(n, eta, pr.get("n_nodes", 0), pr.get("nodes", "unit"),
+                                   pr.get("precision", "fp64"), pr.get("paper_norm", False))
             a.phi, a.n_walkers, a.Q, a.bits, a.n_shadows = phi.data_ptr(), W, Q.data_ptr(), bits.data_ptr(), S
             a.overlap, a.status = out.data_ptr(), st.data_ptr()
             a.pair_out = pairs.data_ptr() if pairs is not None else None

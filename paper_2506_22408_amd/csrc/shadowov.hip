@@ -285,7 +285,9 @@ constexpr int kFormShadowsPerWave = 8;                 // shadows per formation 
 constexpr int kPairBatchesPerWave = 2;                 // node batches per fused wave
 
 struct Layout {
-    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_fbB, off_F, off_O, total;
+    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_fbB, off_F, off_O;
+    size_t off_X32, off_C32;   // single-precision formation operands (mixed precision)
+    size_t total;
     int Sc;
     int64_t fb_cap;
     int Gy;   // shadow ranges per walker of the derivative kernel
@@ -309,7 +311,7 @@ int grad_ranges(int64_t W, int64_t S) {
 
 bool grad_ok(int n, int eta) { return fused_ok(n, eta) && so_tiles(n) <= 2; }
 
-Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false) {
+Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false, bool mixed = false) {
     Layout L{};
     const int m = mvalue(n, eta), DP = 16 * so_tiles(n), M2 = m - eta;
     const size_t per_shadow = (size_t)W * ((size_t)M2 * M2 + 1) * sizeof(double2);
@@ -339,6 +341,11 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false)
         L.off_F = o; o = align_up(o + (size_t)W * L.Gy * 2 * n * m * sizeof(double2));
         L.off_O = o; o = align_up(o + (size_t)W * L.Gy * sizeof(double2));
     }
+    L.off_X32 = L.off_C32 = o;
+    if (mixed) {
+        L.off_X32 = o; o = align_up(o + (size_t)W * DP * DP * sizeof(float));
+        L.off_C32 = o; o = align_up(o + (size_t)S * DP * DP * sizeof(float));
+    }
     L.total = o;
     return L;
 }
@@ -347,7 +354,8 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false)
 // up to a power of two.
 struct FormArgs {
     int n, eta;
-    const double2 *Xa, *Ca;
+    bool mix;                 // single-precision formation operands
+    const void *Xa, *Ca;
     int64_t S_total, s0;
     int Sc, spw;
     double2 *Sb, *Pb;
@@ -362,8 +370,12 @@ hipError_t launch_form_tn(const FormArgs &a, hipStream_t st) {
     const int m = mvalue(a.n, a.eta);
     const size_t lds = form_lds_bytes_t(T, a.eta, m);
     dim3 grid((unsigned)a.W, (unsigned)((a.Sc + a.spw - 1) / a.spw));
-    hipLaunchKernelGGL((k_form_mfma<T, NS>), grid, dim3(64), lds, st, a.n, a.eta, a.Xa, a.Ca, a.S_total, a.s0,
-                       a.Sc, a.spw, a.Sb, a.Pb, a.fbc, a.fbl, a.fb_cap, a.wst);
+    if (a.mix)
+        hipLaunchKernelGGL((k_form_mfma<T, NS, true>), grid, dim3(64), lds, st, a.n, a.eta, a.Xa, a.Ca, a.S_total,
+                           a.s0, a.Sc, a.spw, a.Sb, a.Pb, a.fbc, a.fbl, a.fb_cap, a.wst);
+    else
+        hipLaunchKernelGGL((k_form_mfma<T, NS, false>), grid, dim3(64), lds, st, a.n, a.eta, a.Xa, a.Ca, a.S_total,
+                           a.s0, a.Sc, a.spw, a.Sb, a.Pb, a.fbc, a.fbl, a.fb_cap, a.wst);
     return hipGetLastError();
 }
 
@@ -395,8 +407,8 @@ hipError_t launch_form(const FormArgs &a, hipStream_t st) {
 
 // Fused pair kernel: T = ceil(2n/16), NE = ne.  The grid's y extent is
 // limited to 65535, so long shadow ranges go in several launches.
-template <int T, int NE>
-hipError_t launch_pair_tn(int n, int eta, const double2 *Xa, const double2 *Ca, int64_t W, int64_t S,
+template <int T, int NE, bool MIX>
+hipError_t launch_pair_tn(int n, int eta, const void *Xa, const void *Ca, int64_t W, int64_t S,
                           const RedTab &rt, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap,
                           int32_t *wst, hipStream_t st) {
     constexpr int NB = 64 / (NE + 1);
@@ -405,36 +417,39 @@ hipError_t launch_pair_tn(int n, int eta, const double2 *Xa, const double2 *Ca, 
     const int64_t ny = (S + spw - 1) / spw;
     for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
         const int64_t gy = (ny - y0) < 65535 ? (ny - y0) : 65535;
-        hipLaunchKernelGGL((k_pair<T, NE>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds, st, n, eta, Xa, Ca, S,
+        hipLaunchKernelGGL((k_pair<T, NE, MIX>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds, st, n, eta, Xa, Ca, S,
                            y0, spw, rt, pairs, fbc, fbl, fb_cap, wst);
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }
     return hipSuccess;
 }
 
-template <int T>
-hipError_t launch_pair_t(int n, int eta, const double2 *Xa, const double2 *Ca, int64_t W, int64_t S,
+template <int T, bool MIX>
+hipError_t launch_pair_t(int n, int eta, const void *Xa, const void *Ca, int64_t W, int64_t S,
                          const RedTab &rt, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
                          hipStream_t st) {
     switch (n - eta) {
-        case 2: return launch_pair_tn<T, 2>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 4: return launch_pair_tn<T, 4>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 6: return launch_pair_tn<T, 6>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 8: return launch_pair_tn<T, 8>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 2: return launch_pair_tn<T, 2, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 4: return launch_pair_tn<T, 4, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 6: return launch_pair_tn<T, 6, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 8: return launch_pair_tn<T, 8, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_pair(int n, int eta, const double2 *Xa, const double2 *Ca, int64_t W, int64_t S,
+hipError_t launch_pair(int n, int eta, bool mix, const void *Xa, const void *Ca, int64_t W, int64_t S,
                        const NodeTab &tab, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
                        hipStream_t st) {
     RedTab rt;
     std::memset(&rt, 0, sizeof(rt));
     for (int j = 0; j < tab.Ke; ++j) { rt.e[j] = tab.e[j]; rt.v[j] = tab.v[j]; }
-    switch (so_tiles(n)) {
-        case 1: return launch_pair_t<1>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 2: return launch_pair_t<2>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 3: return launch_pair_t<3>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+    switch (so_tiles(n) * 2 + (mix ? 1 : 0)) {
+        case 2: return launch_pair_t<1, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 3: return launch_pair_t<1, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 4: return launch_pair_t<2, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 5: return launch_pair_t<2, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 6: return launch_pair_t<3, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 7: return launch_pair_t<3, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -510,8 +525,11 @@ struct ProbPlan {
     const double *Q;
     const uint64_t *bits;
     double2 *overlap, *pairs, *Sb, *Pb, *fbB;
-    const double2 *Xa, *Ca;
+    const double2 *Xa, *Ca;   // FP64 operands (full-size path; formation unless mixed)
     double *Xw, *Cw;
+    bool mix;                 // mixed precision: single-precision formation operands
+    float *X32, *C32;
+    const void *Xf, *Cf;      // the formation's operands
     int32_t *wst;
     uint32_t *fbc;
     int64_t *fbl;
@@ -523,7 +541,6 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
     int K;
     if (!params_ok(p, &K) || !phi || !Q || !bits || !overlap || W < 1 || S < 1) return SO_ERR_ARG;
     if (!so_supported(p->n, p->eta)) return SO_ERR_UNSUPPORTED;
-    if (p->precision != SO_PREC_FP64) return SO_ERR_UNSUPPORTED;
     if (W > (int64_t)INT32_MAX || S > (int64_t)INT32_MAX) return SO_ERR_ARG;
     P->n = p->n;
     P->eta = p->eta;
@@ -533,7 +550,8 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
     P->K = K;
     P->W = W;
     P->S = S;
-    P->L = make_layout(p->n, p->eta, W, S);
+    P->mix = p->precision == SO_PREC_MIXED;
+    P->L = make_layout(p->n, p->eta, W, S, false, P->mix);
     if (!ws || bytes < P->L.total) return SO_ERR_WORKSPACE;
     build_nodetab(p, K, &P->tab);
     P->phi = reinterpret_cast<const double2 *>(phi);
@@ -544,6 +562,10 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
     P->Cw = reinterpret_cast<double *>(ws + P->L.off_C);
     P->Xa = reinterpret_cast<const double2 *>(P->Xw);
     P->Ca = reinterpret_cast<const double2 *>(P->Cw);
+    P->X32 = reinterpret_cast<float *>(ws + P->L.off_X32);
+    P->C32 = reinterpret_cast<float *>(ws + P->L.off_C32);
+    P->Xf = P->mix ? static_cast<const void *>(P->X32) : static_cast<const void *>(P->Xa);
+    P->Cf = P->mix ? static_cast<const void *>(P->C32) : static_cast<const void *>(P->Ca);
     P->Sb = reinterpret_cast<double2 *>(ws + P->L.off_S);
     P->Pb = reinterpret_cast<double2 *>(ws + P->L.off_P);
     P->pairs = pair_out ? reinterpret_cast<double2 *>(pair_out) : reinterpret_cast<double2 *>(ws + P->L.off_pairs);
@@ -561,13 +583,24 @@ hipError_t enqueue_prep(const ProbPlan &P, hipStream_t st) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)P.S), dim3(256), (size_t)P.d * P.d * sizeof(double), st, P.n,
                        P.Q, P.bits, P.Cw);
+    e = hipGetLastError();
+    if (e != hipSuccess || !P.mix) return e;
+    // single-precision formation operands (the FP64 ones stay for the full-size path)
+    const int T = so_tiles(P.n), DP = 16 * T;
+    const unsigned bx = (unsigned)((DP * DP + 255) / 256);
+    hipLaunchKernelGGL(k_to_f32, dim3(bx, (unsigned)(P.W < 65535 ? P.W : 65535)), dim3(256), 0, st, T, 0, P.W,
+                       P.Xw, P.X32);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_to_f32, dim3(bx, (unsigned)(P.S < 65535 ? P.S : 65535)), dim3(256), 0, st, T, 1, P.S,
+                       P.Cw, P.C32);
     return hipGetLastError();
 }
 
 // the two-kernel path (n - eta odd, 0 or above 8): formation + Schur
 // complement per chunk of shadows, then the node Pfaffians of the chunk
 hipError_t enqueue_two_kernel(const ProbPlan &P, hipStream_t st) {
-    FormArgs fa{P.n, P.eta, P.Xa, P.Ca, P.S, 0, 0, kFormShadowsPerWave, P.Sb, P.Pb, P.fbc, P.fbl, P.L.fb_cap,
+    FormArgs fa{P.n, P.eta, P.mix, P.Xf, P.Cf, P.S, 0, 0, kFormShadowsPerWave, P.Sb, P.Pb, P.fbc, P.fbl, P.L.fb_cap,
                 P.wst, P.W};
     for (int64_t s0 = 0; s0 < P.S; s0 += P.L.Sc) {
         const int Sc = (int)((P.S - s0) < P.L.Sc ? (P.S - s0) : P.L.Sc);
@@ -628,19 +661,21 @@ double pair_cost(int n, int eta) {
     return 16.0 * n * n * m + 8.0 * n * m * m + 8.0 * (n * n * (n + 2 * ne)) + (ne + 1) * 8.0 * ne * ne * ne;
 }
 
-template <int T, int NE>
+template <int T, int NE, bool MIX>
 hipError_t launch_persistent_tn(const PairJobs &J, int grid, size_t lds, uint32_t *counter, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pair_persistent<T, NE>), dim3((unsigned)grid), dim3(64), lds, st, J, counter);
+    hipLaunchKernelGGL((k_pair_persistent<T, NE, MIX>), dim3((unsigned)grid), dim3(64), lds, st, J, counter);
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(int T, int NE, const PairJobs &J, int grid, size_t lds, uint32_t *counter,
+hipError_t launch_persistent(int T, int NE, bool mix, const PairJobs &J, int grid, size_t lds, uint32_t *counter,
                              hipStream_t st) {
-    switch (T * 16 + NE) {
-#define SO_PCASE(TT, NN) case TT * 16 + NN: return launch_persistent_tn<TT, NN>(J, grid, lds, counter, st);
+    switch (T * 32 + NE * 2 + (mix ? 1 : 0)) {
+#define SO_PCASE(TT, NN)                                                                                  \
+    case TT * 32 + NN * 2: return launch_persistent_tn<TT, NN, false>(J, grid, lds, counter, st); \
+    case TT * 32 + NN * 2 + 1: return launch_persistent_tn<TT, NN, true>(J, grid, lds, counter, st);
         SO_PCASE(1, 2) SO_PCASE(1, 4) SO_PCASE(1, 6) SO_PCASE(1, 8)
         SO_PCASE(2, 2) SO_PCASE(2, 4) SO_PCASE(2, 6) SO_PCASE(2, 8)
         SO_PCASE(3, 2) SO_PCASE(3, 4) SO_PCASE(3, 6) SO_PCASE(3, 8)
@@ -660,8 +695,8 @@ PairJobs make_jobs(const ProbPlan *plans, const so_problem *probs, const int *ix
         const ProbPlan &P = plans[ix[k]];
         PairJob &jb = J.job[k];
         const int64_t S = (S_limit > 0 && S_limit < P.S) ? S_limit : P.S;
-        jb.Xa = P.Xa;
-        jb.Ca = P.Ca;
+        jb.Xa = P.Xf;
+        jb.Ca = P.Cf;
         jb.pairs = P.pairs;
         jb.fb_count = P.fbc;
         jb.fb_list = P.fbl;
@@ -698,7 +733,7 @@ hipError_t launch_jobs(const ProbPlan *plans, const so_problem *probs, const int
     for (int k = 0; k < nj; ++k) pairs += plans[ix[k]].W * plans[ix[k]].S;
     hipEvent_t ea = nullptr;
     hipError_t e = prof_begin(st, &ea);
-    if (e == hipSuccess) e = launch_persistent(T, NE, J, (int)grid, lds, counter, st);
+    if (e == hipSuccess) e = launch_persistent(T, NE, P0.mix, J, (int)grid, lds, counter, st);
     if (e == hipSuccess) e = prof_end(st, ea, PROF_PAIR, pairs);
     return e;
 }
@@ -708,7 +743,8 @@ size_t batch_layout(const so_problem *probs, int n_probs, size_t *offs) {
     for (int k = 0; k < n_probs; ++k) {
         offs[k] = o;
         o = align_up(o + make_layout(probs[k].params.n, probs[k].params.eta, probs[k].n_walkers,
-                                     probs[k].n_shadows).total);
+                                     probs[k].n_shadows, false, probs[k].params.precision == SO_PREC_MIXED)
+                             .total);
     }
     offs[n_probs] = o;                                   // launch counters
     return align_up(o + (size_t)kBatchMax * sizeof(uint32_t));
@@ -739,7 +775,7 @@ so_status so_workspace_size(const so_params *p, int64_t n_walkers, int64_t n_sha
     int K;
     if (!bytes || !params_ok(p, &K) || n_walkers < 1 || n_shadows < 1) return SO_ERR_ARG;
     if (!so_supported(p->n, p->eta)) return SO_ERR_UNSUPPORTED;
-    *bytes = make_layout(p->n, p->eta, n_walkers, n_shadows, with_grad != 0).total;
+    *bytes = make_layout(p->n, p->eta, n_walkers, n_shadows, with_grad != 0, p->precision == SO_PREC_MIXED).total;
     return SO_OK;
 }
 
@@ -768,7 +804,7 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
     if (fused_ok(P.n, P.eta)) {
         hipEvent_t ea = nullptr;
         if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
-        if (launch_pair(P.n, P.eta, P.Xa, P.Ca, P.W, P.S, P.tab, P.pairs, P.fbc, P.fbl, P.L.fb_cap, P.wst, st) !=
+        if (launch_pair(P.n, P.eta, P.mix, P.Xf, P.Cf, P.W, P.S, P.tab, P.pairs, P.fbc, P.fbl, P.L.fb_cap, P.wst, st) !=
             hipSuccess)
             return SO_ERR_HIP;
         if (prof_end(st, ea, PROF_PAIR, P.W * P.S) != hipSuccess) return SO_ERR_HIP;
@@ -905,7 +941,9 @@ so_status shadow_overlap_batched(const so_problem *probs, int n_probs, void *wor
         int ix[SO_JOBS_PER_LAUNCH], nj = 0;
         for (int b = a; b < nf && nj < SO_JOBS_PER_LAUNCH; ++b) {
             const int kb = order[b];
-            if (used[b] || so_tiles(plans[kb].n) != T || plans[kb].n - plans[kb].eta != NE) continue;
+            if (used[b] || so_tiles(plans[kb].n) != T || plans[kb].n - plans[kb].eta != NE ||
+                plans[kb].mix != plans[ka].mix)
+                continue;
             used[b] = true;
             ix[nj++] = kb;
         }

@@ -2,7 +2,7 @@
 // problems (several walker sets, shadow sets and orbital counts in one call).
 //
 // A launch serves up to SO_JOBS_PER_LAUNCH problems of one kernel class
-// (same MFMA tile count T and same ne = n - eta).  Their work items
+// (same MFMA tile count T, same ne = n - eta and same formation precision).  Their work items
 // (walker, range of shadows) are numbered problem by problem, the problem
 // with the costliest items first (longest-processing-time order), walkers
 // fastest within a shadow range so that concurrent waves share C'_s in L2.
@@ -16,7 +16,7 @@
 #define SO_JOBS_PER_LAUNCH 2
 
 struct PairJob {
-    const double2 *Xa, *Ca;
+    const void *Xa, *Ca;   // formation operands (FP64 or single precision)
     double2 *pairs;
     uint32_t *fb_count;
     int64_t *fb_list;
@@ -37,7 +37,7 @@ __global__ void k_zero_u32(uint32_t *counter) {
     if (threadIdx.x == 0) counter[0] = 0u;
 }
 
-template <int T, int NE>
+template <int T, int NE, bool MIX>
 __global__ __launch_bounds__(64) void k_pair_persistent(PairJobs J, uint32_t *__restrict__ counter) {
     for (;;) {
         uint32_t it = 0u;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(64) void k_pair_persistent(PairJobs J, uint32_t *__
         const int w = (int)(local - y * jb.W);
         const int64_t sb0 = y * jb.spw;
         const int64_t sb1 = min(jb.S, sb0 + jb.spw);
-        pair_range<T, NE>(jb.n, jb.eta, jb.Xa, jb.Ca, jb.S, tb, jb.pairs, jb.fb_count, jb.fb_list, jb.fb_cap,
+        pair_range<T, NE, MIX>(jb.n, jb.eta, jb.Xa, jb.Ca, jb.S, tb, jb.pairs, jb.fb_count, jb.fb_list, jb.fb_cap,
                           jb.wstat, w, sb0, sb1);
     }
 }

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 // complex helpers on double2 (x = re, y = im)
@@ -158,6 +159,7 @@ struct RedTab {
 // coalesced 1 KiB access:
 //   flat(I, kk, l) = ((I (KK/2) + kk/2) 64 + l) 2 + kk % 2,  KK = 4 T.
 typedef double so_d4 __attribute__((ext_vector_type(4)));
+typedef float so_f4 __attribute__((ext_vector_type(4)));
 
 __host__ __device__ inline int so_tiles(int n) { return (2 * n + 15) / 16; }
 
@@ -171,3 +173,115 @@ __device__ __forceinline__ void ao_rowcol(int f, int T, int &row, int &col) {
     row = 16 * I + (l & 15);
     col = 4 * (2 * kh + c) + (l >> 4);
 }
+
+// ---- single-precision operands (mixed-precision formation) -------------------
+// v_mfma_f32_16x16x4f32 reads its A and B operands like the FP64 instruction
+// but leaves register r of the accumulator holding D[4 (l/16) + r][l%16]
+// (rows 4 apart in the FP64 form are adjacent here).  The same operands in
+// single precision are stored four k-steps per lane as one float4:
+//   flat32(I, kk, l) = ((I T + kk/4) 64 + l) 4 + kk % 4.
+__device__ __forceinline__ int ao32_index(int row, int col, int T) {
+    const int I = row >> 4, kk = col >> 2, l = (row & 15) | ((col & 3) << 4);
+    return ((I * T + (kk >> 2)) * 64 + l) * 4 + (kk & 3);
+}
+__device__ __forceinline__ void ao32_rowcol(int f, int T, int &row, int &col) {
+    const int c = f & 3, l = (f >> 2) & 63, rest = f >> 8;
+    const int kq = rest % T, I = rest / T;
+    row = 16 * I + (l & 15);
+    col = 16 * kq + 4 * c + (l >> 4);
+}
+// Row order of the single-precision C': within each block of 16 rows, row
+// 4 g + r is stored at position 4 r + g.  With C' so permuted, U = C' Xall^T
+// comes out of the single-precision accumulator in the FP64 register order,
+// so the second product P = Xall U consumes it exactly as in FP64.
+__host__ __device__ __forceinline__ int sig16(int row) {
+    return (row & ~15) | ((row & 3) << 2) | ((row >> 2) & 3);
+}
+
+// ---- the formation products ---------------------------------------------------
+// This lane's operand registers of one d x d matrix: a[I][kk] = element of
+// row tile I at k-step kk (the A order above).
+template <int T>
+__device__ __forceinline__ void load_ops(const double2 *__restrict__ M, double (&a)[T][4 * T], int l) {
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int h = 0; h < 2 * T; ++h) {
+            const double2 v = M[(I * 2 * T + h) * 64 + l];
+            a[I][2 * h] = v.x;
+            a[I][2 * h + 1] = v.y;
+        }
+}
+template <int T>
+__device__ __forceinline__ void load_ops(const float4 *__restrict__ M, float (&a)[T][4 * T], int l) {
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int q = 0; q < T; ++q) {
+            const float4 v = M[(I * T + q) * 64 + l];
+            a[I][4 * q] = v.x;
+            a[I][4 * q + 1] = v.y;
+            a[I][4 * q + 2] = v.z;
+            a[I][4 * q + 3] = v.w;
+        }
+}
+// U = C' Xall^T, then the tiles I <= J of P = Xall U.  The accumulator of U's
+// tile (I, J), register r, is the B operand of P at k-step 4 I + r (in single
+// precision because C' is stored with its rows in the order sig16).
+template <int T>
+__device__ __forceinline__ void form_p(const double (&xa)[T][4 * T], const double (&ca)[T][4 * T],
+                                       so_d4 (&P)[T][T]) {
+    so_d4 U[T][T];
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J) U[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4 * T; ++kk)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = 0; J < T; ++J)
+                U[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[I][kk], xa[J][kk], U[I][J], 0, 0, 0);
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J) P[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4 * T; ++kk)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = I; J < T; ++J)
+                P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0, 0, 0);
+}
+template <int T>
+__device__ __forceinline__ void form_p(const float (&xa)[T][4 * T], const float (&ca)[T][4 * T], so_f4 (&P)[T][T]) {
+    so_f4 U[T][T];
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J) U[I][J] = so_f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < 4 * T; ++kk)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = 0; J < T; ++J)
+                U[I][J] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[I][kk], xa[J][kk], U[I][J], 0, 0, 0);
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J) P[I][J] = so_f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kk = 0; kk < 4 * T; ++kk)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = I; J < T; ++J)
+                P[I][J] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0, 0, 0);
+}
+// row of P held by register r of a tile's accumulator in lane l (the column
+// is 16 J + l % 16)
+__device__ __forceinline__ int p_row(const so_d4 &, int I, int r, int l) { return 16 * I + 4 * r + (l >> 4); }
+__device__ __forceinline__ int p_row(const so_f4 &, int I, int r, int l) { return 16 * I + 4 * (l >> 4) + r; }

@@ -16,9 +16,11 @@
 // Formation.  The empty rows of X are real, so with the real d x d matrix
 // Xall = [Re X_O; Im X_O; X_U] (so_prep.h) the pair needs two real products,
 //   U = C' Xall^T,   P = Xall U = Xall C' Xall^T,
-// on v_mfma_f64_16x16x4f64 (so_common.h for the operand order).  The
-// accumulator of U's tile (I, J), register r, is exactly the B operand of
-// P at k-step 4 I + r, so U never leaves the registers.  P is antisymmetric;
+// on v_mfma_f64_16x16x4f64, or on v_mfma_f32_16x16x4f32 with single-precision
+// operands and accumulation in the mixed-precision mode (so_common.h for the
+// operand orders).  The accumulator of U's tile (I, J), register r, is
+// exactly the B operand of P at k-step 4 I + r, so U never leaves the
+// registers.  P is antisymmetric;
 // only its tiles I <= J are formed.  Then, with i, j < eta and t, u < 2ne,
 //   B_OO[i][j] = P[i][j] - P[eta+i][eta+j] + i (P[i][eta+j] + P[eta+i][j])
 //   B_OU[i][t] = P[i][2eta+t] + i P[eta+i][2eta+t]
@@ -51,15 +53,19 @@ __host__ __device__ inline size_t form_lds_bytes_t(int T, int eta, int m) {
 // grid (W, ceil(Sc / spw)), one wave per block: walker blockIdx.x, shadows
 // s0 + [blockIdx.y spw, ...) of the chunk.  NS >= ceil((2ne)^2 / 64) entries
 // of S per lane: lane l holds S[e / M2][e % M2], e = l + 64 q.
-template <int T, int NS>
-__global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const double2 *__restrict__ Xa,
-                                                  const double2 *__restrict__ Ca, int64_t S_total, int64_t s0,
+template <int T, int NS, bool MIX>
+__global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const void *__restrict__ Xa,
+                                                  const void *__restrict__ Ca, int64_t S_total, int64_t s0,
                                                   int Sc, int spw, double2 *__restrict__ Sbuf,
                                                   double2 *__restrict__ Pbuf, uint32_t *__restrict__ fb_count,
                                                   int64_t *__restrict__ fb_list, int64_t fb_cap,
                                                   int32_t *__restrict__ wstat) {
-    constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
-    constexpr int MAT2 = DP * DP / 2;   // double2 per stored matrix
+    constexpr int KK = 4 * T, DP = 16 * T, LDP = DP + 1;
+    // operands in FP64 (MIX = false) or single precision (MIX = true)
+    using Op = typename std::conditional<MIX, float, double>::type;
+    using Vec = typename std::conditional<MIX, float4, double2>::type;
+    using Acc = typename std::conditional<MIX, so_f4, so_d4>::type;
+    constexpr int MATV = DP * DP * (int)sizeof(Op) / (int)sizeof(Vec);   // vectors per stored matrix
     extern __shared__ double lds[];
     double *Pl = lds;
     double2 *Rl = reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) +
@@ -68,18 +74,8 @@ __global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const double2 
     const int w = blockIdx.x;
     const int m = 2 * n - eta, ne = n - eta, M2 = 2 * ne;
 
-    double xa[T][KK];
-    {
-        const double2 *Xw = Xa + (size_t)w * MAT2;
-#pragma unroll
-        for (int I = 0; I < T; ++I)
-#pragma unroll
-            for (int h = 0; h < KH; ++h) {
-                const double2 v = Xw[(I * KH + h) * 64 + l];
-                xa[I][2 * h] = v.x;
-                xa[I][2 * h + 1] = v.y;
-            }
-    }
+    Op xa[T][KK];
+    load_ops<T>(static_cast<const Vec *>(Xa) + (size_t)w * MATV, xa, l);
     // P[a][b] for any a, b < DP from the stored tiles I <= J
     auto Pget = [&](int a, int b) -> double {
         return ((a >> 4) <= (b >> 4)) ? Pl[a * LDP + b] : -Pl[b * LDP + a];
@@ -88,42 +84,10 @@ __global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const double2 
     const int sl0 = blockIdx.y * spw;
     const int sl1 = min(Sc, sl0 + spw);
     for (int sl = sl0; sl < sl1; ++sl) {
-        const double2 *Cs = Ca + (size_t)(s0 + sl) * MAT2;
-        double ca[T][KK];
-#pragma unroll
-        for (int I = 0; I < T; ++I)
-#pragma unroll
-            for (int h = 0; h < KH; ++h) {
-                const double2 v = Cs[(I * KH + h) * 64 + l];
-                ca[I][2 * h] = v.x;
-                ca[I][2 * h + 1] = v.y;
-            }
-        // U = C' Xall^T
-        so_d4 U[T][T];
-#pragma unroll
-        for (int I = 0; I < T; ++I)
-#pragma unroll
-            for (int J = 0; J < T; ++J) U[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-            for (int I = 0; I < T; ++I)
-#pragma unroll
-                for (int J = 0; J < T; ++J)
-                    U[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[I][kk], xa[J][kk], U[I][J], 0, 0, 0);
-        // P = Xall U, tiles I <= J
-        so_d4 P[T][T];
-#pragma unroll
-        for (int I = 0; I < T; ++I)
-#pragma unroll
-            for (int J = 0; J < T; ++J) P[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-            for (int I = 0; I < T; ++I)
-#pragma unroll
-                for (int J = I; J < T; ++J)
-                    P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0, 0, 0);
+        Op ca[T][KK];
+        load_ops<T>(static_cast<const Vec *>(Ca) + (size_t)(s0 + sl) * MATV, ca, l);
+        Acc P[T][T];
+        form_p<T>(xa, ca, P);
 
         __syncthreads();   // the previous pair's reads of Pl and Rl are done
 #pragma unroll
@@ -131,7 +95,8 @@ __global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const double2 
 #pragma unroll
             for (int J = I; J < T; ++J)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Pl[(16 * I + 4 * r + (l >> 4)) * LDP + 16 * J + (l & 15)] = P[I][J][r];
+                for (int r = 0; r < 4; ++r)
+                    Pl[p_row(P[I][J], I, r, l) * LDP + 16 * J + (l & 15)] = (double)P[I][J][r];
         __syncthreads();
 
         // R = [B_OO | B_OU] and S = B_UU

@@ -95,49 +95,26 @@ __device__ __forceinline__ double2 pf_lane_from(double2 (&A)[N][N]) {
 // Pl is (DP + 1) x LDP doubles, row-major; both triangles of P are written and
 // row and column DP are zeroed (an empty orbital's missing imaginary part
 // points there).  Ends with a barrier.
-template <int T>
-__device__ __forceinline__ void pair_formation(const double2 *__restrict__ Xw, const double2 *__restrict__ Cs,
+//
+// MIX = false: FP64 operands (double2 pairs in A order) on
+// v_mfma_f64_16x16x4f64.  MIX = true: single-precision operands (float4
+// quads, C' rows in the order sig16) on v_mfma_f32_16x16x4f32 with
+// single-precision accumulation; P is widened to FP64 when it is stored and
+// everything after the formation runs in FP64.
+template <int T, bool MIX>
+__device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, const void *__restrict__ Cv,
                                                double *Pl, int l) {
-    constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
-    // operands: the walker's Xall (re-read from L2 per pair: keeping it
-    // live through the elimination and node stages costs occupancy) and C'_s
-    double xa[T][KK], ca[T][KK];
-#pragma unroll
-    for (int I = 0; I < T; ++I)
-#pragma unroll
-        for (int h = 0; h < KH; ++h) {
-            const double2 v = Xw[(I * KH + h) * 64 + l];
-            const double2 c = Cs[(I * KH + h) * 64 + l];
-            xa[I][2 * h] = v.x;
-            xa[I][2 * h + 1] = v.y;
-            ca[I][2 * h] = c.x;
-            ca[I][2 * h + 1] = c.y;
-        }
-    so_d4 U[T][T];
-#pragma unroll
-    for (int I = 0; I < T; ++I)
-#pragma unroll
-        for (int J = 0; J < T; ++J) U[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-        for (int I = 0; I < T; ++I)
-#pragma unroll
-            for (int J = 0; J < T; ++J)
-                U[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[I][kk], xa[J][kk], U[I][J], 0, 0, 0);
-    so_d4 P[T][T];
-#pragma unroll
-    for (int I = 0; I < T; ++I)
-#pragma unroll
-        for (int J = 0; J < T; ++J) P[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int kk = 0; kk < KK; ++kk)
-#pragma unroll
-        for (int I = 0; I < T; ++I)
-#pragma unroll
-            for (int J = I; J < T; ++J)
-                P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0,
-                                                               0, 0);
+    constexpr int KK = 4 * T, DP = 16 * T, LDP = DP + 1;
+    using Op = typename std::conditional<MIX, float, double>::type;
+    using Vec = typename std::conditional<MIX, float4, double2>::type;
+    using Acc = typename std::conditional<MIX, so_f4, so_d4>::type;
+    // operands: the walker's Xall (re-read from L2 per pair: keeping it live
+    // through the elimination and node stages costs occupancy) and C'_s
+    Op xa[T][KK], ca[T][KK];
+    load_ops<T>(static_cast<const Vec *>(Xv), xa, l);
+    load_ops<T>(static_cast<const Vec *>(Cv), ca, l);
+    Acc P[T][T];
+    form_p<T>(xa, ca, P);
     __syncthreads();   // region A is free
 #pragma unroll
     for (int I = 0; I < T; ++I)
@@ -145,9 +122,10 @@ __device__ __forceinline__ void pair_formation(const double2 *__restrict__ Xw, c
         for (int J = I; J < T; ++J)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int a = 16 * I + 4 * r + (l >> 4), bcol = 16 * J + (l & 15);
-                Pl[a * LDP + bcol] = P[I][J][r];
-                if (J > I) Pl[bcol * LDP + a] = -P[I][J][r];   // P is antisymmetric
+                const int a = p_row(P[I][J], I, r, l), bcol = 16 * J + (l & 15);
+                const double v = (double)P[I][J][r];
+                Pl[a * LDP + bcol] = v;
+                if (J > I) Pl[bcol * LDP + a] = -v;   // P is antisymmetric
             }
     // row and column DP are zero (R overlays them, so they are rewritten per pair)
     for (int c = l; c <= DP; c += 64) {
@@ -155,7 +133,6 @@ __device__ __forceinline__ void pair_formation(const double2 *__restrict__ Xw, c
         Pl[c * LDP + DP] = 0.0;
     }
     __syncthreads();
-
 }
 
 // ---- pairwise elimination of K in the bordered rows ---------------------------
@@ -261,15 +238,17 @@ __host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
 
 // One walker w over the shadows [sb0, sb1): formation, elimination, node
 // Pfaffians and the pair values pairs[w S_total + s].  One wave; the LDS
-// layout is pair_lds_bytes(T, n, NE).
-template <int T, int NE>
-__device__ __forceinline__ void pair_range(int n, int eta, const double2 *__restrict__ Xa,
-                                           const double2 *__restrict__ Ca, int64_t S_total, const RedTab &tab,
+// layout is pair_lds_bytes(T, n, NE).  Xa and Ca hold the walker and shadow
+// matrices in FP64 (MIX = false) or single precision (MIX = true), DP x DP
+// elements each, in the formation's operand order.
+template <int T, int NE, bool MIX>
+__device__ __forceinline__ void pair_range(int n, int eta, const void *__restrict__ Xa,
+                                           const void *__restrict__ Ca, int64_t S_total, const RedTab &tab,
                                            double2 *__restrict__ pairs, uint32_t *__restrict__ fb_count,
                                            int64_t *__restrict__ fb_list, int64_t fb_cap,
                                            int32_t *__restrict__ wstat, int w, int64_t sb0, int64_t sb1) {
     constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
-    constexpr int MAT2 = DP * DP / 2;
+    constexpr size_t MATB = (size_t)DP * DP * (MIX ? sizeof(float) : sizeof(double));   // bytes per matrix
     constexpr int KE = NE + 1;
     constexpr int NB = 64 / KE;
     constexpr int NT = NE * (NE - 1) / 2;         // upper entries of one NE x NE matrix
@@ -306,7 +285,7 @@ __device__ __forceinline__ void pair_range(int n, int eta, const double2 *__rest
         tb[q] = a + 1 + e;
     }
 
-    const double2 *Xw = Xa + (size_t)w * MAT2;
+    const char *Xw = static_cast<const char *>(Xa) + (size_t)w * MATB;
     auto Pget = [&](int a, int b) -> double { return Pl[a * LDP + b]; };
     // Xall rows of the real and imaginary parts of stored row i; an empty
     // orbital's row is real, and its imaginary part points at the zero row DP
@@ -322,7 +301,7 @@ __device__ __forceinline__ void pair_range(int n, int eta, const double2 *__rest
         for (int b = 0; b < nb; ++b) {
             const int64_t s = bs + b;
             // ---------------- formation: P = Xall C' Xall^T
-            pair_formation<T>(Xw, Ca + (size_t)s * MAT2, Pl, l);
+            pair_formation<T, MIX>(Xw, static_cast<const char *>(Ca) + (size_t)s * MATB, Pl, l);
 
             // ---------------- R = rows K of Z, trailing T = [[B_LL, 0], [0, 0]]
             constexpr int RPL = (8 * T * (8 * T + NE) + 63) / 64;   // B entries of R per lane (n <= 8 T)
@@ -444,14 +423,14 @@ __device__ __forceinline__ void pair_range(int n, int eta, const double2 *__rest
 
 // grid (W, ceil(S_total / spw)) from shadow group sy0, one wave per block;
 // spw is a multiple of 64 / (NE + 1).
-template <int T, int NE>
-__global__ __launch_bounds__(64) void k_pair(int n, int eta, const double2 *__restrict__ Xa,
-                                             const double2 *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
+template <int T, int NE, bool MIX>
+__global__ __launch_bounds__(64) void k_pair(int n, int eta, const void *__restrict__ Xa,
+                                             const void *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
                                              RedTab tab, double2 *__restrict__ pairs,
                                              uint32_t *__restrict__ fb_count, int64_t *__restrict__ fb_list,
                                              int64_t fb_cap, int32_t *__restrict__ wstat) {
     const int64_t sb0 = (sy0 + blockIdx.y) * (int64_t)spw;
     const int64_t sb1 = min(S_total, sb0 + spw);
-    pair_range<T, NE>(n, eta, Xa, Ca, S_total, tab, pairs, fb_count, fb_list, fb_cap, wstat, (int)blockIdx.x, sb0,
+    pair_range<T, NE, MIX>(n, eta, Xa, Ca, S_total, tab, pairs, fb_count, fb_list, fb_cap, wstat, (int)blockIdx.x, sb0,
                       sb1);
 }

@@ -146,3 +146,25 @@ __global__ __launch_bounds__(256) void k_shadow_prep(int n, const double *__rest
         Cg[f] = acc;
     }
 }
+
+// --------------------------------------------------------------------------
+// k_to_f32: single-precision copies of the walker matrices (sig = 0) or the
+// shadow covariances (sig = 1, rows in the order sig16) for the
+// mixed-precision formation, from the FP64 matrices in A order.  count
+// matrices of DP x DP; grid (ceil(DP^2 / 256), up to 65535), the y blocks
+// striding over the matrices.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_to_f32(int T, int sig, int64_t count, const double *__restrict__ A64,
+                                                float *__restrict__ A32) {
+    const int DP = 16 * T;
+    const int f = blockIdx.x * 256 + threadIdx.x;
+    if (f >= DP * DP) return;
+    int row, col;
+    ao32_rowcol(f, T, row, col);
+    if (sig) row = sig16(row);
+    const int src = ao_index(row, col, T);
+    for (int64_t g = blockIdx.y; g < count; g += gridDim.y) {
+        const size_t base = (size_t)g * DP * DP;
+        A32[base + f] = (float)A64[base + src];
+    }
+}
