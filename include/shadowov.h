@@ -154,7 +154,7 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
                               void *workspace, size_t workspace_bytes, void *stream);
 
 /* One problem of a batch: the arguments of shadow_overlap, plus two tuning
- * knobs for problems on the fused pair kernel (n - eta even, 2..8):
+ * knobs for problems on the fused pair kernel (n - eta even, 2..12):
  *   shadows_per_item  shadows per work item of the persistent kernel
  *                     (rounded up to a multiple of the node batch 64/(ne+1));
  *                     0 = library default

@@ -12,7 +12,7 @@
 // Kernels, all on the caller's stream, per call:
 //   k_walker_prep   X_w from Phi_w (so_prep.h)
 //   k_shadow_prep   C'_s = Q_s^T C_b Q_s (so_prep.h)
-//   when ne = n - eta is even and 2 <= ne <= 8:
+//   when ne = n - eta is even and 2 <= ne <= 12:
 //     k_pair        formation, elimination of K = O u U1 down to the pencil
 //                   M0 + c M1 + c^2 M2, node Pfaffians, weighted sum (so_pair.h)
 //   otherwise, per chunk of shadows:
@@ -295,10 +295,11 @@ struct Layout {
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// the fused pair kernel covers an even ne = n - eta with 2 <= ne <= 8
+// the fused pair kernel covers an even ne = n - eta with 2 <= ne <= 12
+// (node Pfaffians per lane up to ne = 8, per 16-lane row above)
 bool fused_ok(int n, int eta) {
     const int ne = n - eta;
-    return ne >= 2 && ne <= 8 && (ne % 2) == 0;
+    return ne >= 2 && ne <= 12 && (ne % 2) == 0;
 }
 
 // shadow ranges per walker for k_grad_pair: enough waves to fill the chip
@@ -309,7 +310,7 @@ int grad_ranges(int64_t W, int64_t S) {
     return (int)gy;
 }
 
-bool grad_ok(int n, int eta) { return fused_ok(n, eta) && so_tiles(n) <= 2; }
+bool grad_ok(int n, int eta) { return fused_ok(n, eta) && n - eta <= 8 && so_tiles(n) <= 2; }
 
 Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false, bool mixed = false) {
     Layout L{};
@@ -433,8 +434,16 @@ hipError_t launch_pair_t(int n, int eta, const void *Xa, const void *Ca, int64_t
         case 4: return launch_pair_tn<T, 4, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
         case 6: return launch_pair_tn<T, 6, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
         case 8: return launch_pair_tn<T, 8, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        default: return hipErrorInvalidValue;
+        default: break;
     }
+    if constexpr (T >= 2) {   // ne > 8 needs n > 8
+        switch (n - eta) {
+            case 10: return launch_pair_tn<T, 10, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+            case 12: return launch_pair_tn<T, 12, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pair(int n, int eta, bool mix, const void *Xa, const void *Ca, int64_t W, int64_t S,
@@ -679,6 +688,7 @@ hipError_t launch_persistent(int T, int NE, bool mix, const PairJobs &J, int gri
         SO_PCASE(1, 2) SO_PCASE(1, 4) SO_PCASE(1, 6) SO_PCASE(1, 8)
         SO_PCASE(2, 2) SO_PCASE(2, 4) SO_PCASE(2, 6) SO_PCASE(2, 8)
         SO_PCASE(3, 2) SO_PCASE(3, 4) SO_PCASE(3, 6) SO_PCASE(3, 8)
+        SO_PCASE(2, 10) SO_PCASE(2, 12) SO_PCASE(3, 10) SO_PCASE(3, 12)
 #undef SO_PCASE
         default: return hipErrorInvalidValue;
     }

@@ -38,7 +38,7 @@ __global__ void k_zero_u32(uint32_t *counter) {
 }
 
 template <int T, int NE, bool MIX>
-__global__ __launch_bounds__(64) void k_pair_persistent(PairJobs J, uint32_t *__restrict__ counter) {
+__global__ __launch_bounds__(64, 2) void k_pair_persistent(PairJobs J, uint32_t *__restrict__ counter) {
     for (;;) {
         uint32_t it = 0u;
         if (threadIdx.x == 0) it = atomicAdd(counter, 1u);

@@ -40,13 +40,14 @@ __device__ __forceinline__ double2 partner_val(double2 v, int q) {
     else return grp_bcast<16>(v, (M2 - 1 - q) & 15);
 }
 
-template <int M2, int K>
+// HJ = false: the matrix is the registers alone (no c J term; ck unused)
+template <int M2, int K, bool HJ = true>
 __device__ __forceinline__ void pf1_step(const Nd1Ctx &cx, double2 (&R)[M2], double2 &pf) {
     const int q = cx.q;
     // x_i = A[i][K] for rows i > K; J[i][K] != 0 only for i = M2-1-K, which is
     // still active iff K < M2/2, and then J[i][K] = -1
     double2 x = c_sel(cx.act && q > K, R[K], c_make(0, 0));
-    if constexpr (K < M2 / 2) x = c_sel(cx.act && q == M2 - 1 - K, c_sub(x, cx.ck), x);
+    if constexpr (HJ && K < M2 / 2) x = c_sel(cx.act && q == M2 - 1 - K, c_sub(x, cx.ck), x);
     const double nx2 = sum16(c_abs2(x));
     const double2 xf = bc16c<K + 1>(x);
     const double nx = sqrt(nx2);
@@ -72,7 +73,7 @@ __device__ __forceinline__ void pf1_step(const Nd1Ctx &cx, double2 (&R)[M2], dou
                  }()), ...);
             }(std::make_integer_sequence<int, M2 - K - 1>{});
         }
-        {   // J[q][M2-1-q] conj(u_{M2-1-q}), with J[q][.] = +1 for q < M2/2, -1 otherwise
+        if constexpr (HJ) {   // J[q][M2-1-q] conj(u_{M2-1-q}), with J[q][.] = +1 for q < M2/2, -1 otherwise
             const double2 vp = partner_val<M2>(v, q);
             const int p = M2 - 1 - q;
             const double2 t = c_fma(c_scale(cx.ck, q < M2 / 2 ? 1.0 : -1.0), vp, y);
@@ -94,7 +95,7 @@ __device__ __forceinline__ void pf1_step(const Nd1Ctx &cx, double2 (&R)[M2], dou
                  }()), ...);
             }(std::make_integer_sequence<int, M2 - K - 2>{});
         }
-        pf1_step<M2, K + 2>(cx, R, pf);
+        pf1_step<M2, K + 2, HJ>(cx, R, pf);
     }
 }
 

@@ -27,10 +27,13 @@
 // weighted by v_j (node table, so_common.h).  Each lane forms M(e_j) for its
 // (pair, node) and reduces it by Householder tridiagonalisation entirely in
 // registers (static indices), so a wave runs NB = 64 / (ne + 1) pairs'
-// nodes at once.
+// nodes at once.  Above ne = 8 a lane cannot hold a whole node matrix; there
+// each 16-lane row takes one (pair, node), lane q holding row q (so_nodes.h,
+// pf1_step), four per pass over the batch's NB (ne + 1) items.
 #pragma once
 #include "so_common.h"
 #include "so_form.h"
+#include "so_nodes.h"
 
 // ---- per-lane Householder Pfaffian of an N x N complex skew matrix -----------
 // A[i][j] for i < j holds the matrix (the rest is implied).  At even step k the
@@ -382,10 +385,49 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
             }
             if (l == 0) slot[3 * NT] = flag ? c_make(0.0, 0.0) : pfk;
         }
-        // ---------------- node Pfaffians of the batch, one (pair, node) per lane
+        // ---------------- node Pfaffians of the batch
         __syncthreads();
         int ln = l;
         asm volatile("" : "+v"(ln));   // as above: no hoisting out of the loops
+        if constexpr (NE > 8) {
+            // one (pair, node) per 16-lane row, lane q < NE owning row q of
+            // M(e_j); four items per pass (pf1_step without a J term)
+            const int g = ln >> 4, q = ln & 15;
+            for (int it0 = 0; it0 < NB * KE; it0 += 4) {
+                const int item = it0 + g;
+                const int pb = item / KE, nj = item - pb * KE;
+                const double2 *slot = Bt + (pb < nb ? pb : 0) * SLOT;
+                const double2 cj = tab.e[nj];
+                const double2 cj2 = c_mul(cj, cj);
+                Nd1Ctx cx;
+                cx.q = q;
+                cx.act = q < NE;
+                cx.ck = c_make(0.0, 0.0);
+                double2 R[NE];
+#pragma unroll
+                for (int y = 0; y < NE; ++y) {
+                    // entry (q, y) from the upper triangles: (x, z) = (min, max)
+                    const int x = q < y ? q : y, z = q < y ? y : q;
+                    const int e = x * (2 * NE - x - 1) / 2 + (z - x - 1);
+                    R[y] = c_make(0.0, 0.0);
+                    if (cx.act && q != y) {
+                        const double2 v = c_fma(cj2, slot[2 * NT + e], c_fma(cj, slot[NT + e], slot[e]));
+                        R[y] = q < y ? v : c_neg(v);
+                    }
+                }
+                double2 pf = c_make(1.0, 0.0);
+                pf1_step<NE, 0, false>(cx, R, pf);
+                if (q == 0 && pb < nb) Vl[item] = c_mul(pf, tab.v[nj]);
+            }
+            __syncthreads();
+            if (l < nb) {
+                double2 acc = c_make(0.0, 0.0);
+                for (int j = 0; j < KE; ++j) acc = c_add(acc, Vl[l * KE + j]);
+                acc = c_mul(acc, Bt[l * SLOT + 3 * NT]);
+                pairs[(int64_t)w * S_total + bs + l] = acc;
+            }
+            continue;
+        }
         const int pb = ln / KE, nj = ln - pb * KE;
         double2 val = c_make(0.0, 0.0);
         if (pb < nb) {
@@ -422,9 +464,10 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
 }
 
 // grid (W, ceil(S_total / spw)) from shadow group sy0, one wave per block;
-// spw is a multiple of 64 / (NE + 1).
+// spw is a multiple of 64 / (NE + 1).  At least two waves per SIMD: the
+// three-tile instances would otherwise take more than 256 registers.
 template <int T, int NE, bool MIX>
-__global__ __launch_bounds__(64) void k_pair(int n, int eta, const void *__restrict__ Xa,
+__global__ __launch_bounds__(64, 2) void k_pair(int n, int eta, const void *__restrict__ Xa,
                                              const void *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
                                              RedTab tab, double2 *__restrict__ pairs,
                                              uint32_t *__restrict__ fb_count, int64_t *__restrict__ fb_list,

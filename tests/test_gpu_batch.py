@@ -33,9 +33,9 @@ def dev_problem(w, **kw):
 
 def mini_uneven():
     """n = 8, 12, 16, 20 (eta = n/2): fused kernel classes (1, 4), (2, 6),
-    (2, 8) and the two-kernel path for ne = 10; plus a second (2, 8) problem
-    so that one persistent launch serves two problems."""
-    shapes = [(8, 4, 9, 23), (12, 6, 6, 31), (16, 8, 5, 45), (20, 10, 3, 17), (16, 8, 4, 29)]
+    (2, 8) and (3, 10); a second (2, 8) problem so that one persistent launch
+    serves two problems; and a problem on the two-kernel path (ne = 5)."""
+    shapes = [(8, 4, 9, 23), (12, 6, 6, 31), (16, 8, 5, 45), (20, 10, 3, 17), (16, 8, 4, 29), (9, 4, 3, 11)]
     return [wl.make(f"u{k}", n, eta, W, S, seed=900 + k) for k, (n, eta, W, S) in enumerate(shapes)]
 
 
@@ -86,7 +86,7 @@ def test_autotune_returns_valid_knobs(B):
     knobs = bt.autotune()
     for w, (spi, wpc) in zip(ws, knobs):
         ne = w.n - w.eta
-        if ne % 2 == 0 and 2 <= ne <= 8:
+        if ne % 2 == 0 and 2 <= ne <= 12:
             nb = 64 // (ne + 1)
             assert spi % nb == 0 and spi // nb in (1, 2, 4, 8) and wpc in (4, 8, 16)
         else:

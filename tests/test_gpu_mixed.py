@@ -60,7 +60,8 @@ def check_mixed(S_gpu, P_gpu, P_ref):
     (8, 4, 5, 40), (6, 2, 4, 33),                      # one tile, fused (ne = 4)
     (16, 8, 6, 70), (12, 6, 4, 50), (10, 4, 3, 41),    # two tiles, fused (ne = 8, 6, 6)
     (24, 16, 3, 30), (20, 14, 2, 17),                  # three tiles, fused (ne = 8, 6)
-    (24, 12, 4, 60), (20, 10, 3, 40), (11, 4, 3, 21),  # two-kernel path (ne = 12, 10, 7)
+    (24, 12, 4, 60), (20, 10, 3, 40), (16, 4, 2, 21),  # fused, row-mapped nodes (ne = 12, 10, 12)
+    (11, 4, 3, 21), (18, 2, 2, 9),                     # two-kernel path (ne = 7, 16)
 ])
 def test_mixed_matches_oracle(B, n, eta, W, S):
     w = wl.make("mx", n, eta, W, S, seed=1000 + 7 * n + eta)

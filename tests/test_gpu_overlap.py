@@ -69,12 +69,15 @@ def test_small_workload_all_pairs(B):
 
 
 @pytest.mark.parametrize("n,eta,W,S", [
-    # two-kernel path (ne = n - eta odd, 0 or above 8)
-    (2, 2, 3, 4), (5, 4, 2, 7), (8, 8, 2, 3), (14, 4, 2, 6), (16, 2, 2, 3), (20, 10, 3, 9), (17, 2, 2, 5),
-    (18, 2, 2, 3), (20, 4, 2, 3), (24, 12, 2, 5),
+    # two-kernel path (ne = n - eta odd, 0 or above 12)
+    (2, 2, 3, 4), (5, 4, 2, 7), (8, 8, 2, 3), (16, 2, 2, 3), (17, 2, 2, 5), (21, 8, 2, 3),
+    (18, 2, 2, 3), (20, 4, 2, 3), (24, 10, 2, 3), (24, 8, 2, 3),
     # fused pair kernel, every (tiles, ne) instance; S ragged against the node batches
     (4, 2, 3, 5), (6, 2, 5, 9), (8, 2, 3, 7), (10, 4, 4, 11), (12, 6, 3, 13), (12, 8, 3, 10), (16, 14, 2, 5),
-    (16, 8, 5, 33), (18, 16, 2, 4), (20, 16, 2, 5), (22, 16, 2, 4), (24, 16, 2, 9)])
+    (16, 8, 5, 33), (18, 16, 2, 4), (20, 16, 2, 5), (22, 16, 2, 4), (24, 16, 2, 9),
+    # ne = 10 and 12: node Pfaffians per 16-lane row (batches of 5 and 4 pairs)
+    (14, 4, 2, 6), (12, 2, 3, 11), (16, 4, 2, 9), (14, 2, 2, 5), (20, 10, 3, 9), (18, 8, 2, 7),
+    (24, 12, 3, 10), (22, 10, 2, 5)])
 def test_sizes_and_ragged_shapes(B, n, eta, W, S):
     """Every compiled size class: m = 2n - eta from 2 to 46, both paths."""
     w = wl.make("t", n, eta, W, S, seed=1000 + 7 * n + eta, orthonormal=(n % 2 == 0))
