@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--uneven-steps", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES bytes device to device, three times (scales the HBM counters)")
     ap.add_argument("--precision-steps", type=int, default=2)
     ap.add_argument("--precision-sample", type=int, default=2000,
                     help="pairs of the n=24 workload checked against the oracle")
@@ -286,6 +288,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": 3}), flush=True)
+        return
 
     from paper_2506_22408_amd import binding as B
     from paper_2506_22408_amd import workload as wl
