@@ -225,13 +225,13 @@ __device__ __forceinline__ void load_ops(const float4 *__restrict__ M, float (&a
             a[I][4 * q + 3] = v.w;
         }
 }
-// U = C' Xall^T, then the tiles I <= J of P = Xall U.  The accumulator of U's
+// U = C' Xall^T (all tiles, returned as well), then the tiles I <= J of
+// P = Xall U.  The accumulator of U's
 // tile (I, J), register r, is the B operand of P at k-step 4 I + r (in single
 // precision because C' is stored with its rows in the order sig16).
 template <int T>
 __device__ __forceinline__ void form_p(const double (&xa)[T][4 * T], const double (&ca)[T][4 * T],
-                                       so_d4 (&P)[T][T]) {
-    so_d4 U[T][T];
+                                       so_d4 (&P)[T][T], so_d4 (&U)[T][T]) {
 #pragma unroll
     for (int I = 0; I < T; ++I)
 #pragma unroll
@@ -256,8 +256,8 @@ __device__ __forceinline__ void form_p(const double (&xa)[T][4 * T], const doubl
                 P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0, 0, 0);
 }
 template <int T>
-__device__ __forceinline__ void form_p(const float (&xa)[T][4 * T], const float (&ca)[T][4 * T], so_f4 (&P)[T][T]) {
-    so_f4 U[T][T];
+__device__ __forceinline__ void form_p(const float (&xa)[T][4 * T], const float (&ca)[T][4 * T], so_f4 (&P)[T][T],
+                                       so_f4 (&U)[T][T]) {
 #pragma unroll
     for (int I = 0; I < T; ++I)
 #pragma unroll

@@ -86,8 +86,8 @@ __global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const void *__
     for (int sl = sl0; sl < sl1; ++sl) {
         Op ca[T][KK];
         load_ops<T>(static_cast<const Vec *>(Ca) + (size_t)(s0 + sl) * MATV, ca, l);
-        Acc P[T][T];
-        form_p<T>(xa, ca, P);
+        Acc P[T][T], U[T][T];
+        form_p<T>(xa, ca, P, U);
 
         __syncthreads();   // the previous pair's reads of Pl and Rl are done
 #pragma unroll

@@ -119,17 +119,19 @@ __device__ __forceinline__ void gj_rows16(double2 *G0, int stride, int l, bool *
     }
 }
 
-// LDS regions of k_grad_pair (bytes), in order RP, RX, RB, RR, RG, RA, RS.
+// LDS regions of k_grad_pair (bytes), in order RP, RU, RB, RR, RG, RS.  RP
+// holds P until B is built and Abar after that.
 struct GradLds {
-    size_t rp, rx, rb, rr, rg, ra, rs, total;
+    size_t rp, ru, rb, rr, rg, rs, total;
 };
 __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
     const int DP = 16 * T, LDP = DP + 1, m = n + NE, d = 2 * n;
     GradLds g;
     auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
     g.rp = al((size_t)(DP + 1) * LDP * sizeof(double));
-    g.rx = g.rp;
+    g.ru = g.rp;
     g.rb = al((size_t)m * m * sizeof(double2));
+    if (g.rb > g.rp) g.rp = g.rb;
     size_t rr = (size_t)n * (n + 2 * NE);
     if ((size_t)4 * NE * 2 * NE > rr) rr = (size_t)4 * NE * 2 * NE;
     if ((size_t)NE * (2 * NE - 1) > rr) rr = (size_t)NE * (2 * NE - 1);
@@ -141,9 +143,8 @@ __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
     if ((size_t)2 * m * m * sizeof(double2) > g.rr + rg * sizeof(double2))
         rg = ((size_t)2 * m * m * sizeof(double2) - g.rr + sizeof(double2) - 1) / sizeof(double2);
     g.rg = al(rg * sizeof(double2));
-    g.ra = g.rb;
     g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + 3 * NE * NE + (NE + 1) + 2 * m + 4) * sizeof(double2));
-    g.total = g.rp + g.rx + g.rb + g.rr + g.rg + g.ra + g.rs;
+    g.total = g.rp + g.ru + g.rb + g.rr + g.rg + g.rs;
     return g;
 }
 
@@ -167,12 +168,12 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
     const GradLds L = grad_lds(T, n, NE);
     char *base = reinterpret_cast<char *>(lds);
     double *RP = reinterpret_cast<double *>(base);
-    double *RX = reinterpret_cast<double *>(base + L.rp);
-    double2 *RB = reinterpret_cast<double2 *>(base + L.rp + L.rx);
-    double2 *RR = reinterpret_cast<double2 *>(base + L.rp + L.rx + L.rb);
-    double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.rx + L.rb + L.rr);
-    double2 *RA = reinterpret_cast<double2 *>(base + L.rp + L.rx + L.rb + L.rr + L.rg);
-    double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.rx + L.rb + L.rr + L.rg + L.ra);
+    double2 *RA = reinterpret_cast<double2 *>(base);   // over P once B is built
+    double *RU = reinterpret_cast<double *>(base + L.rp);
+    double2 *RB = reinterpret_cast<double2 *>(base + L.rp + L.ru);
+    double2 *RR = reinterpret_cast<double2 *>(base + L.rp + L.ru + L.rb);
+    double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.ru + L.rb + L.rr);
+    double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.ru + L.rb + L.rr + L.rg);
     double2 *Mup = RS;                       // M0, M1, M2 upper triangles
     double2 *Ahat = RS + 3 * NT;             // A_0, A_1, A_2 (NE x NE each)
     double2 *pfm = Ahat + 3 * NE * NE;       // Pf(M_j)
@@ -189,17 +190,10 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
         ta[q] = a;
         tb[q] = a + 1 + e;
     }
-    // the walker's Xall, row-major, with a zero row DP
     const double2 *Xw = Xa + (size_t)w * MAT2;
-    {
-        const double *Xd = reinterpret_cast<const double *>(Xw);
-        for (int f = l; f < DP * DP; f += 64) {
-            int row, col;
-            ao_rowcol(f, T, row, col);
-            RX[row * LDP + col] = Xd[f];
-        }
-        for (int c = l; c <= DP; c += 64) RX[DP * LDP + c] = 0.0;
-    }
+    // U = C' Xall^T of each pair goes to RU (rows and columns < DP); its
+    // column DP stays zero (the missing imaginary part of an empty row)
+    for (int r = l; r < DP; r += 64) RU[r * LDP + DP] = 0.0;
     auto rre = [&](int i) -> int { return i < eta ? i : eta + i; };
     auto rim = [&](int i) -> int { return i < eta ? eta + i : DP; };
     // J of the stored order: +1 at (eta+t, eta+2ne-1-t), -1 at the transpose
@@ -219,7 +213,7 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
     const int64_t s1 = min(S_total, s0 + spw);
     for (int64_t s = s0; s < s1; ++s) {
         const double2 *Cs = Ca + (size_t)s * MAT2;
-        pair_formation<T, false>(Xw, Cs, RP, l);
+        pair_formation<T, false>(Xw, Cs, RP, l, RU);
 
         // ---------------- B (m x m), then R = rows K of Z, G = [B_KK | B_KL | J_KL | I]
         double bmax = 0.0;
@@ -272,18 +266,11 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
                 Mup[2 * NT + e] = RR[tix(NE + x, NE + y)];
             }
             __syncthreads();
-            if (l < KE) {
-                const double2 cj = tab.e[l], cj2 = c_mul(cj, cj);
-                double2 A[NE][NE];
-                int e = 0;
-#pragma unroll
-                for (int x = 0; x < NE; ++x)
-#pragma unroll
-                    for (int y = x + 1; y < NE; ++y) {
-                        A[x][y] = c_fma(cj2, Mup[2 * NT + e], c_fma(cj, Mup[NT + e], Mup[e]));
-                        ++e;
-                    }
-                pfm[l] = pf_lane_from<NE, 0>(A);
+            // Pf(M_j), four nodes per pass, one per 16-lane row
+            for (int j0 = 0; j0 < KE; j0 += 4) {
+                const int j = j0 + (l >> 4);
+                const double2 pf = pencil_pf_row<NE>(Mup, tab.e[j < KE ? j : KE - 1], l & 15);
+                if ((l & 15) == 0 && j < KE) pfm[j] = pf;
             }
             __syncthreads();
             for (int j = 0; j < KE; ++j) o = c_fma(tab.v[j], pfm[j], o);
@@ -406,33 +393,15 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
         }
         oacc = c_add(oacc, o);
 
-        // ---------------- F += C' X^T Abar: H = X^T Abar into RG, C' into RP
-        for (int e = l; e < d * m; e += 64) {
-            const int mu = e / m, r = e - mu * m;
-            double2 h = c_make(0, 0);
-            for (int i = 0; i < m; ++i) {
-                const double xr = RX[rre(i) * LDP + mu], xi = RX[rim(i) * LDP + mu];
-                const double2 a = RA[i * m + r];
-                h = c_fma(c_make(xr, xi), a, h);
-            }
-            RG[e] = h;
-        }
-        {
-            const double *Cd = reinterpret_cast<const double *>(Cs);
-            for (int f = l; f < DP * DP; f += 64) {
-                int row, col;
-                ao_rowcol(f, T, row, col);
-                RP[row * LDP + col] = Cd[f];
-            }
-        }
-        __syncthreads();
+        // ---------------- F += (C' X^T) Abar, with (C' X^T)[mu][i] = U[mu][rre(i)] + i U[mu][rim(i)]
 #pragma unroll
         for (int q = 0; q < FQ; ++q) {
             const int e = l + 64 * q;
             if (e < d * m) {
                 const int mu = e / m, r = e - mu * m;
+                const double *urow = RU + mu * LDP;
                 double2 acc = facc[q];
-                for (int nu = 0; nu < d; ++nu) acc = c_fma(c_make(RP[mu * LDP + nu], 0.0), RG[nu * m + r], acc);
+                for (int i = 0; i < m; ++i) acc = c_fma(c_make(urow[rre(i)], urow[rim(i)]), RA[i * m + r], acc);
                 facc[q] = acc;
             }
         }

@@ -104,9 +104,11 @@ __device__ __forceinline__ double2 pf_lane_from(double2 (&A)[N][N]) {
 // quads, C' rows in the order sig16) on v_mfma_f32_16x16x4f32 with
 // single-precision accumulation; P is widened to FP64 when it is stored and
 // everything after the formation runs in FP64.
+// With Ul (FP64 only) U = C' Xall^T is kept as well: Ul[r LDP + c] = U[r][c]
+// for r, c < DP (LDP = DP + 1 columns, column DP left to the caller).
 template <int T, bool MIX>
 __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, const void *__restrict__ Cv,
-                                               double *Pl, int l) {
+                                               double *Pl, int l, double *Ul = nullptr) {
     constexpr int KK = 4 * T, DP = 16 * T, LDP = DP + 1;
     using Op = typename std::conditional<MIX, float, double>::type;
     using Vec = typename std::conditional<MIX, float4, double2>::type;
@@ -116,9 +118,21 @@ __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, cons
     Op xa[T][KK], ca[T][KK];
     load_ops<T>(static_cast<const Vec *>(Xv), xa, l);
     load_ops<T>(static_cast<const Vec *>(Cv), ca, l);
-    Acc P[T][T];
-    form_p<T>(xa, ca, P);
+    Acc P[T][T], U[T][T];
+    form_p<T>(xa, ca, P, U);
     __syncthreads();   // region A is free
+    if constexpr (!MIX) {
+        if (Ul) {
+            // register r of U's tile (I, J) holds U[16 I + 4 r + l/16][16 J + l%16]
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = 0; J < T; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        Ul[(16 * I + 4 * r + (l >> 4)) * LDP + 16 * J + (l & 15)] = U[I][J][r];
+        }
+    }
 #pragma unroll
     for (int I = 0; I < T; ++I)
 #pragma unroll
@@ -220,6 +234,36 @@ __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const 
     tmax = wave_max(fmax(tmax, gmax));
     const bool flag = zero || !(tmax <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * fmax(bmax, 1.0));
     return flag;
+}
+
+// Pf(M(c)) of the pencil M(c) = M0 + c M1 + c^2 M2 (ne x ne, ne <= 16, even)
+// whose upper triangles are stored row by row at slot, slot + NT, slot + 2 NT
+// (NT = NE (NE - 1) / 2), on one 16-lane row: lane q = l % 16 builds row q of
+// M(c) and the row reduces it (pf1_step without a J term).  Every lane of the
+// row returns the Pfaffian.
+template <int NE>
+__device__ __forceinline__ double2 pencil_pf_row(const double2 *slot, double2 c, int q) {
+    constexpr int NT = NE * (NE - 1) / 2;
+    const double2 c2 = c_mul(c, c);
+    Nd1Ctx cx;
+    cx.q = q;
+    cx.act = q < NE;
+    cx.ck = c_make(0.0, 0.0);
+    double2 R[NE];
+#pragma unroll
+    for (int y = 0; y < NE; ++y) {
+        // entry (q, y) from the upper triangles: (x, z) = (min, max)
+        const int x = q < y ? q : y, z = q < y ? y : q;
+        const int e = x * (2 * NE - x - 1) / 2 + (z - x - 1);
+        R[y] = c_make(0.0, 0.0);
+        if (cx.act && q != y) {
+            const double2 v = c_fma(c2, slot[2 * NT + e], c_fma(c, slot[NT + e], slot[e]));
+            R[y] = q < y ? v : c_neg(v);
+        }
+    }
+    double2 pf = c_make(1.0, 0.0);
+    pf1_step<NE, 0, false>(cx, R, pf);
+    return pf;
 }
 
 // LDS per wave: region A = max(P ((DP+1) x (DP+1) f64), R (n x (n + 2 NE) c128),
@@ -396,27 +440,7 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
             for (int it0 = 0; it0 < NB * KE; it0 += 4) {
                 const int item = it0 + g;
                 const int pb = item / KE, nj = item - pb * KE;
-                const double2 *slot = Bt + (pb < nb ? pb : 0) * SLOT;
-                const double2 cj = tab.e[nj];
-                const double2 cj2 = c_mul(cj, cj);
-                Nd1Ctx cx;
-                cx.q = q;
-                cx.act = q < NE;
-                cx.ck = c_make(0.0, 0.0);
-                double2 R[NE];
-#pragma unroll
-                for (int y = 0; y < NE; ++y) {
-                    // entry (q, y) from the upper triangles: (x, z) = (min, max)
-                    const int x = q < y ? q : y, z = q < y ? y : q;
-                    const int e = x * (2 * NE - x - 1) / 2 + (z - x - 1);
-                    R[y] = c_make(0.0, 0.0);
-                    if (cx.act && q != y) {
-                        const double2 v = c_fma(cj2, slot[2 * NT + e], c_fma(cj, slot[NT + e], slot[e]));
-                        R[y] = q < y ? v : c_neg(v);
-                    }
-                }
-                double2 pf = c_make(1.0, 0.0);
-                pf1_step<NE, 0, false>(cx, R, pf);
+                const double2 pf = pencil_pf_row<NE>(Bt + (pb < nb ? pb : 0) * SLOT, tab.e[nj], q);
                 if (q == 0 && pb < nb) Vl[item] = c_mul(pf, tab.v[nj]);
             }
             __syncthreads();
