@@ -119,17 +119,18 @@ __device__ __forceinline__ void gj_rows16(double2 *G0, int stride, int l, bool *
     }
 }
 
-// LDS regions of k_grad_pair (bytes), in order RP, RU, RB, RR, RG, RS.  RP
-// holds P until B is built and Abar after that.
+// LDS regions of k_grad_pair (bytes), in order RP, RB, RR, RG, RS.  RP holds
+// P until B is built and Abar after that; RB holds B and, once the full-size
+// route is ruled out, the node sums A_0, A_1, A_2; the full-size route's
+// [B + cJ | I] (m x 2m) and its Householder vectors span RR and RG.
 struct GradLds {
-    size_t rp, ru, rb, rr, rg, rs, total;
+    size_t rp, rb, rr, rg, rs, total;
 };
 __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
     const int DP = 16 * T, LDP = DP + 1, m = n + NE, d = 2 * n;
     GradLds g;
     auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
     g.rp = al((size_t)(DP + 1) * LDP * sizeof(double));
-    g.ru = g.rp;
     g.rb = al((size_t)m * m * sizeof(double2));
     if (g.rb > g.rp) g.rp = g.rb;
     size_t rr = (size_t)n * (n + 2 * NE);
@@ -138,13 +139,11 @@ __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
     if ((size_t)2 * n * NE > rr) rr = (size_t)2 * n * NE;
     g.rr = al(rr * sizeof(double2));
     size_t rg = (size_t)n * (2 * n + 2 * NE);
-    if ((size_t)d * m > rg) rg = (size_t)d * m;
-    // the full-size route's [B + cJ | I] (m x 2m) spans RR and RG
-    if ((size_t)2 * m * m * sizeof(double2) > g.rr + rg * sizeof(double2))
-        rg = ((size_t)2 * m * m * sizeof(double2) - g.rr + sizeof(double2) - 1) / sizeof(double2);
+    const size_t full = ((size_t)2 * m * m + 2 * m) * sizeof(double2);
+    if (full > g.rr + rg * sizeof(double2)) rg = (full - g.rr + sizeof(double2) - 1) / sizeof(double2);
     g.rg = al(rg * sizeof(double2));
-    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + 3 * NE * NE + (NE + 1) + 2 * m + 4) * sizeof(double2));
-    g.total = g.rp + g.ru + g.rb + g.rr + g.rg + g.rs;
+    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1) + 4) * sizeof(double2));
+    g.total = g.rp + g.rb + g.rr + g.rg + g.rs;
     return g;
 }
 
@@ -161,7 +160,8 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
     constexpr int NT = NE * (NE - 1) / 2;
     constexpr int NT2 = NE * (2 * NE - 1);
     constexpr int NTQ = (NT2 + 63) / 64;
-    constexpr int FQ = (16 * T * (8 * T + NE) + 63) / 64;   // F entries per lane (2n x m, n <= 8T)
+    constexpr int KK = 4 * T;
+    constexpr int TM = (8 * T + NE + 15) / 16;              // 16-row tiles of F^T (m = n + NE <= 8T + NE)
     const int m = n + NE, d = 2 * n, WR = n + 2 * NE, GW = 2 * n + 2 * NE;
     const int l = threadIdx.x, w = blockIdx.x;
     extern __shared__ double lds[];
@@ -169,15 +169,14 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
     char *base = reinterpret_cast<char *>(lds);
     double *RP = reinterpret_cast<double *>(base);
     double2 *RA = reinterpret_cast<double2 *>(base);   // over P once B is built
-    double *RU = reinterpret_cast<double *>(base + L.rp);
-    double2 *RB = reinterpret_cast<double2 *>(base + L.rp + L.ru);
-    double2 *RR = reinterpret_cast<double2 *>(base + L.rp + L.ru + L.rb);
-    double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.ru + L.rb + L.rr);
-    double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.ru + L.rb + L.rr + L.rg);
+    double2 *RB = reinterpret_cast<double2 *>(base + L.rp);
+    double2 *RR = reinterpret_cast<double2 *>(base + L.rp + L.rb);
+    double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr);
+    double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr + L.rg);
     double2 *Mup = RS;                       // M0, M1, M2 upper triangles
-    double2 *Ahat = RS + 3 * NT;             // A_0, A_1, A_2 (NE x NE each)
-    double2 *pfm = Ahat + 3 * NE * NE;       // Pf(M_j)
-    double2 *ubuf = pfm + KE;                // Householder scratch (m each)
+    double2 *pfm = RS + 3 * NT;              // Pf(M_j)
+    double2 *Ahat = RB;                      // A_0, A_1, A_2 (NE x NE each), over B
+    double2 *ubuf = RR + 2 * m * m;          // Householder vectors of the full-size route
     double2 *ybuf = ubuf + m;
 
     // trailing entries (a < b) of the 2NE x 2NE block handled by this lane
@@ -191,9 +190,6 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
         tb[q] = a + 1 + e;
     }
     const double2 *Xw = Xa + (size_t)w * MAT2;
-    // U = C' Xall^T of each pair goes to RU (rows and columns < DP); its
-    // column DP stays zero (the missing imaginary part of an empty row)
-    for (int r = l; r < DP; r += 64) RU[r * LDP + DP] = 0.0;
     auto rre = [&](int i) -> int { return i < eta ? i : eta + i; };
     auto rim = [&](int i) -> int { return i < eta ? eta + i : DP; };
     // J of the stored order: +1 at (eta+t, eta+2ne-1-t), -1 at the transpose
@@ -203,9 +199,16 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
         return (u + v == 2 * NE - 1) ? (u < NE ? 1.0 : -1.0) : 0.0;
     };
 
-    double2 facc[FQ];
+    // F^T = sum over the range of Abar''^T (Xall C'^T), real and imaginary
+    // parts, in the matrix-core accumulators (tile (I, J), register r, lane
+    // l: F^T[16 I + 4 r + l/16][16 J + l%16])
+    so_d4 FT[2][TM][T];
 #pragma unroll
-    for (int q = 0; q < FQ; ++q) facc[q] = c_make(0.0, 0.0);
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int I = 0; I < TM; ++I)
+#pragma unroll
+            for (int J = 0; J < T; ++J) FT[p][I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
     double2 oacc = c_make(0.0, 0.0);
     int32_t wflags = 0;
 
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
     const int64_t s1 = min(S_total, s0 + spw);
     for (int64_t s = s0; s < s1; ++s) {
         const double2 *Cs = Ca + (size_t)s * MAT2;
-        pair_formation<T, false>(Xw, Cs, RP, l, RU);
+        pair_formation<T, false>(Xw, Cs, RP, l);
 
         // ---------------- B (m x m), then R = rows K of Z, G = [B_KK | B_KL | J_KL | I]
         double bmax = 0.0;
@@ -393,26 +396,59 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
         }
         oacc = c_add(oacc, o);
 
-        // ---------------- F += (C' X^T) Abar, with (C' X^T)[mu][i] = U[mu][rre(i)] + i U[mu][rim(i)]
+        // ---------------- F += (C' X^T) Abar = U Abar'' with U = C' Xall^T (d x DP)
+        // and Abar'' (DP x m) the rows of Abar placed on the rows of Xall:
+        // Abar''[rre(i)] = Abar[i], Abar''[rim(i)] = i Abar[i].  On the matrix
+        // cores as F^T += Abar''^T U^T: U^T = Xall C'^T from the operands, its
+        // tile (I, J) register r being the B operand at k-step 4 I + r.
+        {
+            double xa[T][KK], ca[T][KK];
+            load_ops<T>(Xw, xa, l);
+            load_ops<T>(Cs, ca, l);
+            so_d4 Ut[T][T];
 #pragma unroll
-        for (int q = 0; q < FQ; ++q) {
-            const int e = l + 64 * q;
-            if (e < d * m) {
-                const int mu = e / m, r = e - mu * m;
-                const double *urow = RU + mu * LDP;
-                double2 acc = facc[q];
-                for (int i = 0; i < m; ++i) acc = c_fma(c_make(urow[rre(i)], urow[rim(i)]), RA[i * m + r], acc);
-                facc[q] = acc;
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int J = 0; J < T; ++J) Ut[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+                for (int I = 0; I < T; ++I)
+#pragma unroll
+                    for (int J = 0; J < T; ++J)
+                        Ut[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], ca[J][kk], Ut[I][J], 0, 0, 0);
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                // A operand: Abar''[k][c], k = 4 kk + l/16 a row of Xall, c = 16 I + l%16
+                const int k = 4 * kk + (l >> 4);
+                const int i = k < eta ? k : k - eta;
+                const bool imag = k >= eta && k < 2 * eta;
+#pragma unroll
+                for (int I = 0; I < TM; ++I) {
+                    const int c = 16 * I + (l & 15);
+                    double2 a = c_make(0.0, 0.0);
+                    if (k < d && c < m) a = RA[i * m + c];
+                    if (imag) a = c_make(-a.y, a.x);
+#pragma unroll
+                    for (int J = 0; J < T; ++J) {
+                        FT[0][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, Ut[kk >> 2][J][kk & 3], FT[0][I][J], 0, 0, 0);
+                        FT[1][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, Ut[kk >> 2][J][kk & 3], FT[1][I][J], 0, 0, 0);
+                    }
+                }
             }
         }
-        __syncthreads();
+        __syncthreads();   // Abar reads done before the next formation
     }
     const int64_t part = (int64_t)w * gridDim.y + blockIdx.y;
 #pragma unroll
-    for (int q = 0; q < FQ; ++q) {
-        const int e = l + 64 * q;
-        if (e < d * m) Fpart[part * (int64_t)(d * m) + e] = facc[q];
-    }
+    for (int I = 0; I < TM; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int c = 16 * I + 4 * r + (l >> 4), mu = 16 * J + (l & 15);
+                if (c < m && mu < d) Fpart[part * (int64_t)(d * m) + mu * m + c] = c_make(FT[0][I][J][r], FT[1][I][J][r]);
+            }
     if (l == 0) {
         Opart[part] = oacc;
         if (wflags) atomicOr(&wstat[w], wflags);
