@@ -35,10 +35,13 @@
 #define SO_GRAD_MMAX 24
 
 // ---- Gauss-Jordan with partial pivoting on the first nr columns of the
-// nr x nc system G (row-major, LDS), one column per lane (nc <= 64).  Leaves
-// [I | G^{-1} rhs].  Returns false on an exactly zero pivot column.  The
-// pivot key is the high word of |G[r][k]|^2 with its low 6 bits replaced by
-// 63 - lane (the high word of a non-negative double orders like the value).
+// nr x nc system G (row-major, LDS), one column per lane (nc <= 64), nr <=
+// NRM.  Leaves [I | G^{-1} rhs].  Returns false on an exactly zero pivot
+// column.  The pivot key is the high word of |G[r][k]|^2 with its low 6 bits
+// replaced by 63 - lane (the high word of a non-negative double orders like
+// the value).  The row loop of the update is unrolled to NRM so that a
+// step's LDS accesses are issued together.
+template <int NRM>
 __device__ __forceinline__ bool gj_wave(double2 *G, int nr, int nc, int l) {
     for (int k = 0; k < nr; ++k) {
         const int r = k + l;
@@ -64,10 +67,12 @@ __device__ __forceinline__ bool gj_wave(double2 *G, int nr, int nc, int l) {
         __syncthreads();
         if (l < nc) {
             const double2 gk = G[k * nc + l];
-            for (int rr = 0; rr < nr; ++rr) {
-                if (rr == k) continue;
-                const double2 f = G[rr * nc + k];
-                G[rr * nc + l] = c_fma(c_neg(f), gk, G[rr * nc + l]);
+#pragma unroll
+            for (int rr = 0; rr < NRM; ++rr) {
+                if (rr < nr && rr != k) {
+                    const double2 f = G[rr * nc + k];
+                    G[rr * nc + l] = c_fma(c_neg(f), gk, G[rr * nc + l]);
+                }
             }
         }
         __syncthreads();
@@ -75,48 +80,58 @@ __device__ __forceinline__ bool gj_wave(double2 *G, int nr, int nc, int l) {
     return true;
 }
 
-// The same for four independent NE x 2NE systems, one per 16-lane row (system
-// g at G0 + g * stride).  A system whose pivot column is zero sets *sing.
+// Gauss-Jordan with partial pivoting for four independent NE x 2NE systems
+// (NE <= 8), one per 16-lane row (system g at G0 + g * stride, row-major):
+// lane c of row g loads column c, the steps run on registers with DPP
+// broadcasts inside the row (no LDS traffic or barrier inside a step), and
+// the column is stored back, leaving [I | M^{-1} rhs].  The pivot is the
+// largest |G[r][k]|, the first one on ties; a system whose pivot column is
+// zero sets *sing (and is left partly reduced).
 template <int NE>
 __device__ __forceinline__ void gj_rows16(double2 *G0, int stride, int l, bool *sing) {
     constexpr int NC = 2 * NE;
     const int g = l >> 4, c = l & 15;
     double2 *G = G0 + g * stride;
-    for (int k = 0; k < NE; ++k) {
-        const int r = k + c;
-        unsigned key = 0u;
-        if (r < NE) {
-            const unsigned hw = (unsigned)(__double_as_longlong(c_abs2(G[r * NC + k])) >> 32);
-            key = (hw & ~63u) | (unsigned)(63 - c);
-        }
-        // row maximum (every lane of the 16-lane row gets it)
-        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0xB1, 0xf, 0xf, false));
-        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x4E, 0xf, 0xf, false));
-        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x141, 0xf, 0xf, false));
-        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x140, 0xf, 0xf, false));
-        if (key < 64u) *sing = true;
-        // a zero column still names a valid row (c = 0 has the largest index bits)
-        const int p = k + (63 - (int)(key & 63u));
-        if (p != k && c < NC) {
-            const double2 t0 = G[k * NC + c], t1 = G[p * NC + c];
-            G[k * NC + c] = t1;
-            G[p * NC + c] = t0;
-        }
-        __syncthreads();
-        const double2 ip = c_inv_nr(G[k * NC + k]);
-        __syncthreads();
-        if (c < NC) G[k * NC + c] = c_mul(G[k * NC + c], ip);
-        __syncthreads();
-        if (c < NC) {
-            const double2 gk = G[k * NC + c];
-            for (int rr = 0; rr < NE; ++rr) {
-                if (rr == k) continue;
-                const double2 f = G[rr * NC + k];
-                G[rr * NC + c] = c_fma(c_neg(f), gk, G[rr * NC + c]);
-            }
-        }
-        __syncthreads();
-    }
+    double2 col[NE];
+#pragma unroll
+    for (int r = 0; r < NE; ++r) col[r] = c < NC ? G[r * NC + c] : c_make(0.0, 0.0);
+    bool zero = false;
+    [&]<int... K>(std::integer_sequence<int, K...>) {
+        (([&] {
+             constexpr int k = K;
+             double best = -1.0;
+             int bi = k;
+#pragma unroll
+             for (int r = k; r < NE; ++r) {
+                 const double a = c_abs2(col[r]);
+                 if (a > best) { best = a; bi = r; }
+             }
+             const double bk = bc16<k>(best);
+             const int p = __builtin_amdgcn_update_dpp(bi, bi, 0x150 + k, 0xf, 0xf, false);
+             zero = zero || !(bk > 0.0);
+#pragma unroll
+             for (int r = k + 1; r < NE; ++r)
+                 if (r == p) {
+                     const double2 t = col[k];
+                     col[k] = col[r];
+                     col[r] = t;
+                 }
+             const double2 piv = bc16c<k>(col[k]);
+             col[k] = c_mul(col[k], c_inv_nr(bk > 0.0 ? piv : c_make(1.0, 0.0)));
+#pragma unroll
+             for (int r = 0; r < NE; ++r)
+                 if (r != k) {
+                     const double2 f = bc16c<k>(col[r]);
+                     col[r] = c_fma(c_neg(f), col[k], col[r]);
+                 }
+         }()), ...);
+    }(std::make_integer_sequence<int, NE>{});
+    if (zero) *sing = true;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NE; ++r)
+        if (c < NC) G[r * NC + c] = col[r];
+    __syncthreads();
 }
 
 // LDS regions of k_grad_pair (bytes), in order RP, RB, RR, RG, RS.  RP holds
@@ -279,7 +294,7 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
             for (int j = 0; j < KE; ++j) o = c_fma(tab.v[j], pfm[j], o);
             o = c_mul(o, pfk);
             // ---------------- Y0, Y1, B_KK^{-1}
-            if (!gj_wave(RG, n, GW, l)) flag = true;
+            if (!gj_wave<8 * T>(RG, n, GW, l)) flag = true;
         }
         if (!flag) {
             // ---------------- A_p from the node inverses, four nodes at a time
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
                                      : c_make((c - m == i) ? 1.0 : 0.0, 0.0);
                 }
                 __syncthreads();
-                if (!gj_wave(Aug, m, AW, l)) wflags |= SO_WSTAT_SINGULAR;
+                if (!gj_wave<8 * T + NE>(Aug, m, AW, l)) wflags |= SO_WSTAT_SINGULAR;
                 const double2 f = c_mul(tab.v[j], qj);
                 o = c_fma(tab.v[j], qj, o);
                 for (int e = l; e < m * m; e += 64) {
@@ -501,7 +516,7 @@ __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double
         Gm[e] = v;
     }
     __syncthreads();
-    const bool ok = gj_wave(Gm, eta, gw, l);
+    const bool ok = gj_wave<SO_GRAD_NMAX>(Gm, eta, gw, l);
     for (int e = l; e < eta * n; e += 64) {
         const int j = e / n, q = e - j * n;
         double2 v = c_make(0, 0);
