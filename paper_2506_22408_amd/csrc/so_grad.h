@@ -157,7 +157,7 @@ __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
     const size_t full = ((size_t)2 * m * m + 2 * m) * sizeof(double2);
     if (full > g.rr + rg * sizeof(double2)) rg = (full - g.rr + sizeof(double2) - 1) / sizeof(double2);
     g.rg = al(rg * sizeof(double2));
-    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1) + 4) * sizeof(double2));
+    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1) + 8) * sizeof(double2));   // + the permutation
     g.total = g.rp + g.rb + g.rr + g.rg + g.rs;
     return g;
 }
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
         const double2 *Cs = Ca + (size_t)s * MAT2;
         pair_formation<T, false>(Xw, Cs, RP, l);
 
-        // ---------------- B (m x m), then R = rows K of Z, G = [B_KK | B_KL | J_KL | I]
+        // ---------------- B (m x m), then R = rows K of Z
         double bmax = 0.0;
         for (int e = l; e < m * m; e += 64) {
             const int i = e / m, j = e - i * m;
@@ -249,14 +249,6 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
             const int i = e / WR, j = e - i * WR;
             RR[e] = (j < m) ? RB[i * m + j] : c_make(Jel(i, n + (j - m)), 0.0);
         }
-        for (int e = l; e < n * GW; e += 64) {
-            const int i = e / GW, c = e - i * GW;
-            double2 v;
-            if (c < m) v = RB[i * m + c];
-            else if (c < m + NE) v = c_make(Jel(i, n + (c - m)), 0.0);
-            else v = c_make((c - m - NE == i) ? 1.0 : 0.0, 0.0);
-            RG[e] = v;
-        }
         double2 tv[NTQ];
 #pragma unroll
         for (int q = 0; q < NTQ; ++q) {
@@ -267,9 +259,60 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
 
         // ---------------- elimination of K, pencil, node Pfaffians
         double2 pfk;
-        bool flag = elim_bordered<NE, NTQ>(n, WR, RR, ta, tb, tv, bmax, rbmax, l, pfk);
+        int perm = l;
+        bool flag = elim_bordered<NE, NTQ>(n, WR, RR, ta, tb, tv, bmax, rbmax, l, pfk, &perm);
         double2 o = c_make(0.0, 0.0);
         if (!flag) {
+            // ---------------- Y0, Y1, B_KK^{-1} by back substitution with the pivot rows
+            // U [Y' | W] = [R_LE | I] in the pivoted order (U = the rows of R, block
+            // upper triangular with pivots [[0, a], [-a, 0]]); then, with pi the
+            // permutation, Y[pi(i)] = Y'[i] and B_KK^{-1}[pi(i)][pi(j)] = (-W D W^T)[i][j]
+            // (P B_KK P^T = L D L^T = -U^T D^{-1} U).  Lane c < 2NE + n holds
+            // column c of the right-hand side; the solution goes to RB (free: the
+            // full-size route is ruled out) and then, reordered, to RG.
+            {
+                constexpr int NRM = 8 * T;
+                const int SW = 2 * NE + n;
+                double2 rhs[NRM];
+#pragma unroll
+                for (int i = 0; i < NRM; ++i) {
+                    rhs[i] = c_make(0.0, 0.0);
+                    if (i < n && l < SW) rhs[i] = l < 2 * NE ? RR[i * WR + n + l] : c_make(i == l - 2 * NE ? 1.0 : 0.0, 0.0);
+                }
+#pragma unroll
+                for (int bb = 0; bb < NRM / 2; ++bb) {
+                    const int k = NRM - 2 - 2 * bb;
+                    if (k < n) {
+                        const double2 ia = c_inv_nr(RR[k * WR + k + 1]);
+                        const double2 yk1 = c_mul(rhs[k], ia), yk = c_neg(c_mul(rhs[k + 1], ia));
+                        rhs[k] = yk;
+                        rhs[k + 1] = yk1;
+#pragma unroll
+                        for (int i = 0; i < k; ++i)
+                            rhs[i] = c_fma(c_neg(RR[i * WR + k]), yk, c_fma(c_neg(RR[i * WR + k + 1]), yk1, rhs[i]));
+                    }
+                }
+                int *pis = reinterpret_cast<int *>(pfm + KE);
+                if (l < n) pis[l] = perm;
+#pragma unroll
+                for (int i = 0; i < NRM; ++i)
+                    if (i < n && l < SW) RB[i * SW + l] = rhs[i];
+                __syncthreads();
+                for (int e = l; e < n * 2 * NE; e += 64) {
+                    const int i = e / (2 * NE), c = e - i * (2 * NE);
+                    const double2 v = RB[i * SW + c];
+                    RG[pis[i] * GW + (c < NE ? n + c : m + (c - NE))] = v;
+                }
+                for (int e = l; e < n * n; e += 64) {
+                    const int i = e / n, j = e - i * n;
+                    const double2 *wi = RB + i * SW + 2 * NE, *wj = RB + j * SW + 2 * NE;
+                    double2 acc = c_make(0.0, 0.0);
+                    for (int k = 0; k < n; k += 2)
+                        acc = c_fma(RR[k * WR + k + 1], c_sub(c_mul(wi[k], wj[k + 1]), c_mul(wi[k + 1], wj[k])), acc);
+                    RG[pis[i] * GW + m + NE + pis[j]] = c_neg(acc);
+                }
+                __syncthreads();
+            }
 #pragma unroll
             for (int q = 0; q < NTQ; ++q)
                 if (l + 64 * q < NT2) RR[l + 64 * q] = tv[q];
@@ -293,8 +336,6 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
             __syncthreads();
             for (int j = 0; j < KE; ++j) o = c_fma(tab.v[j], pfm[j], o);
             o = c_mul(o, pfk);
-            // ---------------- Y0, Y1, B_KK^{-1}
-            if (!gj_wave<8 * T>(RG, n, GW, l)) flag = true;
         }
         if (!flag) {
             // ---------------- A_p from the node inverses, four nodes at a time

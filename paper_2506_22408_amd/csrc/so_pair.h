@@ -156,12 +156,19 @@ __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, cons
 // Rl: the rows K of Z (n x WR complex, LDS); tv: this lane's trailing entries
 // (ta < tb) of the 2NE x 2NE block, updated in place; rbmax = 1 / max|B|^2.
 // Returns true when the pair needs the full-size path (zero pivot or growth);
-// pfk = Pf(B_KK).  Ends with a barrier.
+// pfk = Pf(B_KK).  Ends with a barrier.  The rows of R are left as they were
+// when each served as a pivot row, with the K columns in the final pivoted
+// order: rows k, k+1 of pair k/2 are then rows k, k+1 of U in
+// P B_KK P^T = L D L^T, U = D L^T (D: the 2 x 2 pivots [[0, a], [-a, 0]]).
+// With a non-null perm, lane i < n gets perm = the original index of pivoted
+// position i.
 template <int NE, int NTQ>
 __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const int (&ta)[NTQ], const int (&tb)[NTQ],
-                                              double2 (&tv)[NTQ], double bmax, double rbmax, int l, double2 &pfk) {
+                                              double2 (&tv)[NTQ], double bmax, double rbmax, int l, double2 &pfk,
+                                              int *perm = nullptr) {
     constexpr int NT2 = NE * (2 * NE - 1);
     pfk = c_make(1.0, 0.0);
+    int pi = l;
     bool zero = false;
     for (int k = 0; k < n; k += 2) {
         // partner: the largest |R[k][p]|, p in (k, n), smallest p on near-ties.
@@ -194,6 +201,7 @@ __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const 
             }
             __syncthreads();
             pfk = c_neg(pfk);
+            if (perm) pi = __shfl(pi, l == k + 1 ? p : (l == p ? k + 1 : l), 64);
         }
         const double2 a = Rl[k * WR + k + 1];
         pfk = c_mul(pfk, a);
@@ -233,6 +241,7 @@ __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const 
     for (int q = 0; q < NTQ; ++q) tmax = fmax(tmax, c_abs2(tv[q]));
     tmax = wave_max(fmax(tmax, gmax));
     const bool flag = zero || !(tmax <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * fmax(bmax, 1.0));
+    if (perm) *perm = pi;
     return flag;
 }
 
