@@ -233,10 +233,13 @@ def precision_leg(args, B, wl, torch, np):
         if ns > chunk:
             print(f"precision leg: oracle {b}/{ns} pairs, {time.perf_counter() - t0:.0f} s", file=sys.stderr,
                   flush=True)
+    scale = float(np.abs(ref).mean())
     for prec in ("fp64", "mixed"):
-        rel = np.abs(sample[prec] - ref) / np.abs(ref)
+        err = np.abs(sample[prec] - ref)
+        rel = err / np.abs(ref)
         res[prec]["pair_rel_err"] = {"median": float(np.median(rel)), "p99": float(np.quantile(rel, 0.99)),
-                                     "max": float(rel.max()), "frac_le_1e-6": float(np.mean(rel <= 1e-6))}
+                                     "max": float(rel.max()), "frac_le_1e-6": float(np.mean(rel <= 1e-6)),
+                                     "max_err_over_mean_abs_o": float(err.max() / scale)}
     res["sample"] = f"{ns} pairs drawn uniformly without replacement (seed 2024) of {w.W * w.S}"
     res["value"] = res["mixed"]["value"]
     res["speedup_mixed_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
