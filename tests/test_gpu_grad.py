@@ -3,9 +3,11 @@ CPU oracle's gradient, and with central finite differences of the HIP
 forward itself.
 
 Tolerances: S_w as in the forward (1e-10 relative); D_w and G_w per walker
-|x_gpu - x_oracle| <= 1e-9 max|x_oracle| (the derivative goes through matrix
-inverses, whose rounding is amplified by their condition number, on both
-sides); finite differences (h = 1e-6, central) to 1e-6 relative.
+|x_gpu - x_oracle| <= 1e-10 max|x_oracle| (observed: below 2e-13); central
+finite differences (h = 1e-6) to 1e-7 relative (their own truncation and
+rounding error is about 1e-8).  Shadows near a pair-preserving rotation,
+whose pair values nearly cancel, hold S_w to 1e-9 (D_w and G_w still to
+1e-10).
 """
 import numpy as np
 import pytest
@@ -40,10 +42,13 @@ def gpu_grad(B, phi, Q, bits):
 
 
 def close_per_walker(a, b, rtol):
+    worst = 0.0
     for w in range(a.shape[0]):
         scale = np.abs(b[w]).max()
         err = np.abs(a[w] - b[w]).max()
         assert err <= rtol * scale, f"walker {w}: err {err:.3e} vs scale {scale:.3e}"
+        worst = max(worst, err / scale)
+    return worst
 
 
 @pytest.mark.parametrize("n,eta,W,S", [
@@ -55,8 +60,8 @@ def test_grad_matches_oracle(B, n, eta, W, S):
     so, do, go = oracle.grad(w.phi, w.Q, w.bits)
     assert not st.any()
     assert np.all(np.abs(sg - so) <= 1e-10 * np.abs(so))
-    close_per_walker(dg, do, 1e-9)
-    close_per_walker(gg, go, 1e-9)
+    ed, eg = close_per_walker(dg, do, 1e-10), close_per_walker(gg, go, 1e-10)
+    print(f"n={n} eta={eta}: worst D {ed:.2e}, G {eg:.2e} (relative to max per walker)")
 
 
 def test_grad_finite_differences_of_the_gpu_forward(B):
@@ -77,7 +82,8 @@ def test_grad_finite_differences_of_the_gpu_forward(B):
             sm, _, _ = B.shadow_overlap(*to_dev(ph, w.Q, w.bits))
             fd = (sp.cpu().numpy() - sm.cpu().numpy()) / (2 * step)
             an = dg[:, p, j] * sg
-            assert np.all(np.abs(fd - an) <= 1e-6 * np.abs(an) + 1e-12), (p, j, step, fd, an)
+            assert np.all(np.abs(fd - an) <= 1e-7 * np.abs(an) + 1e-12), (p, j, step, fd, an)
+            print(f"FD ({p},{j}) step {step}: worst rel {np.max(np.abs(fd - an) / np.abs(an)):.2e}")
 
 
 def test_grad_full_size_route(B):
@@ -98,8 +104,8 @@ def test_grad_full_size_route(B):
     so, do, go = oracle.grad(phi, Qs, bits)
     assert not (st & ~B.SO_WSTAT_SINGULAR).any()
     assert np.all(np.abs(sg - so) <= 1e-9 * np.abs(so))
-    close_per_walker(dg, do, 1e-7)
-    close_per_walker(gg, go, 1e-7)
+    ed, eg = close_per_walker(dg, do, 1e-10), close_per_walker(gg, go, 1e-10)
+    print(f"full-size route: worst D {ed:.2e}, G {eg:.2e} (relative to max per walker)")
 
 
 def test_grad_unsupported_shapes_are_refused(B):
@@ -152,7 +158,7 @@ def test_autograd_log_overlap(B):
             ph[wi, p, j] -= 2 * step
             lm = loss(ph)
             num += unit * (lp - lm) / (2 * h)
-        assert abs(num - g[wi, p, j]) <= 1e-6 * max(abs(g[wi, p, j]), 1e-3), (wi, p, j, num, g[wi, p, j])
+        assert abs(num - g[wi, p, j]) <= 1e-7 * max(abs(g[wi, p, j]), 1e-3), (wi, p, j, num, g[wi, p, j])
 
 
 def test_grad_deterministic(B):
