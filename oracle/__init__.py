@@ -277,3 +277,47 @@ def force_bias(G, L, dt: float = 0.01) -> np.ndarray:
     G = np.asarray(G)
     W, n, _ = G.shape
     return -np.sqrt(dt) * 1j * (G.reshape(W, n * n) @ np.asarray(L).reshape(n * n, -1))
+
+
+def rdm1(Q, bits, weights=None, trial: bool = False):
+    """One-particle reduced density matrix from matchgate shadows
+    (Supp. "Reduced Density Matrices").
+
+    For a Majorana product of |S| = 2 operators the estimator of eq.
+    local_fermionic_ob_exp is C(2n,2)/C(n,1) pf(i C'_s|_S) = (2n - 1) i C'_s[mu][nu]
+    per shadow, with C'_s = Q_s^T C_b Q_s the shadow covariance, so
+    <gamma_mu gamma_nu> (mu != nu) is estimated by i M[mu][nu] with
+    M = (2n - 1) sum_s w_s C'_s (weights w_s, default 1/S).  The fermionic
+    elements follow from gamma_{2j-1} = a_j + a_j^dag, gamma_{2j} = -i (a_j - a_j^dag)
+    (eqs. majorana_op, 1rdm_off_diagonal, 1rdm_diagonal), written here 0-based
+    (mode p <-> Majoranas 2p, 2p+1):
+        <a_p^dag a_q> = 1/4 (<g_2p g_2q> + i <g_2p g_2q+1> - i <g_2p+1 g_2q> + <g_2p+1 g_2q+1>),  p != q
+        <a_p^dag a_p> = 1/2 (1 + i <g_2p g_2p+1>).
+    With trial=True the shadows are taken to be of (|0> + |Psi_T>)/sqrt2 and
+    the result is the trial state's matrix, twice the measured state's (a
+    number-conserving operator has no vacuum or cross term).
+
+    Returns (G [n, n] complex128 with G[p, q] = <a_p^dag a_q>, M [2n, 2n] real).
+    """
+    Q = _f64(Q)
+    bits = np.asarray(bits, dtype=np.uint64).reshape(-1)
+    S, d, _ = Q.shape
+    n = d // 2
+    w = np.full(S, 1.0 / S) if weights is None else np.asarray(weights, np.float64)
+    Cbar = np.zeros((d, d))
+    for s in range(S):
+        Cbar += w[s] * covariance(Q[s], int(bits[s]))
+    M = (2 * n - 1) * Cbar
+    np.fill_diagonal(M, 0.0)
+    g2 = 1j * M                        # <gamma_mu gamma_nu>, mu != nu
+    G = np.zeros((n, n), np.complex128)
+    for p in range(n):
+        for q in range(n):
+            if p == q:
+                G[p, p] = 0.5 * (1.0 + 1j * g2[2 * p, 2 * p + 1])
+            else:
+                G[p, q] = 0.25 * (g2[2 * p, 2 * q] + 1j * g2[2 * p, 2 * q + 1]
+                                  - 1j * g2[2 * p + 1, 2 * q] + g2[2 * p + 1, 2 * q + 1])
+    if trial:
+        G = 2.0 * G
+    return G, M

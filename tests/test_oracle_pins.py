@@ -177,14 +177,50 @@ def test_brute_snapshot_covariance():
 
 
 # ---------------------------------------------------------------- exact average
+_ENSEMBLE = {}
+
+
+def _signed_permutation_ensemble(n):
+    """Every det = +1 signed permutation Q of 2n Majoranas with, for each
+    outcome b, the projector prod_j (1 + beta_j M_j)/2 onto that outcome
+    (M_j = -i s s gamma_{pi(2j)} gamma_{pi(2j+1)}): lists of Q, b and the
+    dense projector, and the group order."""
+    if n in _ENSEMBLE:
+        return _ENSEMBLE[n]
+    d = 2 * n
+    g = brute.majoranas_dense(n)
+    dim = 1 << n
+    Qs, bl, projs = [], [], []
+    for perm in itertools.permutations(range(d)):
+        for sg in itertools.product([-1.0, 1.0], repeat=d):
+            Q = np.zeros((d, d))
+            Q[np.arange(d), perm] = sg
+            if np.linalg.det(Q) < 0:
+                continue
+            M = [-1j * sg[2 * j] * sg[2 * j + 1] * (g[perm[2 * j]] @ g[perm[2 * j + 1]]) for j in range(n)]
+            for bits in range(1 << n):
+                P = np.eye(dim, dtype=complex)
+                for j in range(n):
+                    beta = -1.0 if (bits >> j) & 1 else 1.0
+                    P = P @ (np.eye(dim) + beta * M[j]) / 2
+                Qs.append(Q)
+                bl.append(bits)
+                projs.append(P)
+    n_group = len(Qs) // (1 << n)
+    _ENSEMBLE[n] = (np.array(Qs), np.array(bl, np.uint64), np.array(projs), n_group)
+    return _ENSEMBLE[n]
+
+
+def _born(projs, Psi):
+    return np.einsum("i,kij,j->k", Psi.conj(), projs, Psi).real
+
+
 def test_exact_channel_average_signed_permutations():
     """n = 3, eta = 2: averaging o over every det=+1 signed permutation Q and
     every outcome b with its Born probability for |Psi> = (|0>+|Psi_T>)/sqrt2
     gives <Psi_T|phi> exactly (pins the factor 2 and the channel factors)."""
     n, eta = 3, 2
-    d = 2 * n
     rng = np.random.default_rng(42)
-    g = brute.majoranas_dense(n)
     dim = 1 << n
     psiT = np.zeros(dim, complex)
     two = [x for x in range(dim) if bin(x).count("1") == eta]
@@ -195,31 +231,47 @@ def test_exact_channel_average_signed_permutations():
     Psi = (vac + psiT) / np.sqrt(2)
     phi = wl.walkers(rng, 1, n, eta)[0]
     target = np.vdot(psiT, brute.slater_state(phi))
-    Qs, bl, probs = [], [], []
-    for perm in itertools.permutations(range(d)):
-        for sg in itertools.product([-1.0, 1.0], repeat=d):
-            Q = np.zeros((d, d))
-            Q[np.arange(d), perm] = sg
-            if np.linalg.det(Q) < 0:
-                continue
-            # bilinears M_j = -i s s gamma_{pi(2j)} gamma_{pi(2j+1)}; P(b) = <Psi| prod_j (1 + beta_j M_j)/2 |Psi>
-            M = [-1j * sg[2 * j] * sg[2 * j + 1] * (g[perm[2 * j]] @ g[perm[2 * j + 1]]) for j in range(n)]
-            for bits in range(1 << n):
-                P = np.eye(dim, dtype=complex)
-                for j in range(n):
-                    beta = -1.0 if (bits >> j) & 1 else 1.0
-                    P = P @ (np.eye(dim) + beta * M[j]) / 2
-                p = np.vdot(Psi, P @ Psi).real
-                if p > 1e-14:
-                    Qs.append(Q)
-                    bl.append(bits)
-                    probs.append(p)
-    Qs = np.array(Qs)
-    probs = np.array(probs)
-    n_group = 720 * 64 // 2
-    o = oracle.overlap_pairs(phi[None], Qs, np.array(bl, np.uint64))[0]
-    est = np.sum(probs * o) / n_group
+    Qs, bl, projs, n_group = _signed_permutation_ensemble(n)
+    probs = _born(projs, Psi)
+    keep = probs > 1e-14
+    o = oracle.overlap_pairs(phi[None], Qs[keep], bl[keep])[0]
+    est = np.sum(probs[keep] * o) / n_group
     assert abs(est - target) <= 1e-12 * max(1.0, abs(target))
+
+
+def test_rdm1_exact_channel_average_signed_permutations():
+    """n = 3: the 1-RDM estimator (Supp. "Reduced Density Matrices", |S| = 2)
+    averaged over every det=+1 signed permutation and every outcome with its
+    Born probability equals <Psi|a_p^dag a_q|Psi> (and -i<gamma_mu gamma_nu>)
+    from dense matrices, for a state mixing all particle numbers; with
+    trial=True and Psi = (|0> + |Psi_T>)/sqrt2 it gives Psi_T's matrix."""
+    n = 3
+    rng = np.random.default_rng(7)
+    dim = 1 << n
+    Qs, bl, projs, n_group = _signed_permutation_ensemble(n)
+    a = brute.annihilators_dense(n)
+    g = brute.majoranas_dense(n)
+
+    def dense_rdm(v):
+        return np.array([[np.vdot(v, a[p].conj().T @ a[q] @ v) for q in range(n)] for p in range(n)])
+
+    Psi = rng.standard_normal(dim) + 1j * rng.standard_normal(dim)
+    Psi /= np.linalg.norm(Psi)
+    G, M = oracle.rdm1(Qs, bl, weights=_born(projs, Psi) / n_group)
+    assert np.abs(G - dense_rdm(Psi)).max() <= 1e-12
+    Mref = np.array([[(-1j * np.vdot(Psi, g[m] @ g[v] @ Psi)).real if m != v else 0.0
+                      for v in range(2 * n)] for m in range(2 * n)])
+    assert np.abs(M - Mref).max() <= 1e-12
+
+    psiT = np.zeros(dim, complex)
+    two = [x for x in range(dim) if bin(x).count("1") == 2]
+    psiT[two] = rng.standard_normal(len(two)) + 1j * rng.standard_normal(len(two))
+    psiT /= np.linalg.norm(psiT)
+    vac = np.zeros(dim, complex)
+    vac[0] = 1
+    Gt, _ = oracle.rdm1(Qs, bl, weights=_born(projs, (vac + psiT) / np.sqrt(2)) / n_group, trial=True)
+    assert np.abs(Gt - dense_rdm(psiT)).max() <= 1e-12
+    assert abs(np.trace(Gt) - 2.0) <= 1e-12                 # particle number of Psi_T
 
 
 # ---------------------------------------------------------------- closed form
