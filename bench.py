@@ -246,6 +246,38 @@ def precision_leg(args, B, wl, torch, np):
     return res
 
 
+def rdm_leg(args, B, wl, torch, np, Q16, bits16):
+    """The one-particle density matrix from the shadows (so_rdm1): the
+    10,000 shadows of the main workload and the 50,000 of the n = 24 one.
+    Bound by HBM: the kernel reads every element of Q once, so the achieved
+    bandwidth is 8 (2n)^2 S bytes over the reduction kernel's time."""
+    out = {}
+    dev = torch.device("cuda:0")
+    cases = [("paper_n16", Q16, bits16)]
+    w24 = wl.config("precision_n24")
+    cases.append(("precision_n24", torch.from_numpy(w24.Q).to(dev), torch.from_numpy(w24.bits.view(np.int64)).to(dev)))
+    for name, Q, bits in cases:
+        S, d = Q.shape[0], Q.shape[1]
+        B.rdm1(Q, bits)
+        torch.cuda.synchronize()
+        B.profile_enable(True)
+        B.profile_read(B.PROF_RDM)
+        t0 = time.perf_counter()
+        for _ in range(args.rdm_steps):
+            G, _ = B.rdm1(Q, bits)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / args.rdm_steps
+        ms, launches, _ = B.profile_read(B.PROF_RDM)
+        B.profile_enable(False)
+        kern_s = ms / 1e3 / launches
+        qbytes = 8.0 * d * d * S
+        out[name] = {"ms_per_call": per * 1e3, "kernel_ms": kern_s * 1e3, "shadows": S, "n": d // 2,
+                     "particle_number_trial": float(torch.trace(G).real),
+                     "roofline": {"bound": "hbm", "kernel": "k_rdm_partial", "achieved": qbytes / kern_s / 1e9,
+                                  "peak": 8000.0, "unit": "GB/s", "frac": qbytes / kern_s / 1e9 / 8000.0}}
+    return {"metric": "one-particle density matrix from shadows", "steps": args.rdm_steps, "cases": out}
+
+
 def cpu_grad_baseline(wl, target_s=20.0):
     """The oracle's gradient on 16 walkers (one per host thread on the GPU
     host) x the first few shadows; the pilot overestimates, so the sample
@@ -277,6 +309,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--uneven-steps", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--no-rdm", action="store_true", help="skip the density-matrix leg")
+    ap.add_argument("--rdm-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device to device, three times (scales the HBM counters)")
     ap.add_argument("--precision-steps", type=int, default=2)
@@ -385,6 +419,8 @@ def main():
         rec["precision_n24"] = precision_leg(args, B, wl, torch, np)
     if not args.no_grad:
         rec["grad"] = grad_leg(args, B, wl, torch, np)
+    if not args.no_rdm:
+        rec["rdm1"] = rdm_leg(args, B, wl, torch, np, Q, bits)
     if not args.no_uneven:
         rec["uneven"] = uneven_leg(args, B, wl, torch, np)
     if not args.no_cpu_baseline:

@@ -197,6 +197,30 @@ so_status shadow_overlap_batched(const so_problem *probs, int n_probs, void *wor
  * so_batch_workspace_size(prob, 1). */
 so_status so_autotune(so_problem *prob, void *workspace, size_t workspace_bytes, void *stream);
 
+/* One-particle reduced density matrix from the shadows (Supp. "Reduced
+ * Density Matrices": eq. local_fermionic_ob_exp for a product of two
+ * Majoranas, whose channel factor is C(2n,2)/C(n,1) = 2n - 1, and eqs.
+ * majorana_op, 1rdm_off_diagonal, 1rdm_diagonal for the fermionic elements).
+ *   n          modes, 2 <= n <= so_max_n()
+ *   Q, bits    [n_shadows][2n][2n] float64 and [n_shadows] uint64 (device),
+ *              as in shadow_overlap
+ *   trial      0: the matrix of the measured state; 1: of the trial state
+ *              when the shadows are of (|0> + |Psi_T>)/sqrt2 (twice the
+ *              measured state's: a number-conserving operator has no vacuum
+ *              or cross term)
+ *   rdm        [n][n] complex128 out (device): rdm[p][q] = <a_p^dag a_q>,
+ *              modes 0-based (mode p <-> Majoranas 2p, 2p+1); its trace is the
+ *              particle number
+ *   majorana   [2n][2n] float64 out (device) or NULL: M[mu][nu] =
+ *              (2n - 1)/S sum_s C'_s[mu][nu], the estimate of -i<gamma_mu gamma_nu>
+ *              (mu != nu), zero diagonal
+ *   workspace  so_rdm1_workspace_size(n, n_shadows) bytes (device)
+ * Deterministic (fixed reduction order); enqueued on `stream`; no
+ * allocation or host synchronisation. */
+so_status so_rdm1_workspace_size(int n, int64_t n_shadows, size_t *bytes);
+so_status so_rdm1(int n, const double *Q, const uint64_t *bits, int64_t n_shadows, int trial, so_c64 *rdm,
+                  double *majorana, void *workspace, size_t workspace_bytes, void *stream);
+
 /* Force bias of every walker ("Force bias and local energy", eq. force_bias,
  * with the Cholesky vectors L^gamma of eq. cholesky_vec):
  *   xbar[w][gamma] = -sqrt(dt) i sum_pq L[p n + q][gamma] G_w[p][q].

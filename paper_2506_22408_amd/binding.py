@@ -73,6 +73,10 @@ def _load():
     lib.so_force_bias.argtypes = [c.c_void_p, c.c_int64, c.c_int, c.c_void_p, c.c_int64, c.c_double, c.c_void_p,
                                   c.c_void_p]
     lib.so_force_bias.restype = c.c_int
+    lib.so_rdm1_workspace_size.argtypes = [c.c_int, c.c_int64, c.POINTER(c.c_size_t)]
+    lib.so_rdm1_workspace_size.restype = c.c_int
+    lib.so_rdm1.argtypes = [c.c_int, P, P, c.c_int64, c.c_int, P, P, P, c.c_size_t, P]
+    lib.so_rdm1.restype = c.c_int
     lib.so_profile_enable.argtypes = [c.c_int]
     lib.so_profile_enable.restype = c.c_int
     lib.so_profile_read.argtypes = [c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
@@ -124,7 +128,7 @@ def node_weights(p: SoParams):
             np.array([complex(w[i].re, w[i].im) for i in range(k)]))
 
 
-PROF_PFAFF, PROF_FORM, PROF_PAIR, PROF_GRAD = 0, 1, 2, 3
+PROF_PFAFF, PROF_FORM, PROF_PAIR, PROF_GRAD, PROF_RDM = 0, 1, 2, 3, 4
 
 
 def profile_enable(on: bool = True) -> None:
@@ -238,6 +242,36 @@ def force_bias(green: torch.Tensor, L: torch.Tensor, dt: float = 0.01) -> torch.
     if st != SO_OK:
         raise ShadowOvError(st, "so_force_bias")
     return xbar
+
+
+def rdm1(Q: torch.Tensor, bits: torch.Tensor, *, trial: bool = True, with_majorana: bool = False,
+         workspace: torch.Tensor | None = None):
+    """One-particle density matrix <a_p^dag a_q> [n, n] complex128 from the
+    shadows (so_rdm1); with ``trial`` the shadows are taken to be of
+    (|0> + |Psi_T>)/sqrt2 and the trial state's matrix is returned.  Returns
+    (rdm, majorana [2n, 2n] float64 or None); the particle number is the
+    trace of rdm."""
+    if Q.dtype != torch.float64 or bits.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("Q must be float64 and bits 64-bit integers")
+    if not Q.is_cuda or not bits.is_cuda:
+        raise ValueError("Q and bits must be device tensors")
+    if Q.dim() != 3 or Q.shape[1] != Q.shape[2] or Q.shape[1] % 2 or bits.shape != (Q.shape[0],):
+        raise ValueError("Q must be [S, 2n, 2n] and bits [S]")
+    S, n = Q.shape[0], Q.shape[1] // 2
+    Q, bits = Q.contiguous(), bits.contiguous()
+    nbytes = ctypes.c_size_t(0)
+    st = lib.so_rdm1_workspace_size(n, S, ctypes.byref(nbytes))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_rdm1_workspace_size")
+    ws = workspace if workspace is not None else _workspace(int(nbytes.value), Q.device)
+    rdm = torch.empty((n, n), dtype=torch.complex128, device=Q.device)
+    maj = torch.empty((2 * n, 2 * n), dtype=torch.float64, device=Q.device) if with_majorana else None
+    stream = torch.cuda.current_stream(Q.device).cuda_stream
+    st = lib.so_rdm1(n, _dev_ptr(Q), _dev_ptr(bits), S, int(bool(trial)), _dev_ptr(rdm), _dev_ptr(maj),
+                     _dev_ptr(ws), ws.numel(), ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_rdm1")
+    return rdm, maj
 
 
 class ShadowLogOverlap(torch.autograd.Function):

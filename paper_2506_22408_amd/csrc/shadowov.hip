@@ -42,6 +42,7 @@
 #include "so_grad.h"
 #include "so_force.h"
 #include "so_batch.h"
+#include "so_rdm.h"
 
 // --------------------------------------------------------------------------
 // k_reduce: S_w = (1/S) sum_s o_ws, fixed order: lane l sums s = l, l+64, ...
@@ -283,6 +284,7 @@ constexpr size_t kSChunkBytes = (size_t)512 << 20;   // budget for one chunk of 
 constexpr int FB_GRID = 256;                           // blocks of the fallback kernel
 constexpr int kFormShadowsPerWave = 8;                 // shadows per formation wave
 constexpr int kPairBatchesPerWave = 2;                 // node batches per fused wave
+constexpr int64_t kRdmBlocks = 2048;                    // blocks of the density-matrix reduction
 
 struct Layout {
     size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_fbB, off_F, off_O;
@@ -492,7 +494,7 @@ hipError_t launch_nodes(int M2, const double2 *Sb, const double2 *Pb, const Node
 }
 
 // ---- optional per-kernel timing (benchmarks): HIP events around launches
-enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_GRAD = 3, PROF_NKIND = 4 };
+enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_GRAD = 3, PROF_RDM = 4, PROF_NKIND = 5 };
 struct ProfRec { hipEvent_t a, b; int kind; int64_t units; };
 struct ProfState {
     bool on = false;
@@ -766,6 +768,23 @@ bool problem_ok(const so_problem &pr) {
            pr.overlap;
 }
 
+// one-particle density matrix: blocks of the partial kernel and their shadows
+struct RdmPlan {
+    int T, DP;
+    int64_t blocks, spb;
+    size_t bytes;
+};
+RdmPlan rdm_plan(int n, int64_t S) {
+    RdmPlan r;
+    r.T = so_tiles(n);
+    r.DP = 16 * r.T;
+    r.blocks = S < kRdmBlocks ? S : kRdmBlocks;
+    r.spb = (S + r.blocks - 1) / r.blocks;
+    r.blocks = (S + r.spb - 1) / r.spb;
+    r.bytes = (size_t)(r.blocks + 1) * r.DP * r.DP * sizeof(double);
+    return r;
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -887,6 +906,38 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
                        reinterpret_cast<double2 *>(green), wst);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     return SO_OK;
+}
+
+so_status so_rdm1_workspace_size(int n, int64_t n_shadows, size_t *bytes) {
+    if (!bytes || n < 2 || n > SO_NMAX_SUPPORTED || n_shadows < 1) return SO_ERR_ARG;
+    *bytes = rdm_plan(n, n_shadows).bytes;
+    return SO_OK;
+}
+
+so_status so_rdm1(int n, const double *Q, const uint64_t *bits, int64_t n_shadows, int trial, so_c64 *rdm,
+                  double *majorana, void *workspace, size_t workspace_bytes, void *stream) {
+    if (!Q || !bits || !rdm || n < 2 || n > SO_NMAX_SUPPORTED || n_shadows < 1) return SO_ERR_ARG;
+    const RdmPlan r = rdm_plan(n, n_shadows);
+    if (!workspace || workspace_bytes < r.bytes) return SO_ERR_WORKSPACE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    double *part = static_cast<double *>(workspace);
+    double *Xsum = part + (size_t)r.blocks * r.DP * r.DP;
+    hipEvent_t ea = nullptr;
+    if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
+    switch (r.T) {
+        case 1: hipLaunchKernelGGL(k_rdm_partial<1>, dim3((unsigned)r.blocks), dim3(256), 0, st, n, Q, bits, n_shadows, r.spb, part); break;
+        case 2: hipLaunchKernelGGL(k_rdm_partial<2>, dim3((unsigned)r.blocks), dim3(256), 0, st, n, Q, bits, n_shadows, r.spb, part); break;
+        case 3: hipLaunchKernelGGL(k_rdm_partial<3>, dim3((unsigned)r.blocks), dim3(256), 0, st, n, Q, bits, n_shadows, r.spb, part); break;
+        default: return SO_ERR_UNSUPPORTED;
+    }
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    if (prof_end(st, ea, PROF_RDM, n_shadows) != hipSuccess) return SO_ERR_HIP;
+    const int dp2 = r.DP * r.DP;
+    hipLaunchKernelGGL(k_rdm_sum, dim3((unsigned)((dp2 + 63) / 64)), dim3(1024), 0, st, dp2, (int)r.blocks, part, Xsum);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    hipLaunchKernelGGL(k_rdm_out, dim3(1), dim3(256), 0, st, n, r.DP, Xsum, (2.0 * n - 1.0) / (double)n_shadows,
+                       trial ? 2.0 : 1.0, majorana, reinterpret_cast<double2 *>(rdm));
+    return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
 }
 
 so_status so_force_bias(const so_c64 *green, int64_t n_walkers, int n, const double *L, int64_t n_gamma,
