@@ -2,20 +2,27 @@
 """Benchmark: walker x shadow overlaps per second on one MI355X.
 
 One step = one call of the whole hot path (walker prep, shadow prep, pair
-formation, node Pfaffians, reduction over shadows) on the paper-sized
-workload: N = 16 qubits, eta = 8 electrons, 1,024 walkers, 10,000 Haar SO(32)
-shadows with even-parity bitstrings, n + 1 = 17 interpolation nodes, FP64;
-seeded synthetic inputs already resident in HBM.
+formation, elimination and node Pfaffians, reduction over shadows) on the
+paper-sized workload: N = 16 qubits, eta = 8 electrons, 1,024 walkers, 10,000
+Haar SO(32) shadows with even-parity bitstrings, n + 1 = 17 interpolation
+nodes, FP64; seeded synthetic inputs already resident in HBM.
 
 Prints one JSON line.  ``roofline`` is for the dominant kernel, timed with
 HIP events around each of its launches on the stream it runs on.  When n - eta
-is even and at most 8 (the paper's N = 16, eta = 8 included) that is the fused
-pair kernel ``k_pair`` (formation, elimination, node Pfaffians), whose
-algorithmic flops per pair are the method's formation plus Pfaffian count,
-16 n^2 m + 8 n m^2 + K (4/3) m^3 (m = 2n - eta, K = n + 1; 485k at N = 16);
-otherwise the node-Pfaffian kernel with K (4/3) m^3.  The peak is the FP64
-peak (vector and matrix alike 78.6 TFLOP/s).  ``cpu_baseline`` times the FP64
-CPU oracle on a bounded sample of the same workload.
+is even and at most 12 (the paper's N = 16, eta = 8 included) that is the
+fused pair kernel ``k_pair``, whose algorithmic flops per pair are the
+method's formation plus Pfaffian count, 16 n^2 m + 8 n m^2 + K (4/3) m^3
+(m = 2n - eta, K = n + 1; 485k at N = 16); otherwise the node-Pfaffian kernel
+with K (4/3) m^3.  The peak is the FP64 peak (vector and matrix alike 78.6
+TFLOP/s).  ``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of
+the same workload.
+
+Further legs (each can be skipped): ``mixed`` (the same workload with the
+single-precision formation), ``precision_n24`` (FP64 and mixed on the n = 24
+workload with sampled pair errors against the oracle), ``grad`` (derivative
+and force bias, with its own oracle baseline), ``rdm1`` (density matrix from
+the shadows, HBM-bound) and ``uneven`` (four geometries in one batched call,
+graph-replayed, FP64 and mixed, beside separate calls).
 """
 from __future__ import annotations
 
@@ -161,9 +168,27 @@ def uneven_leg(args, B, wl, torch, np):
     for st in bt.status:
         if int(st.abs().sum()) != 0:
             raise RuntimeError("uneven batch reported a numerical status")
+    # the same batch with the single-precision formation, autotuned and replayed
+    bm = B.Batch([dict(pr, precision="mixed") for pr in probs])
+    bm.autotune()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bm.run()
+    torch.cuda.current_stream().wait_stream(side)
+    gm = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gm):
+        bm.run()
+    gm.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.uneven_steps):
+        gm.replay()
+    torch.cuda.synchronize()
+    t_mixed = (time.perf_counter() - t0) / args.uneven_steps
     return {"metric": "walker x shadow overlaps/s, uneven batch", "value": pairs / t_graph, "unit": "overlaps/s",
             "ms_per_step": t_graph * 1e3, "steps": args.uneven_steps, "pairs_per_step": pairs,
             "plain_calls": {"value": pairs / t_plain, "ms_per_step": t_plain * 1e3},
+            "mixed_graph": {"value": pairs / t_mixed, "ms_per_step": t_mixed * 1e3},
             "tuning": [{"n": c["n"], "shadows_per_item": k[0], "waves_per_cu": k[1]}
                        for c, k in zip(wl.UNEVEN, knobs)],
             "config": {"workload": "uneven_4_geometries", "n": [c["n"] for c in wl.UNEVEN],
@@ -278,18 +303,18 @@ def rdm_leg(args, B, wl, torch, np, Q16, bits16):
     return {"metric": "one-particle density matrix from shadows", "steps": args.rdm_steps, "cases": out}
 
 
-def cpu_grad_baseline(wl, target_s=20.0):
+def cpu_grad_baseline(wl, target_s=15.0):
     """The oracle's gradient on 16 walkers (one per host thread on the GPU
-    host) x the first few shadows; the pilot overestimates, so the sample
-    lands near 10 s."""
+    host) x the first s shadows, s sized from a 64-shadow pilot to about
+    target_s seconds."""
     import oracle
     g = wl.config("grad_n16")
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    Wb = 16
+    Wb, sp = 16, 64
     t = time.perf_counter()
-    oracle.grad(g.phi[:Wb], g.Q[:4], g.bits[:4], nthreads=nthreads)
-    pilot = max(time.perf_counter() - t, 1e-3) / (4 * Wb)
-    s = int(max(4, min(g.S, target_s / (pilot * Wb))))
+    oracle.grad(g.phi[:Wb], g.Q[:sp], g.bits[:sp], nthreads=nthreads)
+    pilot = max(time.perf_counter() - t, 1e-3) / (sp * Wb)
+    s = int(max(sp, min(g.S, target_s / (pilot * Wb))))
     t = time.perf_counter()
     oracle.grad(g.phi[:Wb], g.Q[:s], g.bits[:s], nthreads=nthreads)
     dt = time.perf_counter() - t
