@@ -108,6 +108,23 @@ def test_grad_full_size_route(B):
     print(f"full-size route: worst D {ed:.2e}, G {eg:.2e} (relative to max per walker)")
 
 
+def test_grad_zero_overlap_is_flagged(B):
+    """Walkers whose orbitals are single modes, with the identity shadow and
+    b = 0, give pair values that are exactly zero, so S_w = 0: the walker is
+    flagged and its derivative (of log S_w) is NaN, not a number."""
+    n, eta, W = 8, 4, 3
+    rng = np.random.default_rng(2)
+    phi = np.zeros((W, n, eta), complex)
+    for w in range(W):
+        phi[w, rng.choice(n, eta, replace=False), np.arange(eta)] = 1.0
+    Q = np.tile(np.eye(2 * n), (5, 1, 1))
+    bits = np.zeros(5, np.uint64)
+    sg, dg, gg, st = gpu_grad(B, phi, Q, bits)
+    assert np.all(sg == 0)
+    assert np.all(st & B.SO_WSTAT_ZERO)
+    assert np.all(np.isnan(dg)) and np.all(np.isnan(gg))
+
+
 def test_grad_unsupported_shapes_are_refused(B):
     for n, eta in ((16, 2), (20, 16), (9, 4)):       # ne = 14; n > 16; ne odd
         w = wl.make("u", n, eta, 2, 3, seed=1)
