@@ -180,6 +180,11 @@ def test_edge_cases(B):
     phi4[0, 0, 0] = np.nan
     sg4, _, st4 = gpu_overlap(B, phi4, Q, bits)
     assert st4[0] & B.SO_WSTAT_NONFINITE and not np.isfinite(sg4[0])
+    # a non-finite shadow reaches every walker
+    Q5 = Q.copy()
+    Q5[1, 0, 0] = np.nan
+    sg5, _, st5 = gpu_overlap(B, phi, Q5, bits)
+    assert np.all(st5 & B.SO_WSTAT_NONFINITE) and not np.isfinite(sg5).any()
 
 
 def test_gpu_multilinearity_full_size(B):
