@@ -344,7 +344,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one MI355X only; multi-GPU runs are not part of it "
+        print("bench.py: this benchmark measures one MI355X only; multi-GPU runs are not part of it "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE={world})", file=sys.stderr)
         sys.exit(2)
 
