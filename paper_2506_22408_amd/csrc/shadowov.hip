@@ -284,6 +284,10 @@ constexpr size_t kSChunkBytes = (size_t)512 << 20;   // budget for one chunk of 
 constexpr int FB_GRID = 256;                           // blocks of the fallback kernel
 constexpr int kFormShadowsPerWave = 8;                 // shadows per formation wave
 constexpr int kPairBatchesPerWave = 2;                 // node batches per fused wave
+#ifndef SO_ROW_BATCHES_PER_WAVE
+#define SO_ROW_BATCHES_PER_WAVE 8
+#endif
+constexpr int kRowBatchesPerWave = SO_ROW_BATCHES_PER_WAVE;   // the same for ne > 8 (single-pair batches)
 constexpr int64_t kRdmBlocks = 2048;                    // blocks of the density-matrix reduction
 
 struct Layout {
@@ -414,8 +418,8 @@ template <int T, int NE, bool MIX>
 hipError_t launch_pair_tn(int n, int eta, const void *Xa, const void *Ca, int64_t W, int64_t S,
                           const RedTab &rt, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap,
                           int32_t *wst, hipStream_t st) {
-    constexpr int NB = 64 / (NE + 1);
-    const int spw = NB * kPairBatchesPerWave;
+    constexpr int NB = pair_node_batch(NE);
+    const int spw = NB * (NE > 8 ? kRowBatchesPerWave : kPairBatchesPerWave);
     const size_t lds = pair_lds_bytes(T, n, NE);
     const int64_t ny = (S + spw - 1) / spw;
     for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
@@ -657,7 +661,7 @@ int device_cus() {
 }
 
 // node batch of the fused kernel (pairs whose nodes run together)
-int node_batch(int ne) { return 64 / (ne + 1); }
+int node_batch(int ne) { return pair_node_batch(ne); }
 
 int item_shadows(const so_problem &pr, int ne) {
     const int nb = node_batch(ne);

@@ -35,6 +35,10 @@
 #include "so_form.h"
 #include "so_nodes.h"
 
+#ifndef SO_ROW_NODE_BATCH
+#define SO_ROW_NODE_BATCH 1
+#endif
+
 // ---- per-lane Householder Pfaffian of an N x N complex skew matrix -----------
 // A[i][j] for i < j holds the matrix (the rest is implied).  At even step k the
 // column c_i = A[i][k] = -A[k][i] (i > k) is mapped to alpha e_{k+1}, alpha =
@@ -275,12 +279,20 @@ __device__ __forceinline__ double2 pencil_pf_row(const double2 *slot, double2 c,
     return pf;
 }
 
+// Pairs whose node Pfaffians run together.  Up to ne = 8 a lane takes one
+// (pair, node), so 64 / (ne + 1) pairs fill the wave; above, a 16-lane row
+// takes one (pair, node) and a pass takes four whatever the batch, so a
+// single pair per batch still keeps most rows busy and saves the LDS of the
+// other slots: at n = 24 (three tiles, ne = 12) 7 waves per CU fit instead
+// of 5, which measured 1.19x faster than a batch of 4 (1.24x at n = 20).
+__host__ __device__ constexpr int pair_node_batch(int ne) { return ne <= 8 ? 64 / (ne + 1) : SO_ROW_NODE_BATCH; }
+
 // LDS per wave: region A = max(P ((DP+1) x (DP+1) f64), R (n x (n + 2 NE) c128),
 // T (NE (2NE - 1) c128), node values), then the batch: NB slots of
 // 3 NE (NE-1)/2 + 1 complex (M0, M1, M2 upper triangles, Pf(B_KK)).
 __host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
     const int DP = 16 * T;
-    const int NB = 64 / (NE + 1);
+    const int NB = pair_node_batch(NE);
     size_t a = (size_t)(DP + 1) * (DP + 1) * sizeof(double);
     const size_t r = (size_t)n * (n + 2 * NE) * sizeof(double2);
     const size_t t = (size_t)NE * (2 * NE - 1) * sizeof(double2);
@@ -306,7 +318,7 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
     constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
     constexpr size_t MATB = (size_t)DP * DP * (MIX ? sizeof(float) : sizeof(double));   // bytes per matrix
     constexpr int KE = NE + 1;
-    constexpr int NB = 64 / KE;
+    constexpr int NB = pair_node_batch(NE);
     constexpr int NT = NE * (NE - 1) / 2;         // upper entries of one NE x NE matrix
     constexpr int NT2 = NE * (2 * NE - 1);        // upper entries of the 2NE x 2NE trailing block
     constexpr int NTQ = (NT2 + 63) / 64;          // trailing entries per lane
@@ -497,7 +509,7 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
 }
 
 // grid (W, ceil(S_total / spw)) from shadow group sy0, one wave per block;
-// spw is a multiple of 64 / (NE + 1).  At least two waves per SIMD: the
+// spw is a multiple of pair_node_batch(NE).  At least two waves per SIMD: the
 // three-tile instances would otherwise take more than 256 registers.
 template <int T, int NE, bool MIX>
 __global__ __launch_bounds__(64, 2) void k_pair(int n, int eta, const void *__restrict__ Xa,

@@ -87,7 +87,7 @@ def test_autotune_returns_valid_knobs(B):
     for w, (spi, wpc) in zip(ws, knobs):
         ne = w.n - w.eta
         if ne % 2 == 0 and 2 <= ne <= 12:
-            nb = 64 // (ne + 1)
+            nb = 64 // (ne + 1) if ne <= 8 else 1         # node batch of the fused kernel
             assert spi % nb == 0 and spi // nb in (1, 2, 4, 8) and wpc in (4, 8, 16)
         else:
             assert (spi, wpc) == (0, 0)
