@@ -17,6 +17,9 @@ Parts
   2^n state vectors (n <= 8).
 * :mod:`oracle.closed_form`: the exact value for signed-permutation shadows
   (a weighted sum of eta x eta minors), usable up to n ~ 20.
+* :mod:`oracle.vce`: the virtual-correlation-energy prologue (full-space
+  walker -> active walker and prefactor, Supp. "Virtual Correlation Energy
+  Derivation") and the plain full-space determinant expansion it is pinned to.
 """
 from __future__ import annotations
 

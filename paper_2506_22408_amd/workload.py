@@ -17,6 +17,11 @@ Recipe (numpy ``default_rng(seed)``, PCG64, drawn in this order):
                  (uniform over even-parity strings); bit j is b_{j+1} [S] u64
   L        Cholesky-like vectors, N(0, 0.1^2), symmetrised per index pair
                                                                   [n*n, n_gamma]
+
+Full-space walkers for the virtual-correlation-energy path (make_vce), drawn
+after nothing else from their own seed: alpha, then beta orbitals, each the
+reduced QR of (Z1 + i Z2) of shape [W, N_B, N_c + n_spin]; then Q and b of
+the active space (n = 2 N_a modes) as above.
 """
 from __future__ import annotations
 
@@ -115,3 +120,63 @@ def config(name: str, W: int | None = None, S: int | None = None) -> Workload:
     if S is not None:
         c["S"] = S
     return make(name, **c)
+
+
+@dataclass
+class VceWorkload:
+    """Full-space walkers (alpha and beta orbital blocks over N_B spatial
+    orbitals: core 0..N_c-1, active N_c..N_c+N_a-1, then virtual) and the
+    shadows of the 2 N_a-mode active space."""
+    name: str
+    n_basis: int
+    n_core: int
+    n_active: int
+    n_alpha: int
+    n_beta: int
+    phi_alpha: np.ndarray
+    phi_beta: np.ndarray
+    Q: np.ndarray
+    bits: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return 2 * self.n_active
+
+    @property
+    def eta(self) -> int:
+        return self.n_alpha + self.n_beta
+
+    @property
+    def W(self) -> int:
+        return self.phi_alpha.shape[0]
+
+    @property
+    def S(self) -> int:
+        return self.Q.shape[0]
+
+
+def make_vce(name: str, n_basis: int, n_core: int, n_active: int, n_alpha: int, n_beta: int, W: int, S: int,
+             seed: int, orthonormal: bool = True) -> VceWorkload:
+    rng = np.random.default_rng(seed)
+    pa = walkers(rng, W, n_basis, n_core + n_alpha, orthonormal)
+    pb = walkers(rng, W, n_basis, n_core + n_beta, orthonormal)
+    n = 2 * n_active
+    Q = haar_so(rng, S, 2 * n)
+    bits = even_bits(rng, S, n)
+    return VceWorkload(name, n_basis, n_core, n_active, n_alpha, n_beta, pa, pb, Q, bits)
+
+
+# N_B = 130 spatial orbitals and the (8e, 8o) active space are the paper's; it
+# gives no core count, and 46 doubly occupied core orbitals is a stand-in.
+VCE_CONFIGS = {
+    "vce_n16": dict(n_basis=130, n_core=46, n_active=8, n_alpha=4, n_beta=4, W=1024, S=10000, seed=6),
+}
+
+
+def vce_config(name: str, W: int | None = None, S: int | None = None) -> VceWorkload:
+    c = dict(VCE_CONFIGS[name])
+    if W is not None:
+        c["W"] = W
+    if S is not None:
+        c["S"] = S
+    return make_vce(name, **c)
