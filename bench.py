@@ -21,8 +21,9 @@ Further legs (each can be skipped): ``mixed`` (the same workload with the
 single-precision formation), ``precision_n24`` (FP64 and mixed on the n = 24
 workload with sampled pair errors against the oracle), ``grad`` (derivative
 and force bias, with its own oracle baseline), ``rdm1`` (density matrix from
-the shadows, HBM-bound) and ``uneven`` (four geometries in one batched call,
-graph-replayed, FP64 and mixed, beside separate calls).
+the shadows, HBM-bound), ``vce`` (full-space overlaps through the
+virtual-correlation-energy prologue) and ``uneven`` (four geometries in one
+batched call, graph-replayed, FP64 and mixed, beside separate calls).
 """
 from __future__ import annotations
 
@@ -303,6 +304,53 @@ def rdm_leg(args, B, wl, torch, np, Q16, bits16):
     return {"metric": "one-particle density matrix from shadows", "steps": args.rdm_steps, "cases": out}
 
 
+def vce_leg(args, B, wl, torch, np):
+    """Full-space overlaps through the virtual-correlation-energy prologue
+    (so_vce_overlap): N_B = 130 spatial orbitals, 46 core, the (8e, 8o)
+    active space, 1,024 walkers x 10,000 shadows.  One step = the prologue
+    kernel (active walkers and prefactors), the active-space overlap path and
+    the prefactor scaling.  The prologue reads the core and active rows of
+    each spin once, (N_c + N_a)(N_c + n_spin) complex entries, and writes the
+    active walker and the prefactor; its achieved bandwidth is those bytes
+    over its launch time (it is latency-bound: a chain of reflections per
+    walker)."""
+    dev = torch.device("cuda:0")
+    w = wl.vce_config("vce_n16")
+    pa = torch.from_numpy(w.phi_alpha).to(dev)
+    pb = torch.from_numpy(w.phi_beta).to(dev)
+    Q = torch.from_numpy(w.Q).to(dev)
+    bits = torch.from_numpy(w.bits.view(np.int64)).to(dev)
+    B.vce_overlap(pa, pb, w.n_core, w.n_active, Q, bits)
+    torch.cuda.synchronize()
+    B.profile_enable(True)
+    for k in (B.PROF_VCE, B.PROF_PAIR):
+        B.profile_read(k)
+    t0 = time.perf_counter()
+    for _ in range(args.vce_steps):
+        o, pref, st = B.vce_overlap(pa, pb, w.n_core, w.n_active, Q, bits)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / args.vce_steps
+    ms_v, l_v, units_v = B.profile_read(B.PROF_VCE)
+    ms_p, l_p, _ = B.profile_read(B.PROF_PAIR)
+    B.profile_enable(False)
+    if int(st.abs().sum()) != 0 or not bool(torch.isfinite(o.real).all()):
+        raise RuntimeError("VCE run reported a numerical status")
+    nc, na = w.n_core, w.n_active
+    per_walker = 16 * ((nc + na) * (nc + w.n_alpha) + (nc + na) * (nc + w.n_beta) + 2 * na * w.eta + 1)
+    pro_s = ms_v / 1e3 / l_v
+    gbs = per_walker * (units_v / l_v) / pro_s / 1e9
+    return {"metric": "full-space (VCE) walker×shadow overlaps/s", "value": w.W * w.S / per, "unit": "overlaps/s",
+            "steps": args.vce_steps, "ms_per_step": per * 1e3,
+            "config": {"workload": "vce_n16", "n_basis": w.n_basis, "n_core": nc, "n_active": na,
+                       "n_alpha": w.n_alpha, "n_beta": w.n_beta, "walkers": w.W, "shadows": w.S},
+            "prologue": {"kernel": "k_vce_prep", "ms": pro_s * 1e3, "walkers_per_s": (units_v / l_v) / pro_s,
+                         "bytes_per_walker": per_walker,
+                         "roofline": {"bound": "latency", "achieved": gbs, "peak": 8000.0, "unit": "GB/s",
+                                      "frac": gbs / 8000.0}},
+            "k_pair_ms": ms_p / l_p if l_p else None,
+            "prologue_share": pro_s / per}
+
+
 def cpu_grad_baseline(wl, target_s=15.0):
     """The oracle's gradient on 16 walkers (one per host thread on the GPU
     host) x the first s shadows, s sized from a 64-shadow pilot to about
@@ -336,6 +384,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--no-rdm", action="store_true", help="skip the density-matrix leg")
     ap.add_argument("--rdm-steps", type=int, default=5)
+    ap.add_argument("--no-vce", action="store_true", help="skip the full-space (VCE) leg")
+    ap.add_argument("--vce-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device to device, three times (scales the HBM counters)")
     ap.add_argument("--precision-steps", type=int, default=2)
@@ -446,6 +496,8 @@ def main():
         rec["grad"] = grad_leg(args, B, wl, torch, np)
     if not args.no_rdm:
         rec["rdm1"] = rdm_leg(args, B, wl, torch, np, Q, bits)
+    if not args.no_vce:
+        rec["vce"] = vce_leg(args, B, wl, torch, np)
     if not args.no_uneven:
         rec["uneven"] = uneven_leg(args, B, wl, torch, np)
     if not args.no_cpu_baseline:

@@ -221,6 +221,62 @@ so_status so_rdm1_workspace_size(int n, int64_t n_shadows, size_t *bytes);
 so_status so_rdm1(int n, const double *Q, const uint64_t *bits, int64_t n_shadows, int trial, so_c64 *rdm,
                   double *majorana, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Virtual correlation energy (section "Virtual correlation energy", eq.
+ * vce_overlap; Supp. "Virtual Correlation Energy Derivation"): overlaps of
+ * full-space walkers with the trial state |Xi_c^a Xi_c^b> (x) |Psi_T,a> (x)
+ * |0_v>, whose frozen core fills spatial orbitals 0..n_core-1 of each spin,
+ * whose active part |Psi_T,a> (the state the shadows are of) lives on the
+ * active orbitals n_core..n_core+n_active-1, and whose virtual orbitals
+ * (the rest of the n_basis) are empty.  The 2 n_active active modes are
+ * ordered alpha orbitals first, then beta; the trial state's creation order
+ * is core alpha, core beta, active alpha, active beta, as in the paper's
+ * first determinant. */
+typedef struct {
+    int n_basis;   /* N_B spatial orbitals of the full space */
+    int n_core;    /* frozen doubly occupied core orbitals, >= 0 */
+    int n_active;  /* active spatial orbitals, 1..12 (n = 2 n_active modes) */
+    int n_alpha;   /* active alpha electrons, 0..n_active */
+    int n_beta;    /* active beta electrons, 0..n_active (n_alpha + n_beta >= 1) */
+} so_vce_dims;
+
+/* The per-walker prologue: from the full-space walker (alpha and beta
+ * orbital blocks) to the active-space walker phi~_a and the prefactor c_w
+ * with <Psi_T|phi_w> = c_w <Psi_T,a|phi~_a,w>.  The paper's c_w is
+ * det(Sigma^a) det(Sigma^b) det(R^a) det(R^b) / (det(U^dag) det(V)), from
+ * an SVD of each spin's core rows and a QR of its projected active rows;
+ * the kernel gets the same value from Householder reflections (an LQ
+ * factorisation of the core rows, then a QR), one wave per walker.
+ *   phi_alpha  [n_walkers][n_basis][n_core + n_alpha] complex128 (device),
+ *              row-major: orbital coefficients, core rows first
+ *   phi_beta   [n_walkers][n_basis][n_core + n_beta]  complex128 (device)
+ *   active_phi [n_walkers][2 n_active][n_alpha + n_beta] complex128 out
+ *              (device): diag(Q^a, Q^b), orthonormal columns, alpha first
+ *   prefactor  [n_walkers] complex128 out (device)
+ * Only the core and active rows are read.  A core block (or projected
+ * active block) with an exactly zero row (column) norm gives c_w = 0 and
+ * an orthonormal phi~_a; non-finite inputs propagate.  Limits: the matrices
+ * of one spin, (n_core + n_active)(n_core + max(n_alpha, n_beta)) complex
+ * entries plus the reflectors, fit 64 KiB of LDS (n_core <= 57 at the
+ * paper's (8e, 8o)); otherwise SO_ERR_ARG.  Enqueued on `stream`; no
+ * allocation. */
+so_status so_vce_walkers(const so_vce_dims *dims, const so_c64 *phi_alpha, const so_c64 *phi_beta,
+                         int64_t n_walkers, so_c64 *active_phi, so_c64 *prefactor, void *stream);
+
+/* Workspace of so_vce_overlap: that of shadow_overlap for (n, eta) =
+ * (2 n_active, n_alpha + n_beta), plus the active walkers and prefactors. */
+so_status so_vce_workspace_size(const so_params *p, const so_vce_dims *dims, int64_t n_walkers,
+                                int64_t n_shadows, size_t *bytes);
+
+/* Full-space overlaps: the prologue above, shadow_overlap on the active
+ * walkers (p->n must be 2 n_active and p->eta n_alpha + n_beta), then
+ * overlap[w] = c_w S_w.  prefactor [n_walkers] (device) receives c_w, or
+ * NULL; status as in shadow_overlap.  All arguments are checked before
+ * anything is enqueued. */
+so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c64 *phi_alpha,
+                         const so_c64 *phi_beta, int64_t n_walkers, const double *Q, const uint64_t *bits,
+                         int64_t n_shadows, so_c64 *overlap, so_c64 *prefactor, int32_t *status,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
 /* Force bias of every walker ("Force bias and local energy", eq. force_bias,
  * with the Cholesky vectors L^gamma of eq. cholesky_vec):
  *   xbar[w][gamma] = -sqrt(dt) i sum_pq L[p n + q][gamma] G_w[p][q].
@@ -235,12 +291,14 @@ so_status so_force_bias(const so_c64 *green, int64_t n_walkers, int n, const dou
  * so_profile_enable(1) makes every later shadow_overlap call bracket each
  * launch of its node-Pfaffian kernel (kind 0), of its formation kernel
  * (kind 1) and of its fused pair kernel (kind 2; formation, elimination and
- * node Pfaffians in one launch, used when n - eta is even and at most 8), and
+ * node Pfaffians in one launch, used when n - eta is even, 2..12), and
  * every shadow_overlap_grad call its per-pair adjoint kernel (kind 3), with
  * HIP events recorded on the call's stream.  so_profile_read
  * waits for the recorded events of one kind, returns their summed duration
  * in milliseconds, the number of launches and the number of walker x shadow
- * pairs those launches processed, and forgets them.  Host only; events are
+ * pairs those launches processed, and forgets them.  Kind 4 is so_rdm1's
+ * contraction kernel (units: shadows) and kind 5 the VCE prologue kernel
+ * (units: walkers).  Host only; events are
  * created with hipEventCreate while enabled. */
 so_status so_profile_enable(int on);
 so_status so_profile_read(int kind, double *ms, int64_t *launches, int64_t *pairs);

@@ -39,6 +39,11 @@ class SoC64(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
 
 
+class SoVceDims(ctypes.Structure):
+    _fields_ = [("n_basis", ctypes.c_int), ("n_core", ctypes.c_int), ("n_active", ctypes.c_int),
+                ("n_alpha", ctypes.c_int), ("n_beta", ctypes.c_int)]
+
+
 class SoProblem(ctypes.Structure):
     _fields_ = [("params", SoParams), ("phi", ctypes.c_void_p), ("n_walkers", ctypes.c_int64),
                 ("Q", ctypes.c_void_p), ("bits", ctypes.c_void_p), ("n_shadows", ctypes.c_int64),
@@ -77,6 +82,14 @@ def _load():
     lib.so_rdm1_workspace_size.restype = c.c_int
     lib.so_rdm1.argtypes = [c.c_int, P, P, c.c_int64, c.c_int, P, P, P, c.c_size_t, P]
     lib.so_rdm1.restype = c.c_int
+    lib.so_vce_walkers.argtypes = [c.POINTER(SoVceDims), P, P, c.c_int64, P, P, P]
+    lib.so_vce_walkers.restype = c.c_int
+    lib.so_vce_workspace_size.argtypes = [c.POINTER(SoParams), c.POINTER(SoVceDims), c.c_int64, c.c_int64,
+                                          c.POINTER(c.c_size_t)]
+    lib.so_vce_workspace_size.restype = c.c_int
+    lib.so_vce_overlap.argtypes = [c.POINTER(SoParams), c.POINTER(SoVceDims), P, P, c.c_int64, P, P, c.c_int64,
+                                   P, P, P, P, c.c_size_t, P]
+    lib.so_vce_overlap.restype = c.c_int
     lib.so_profile_enable.argtypes = [c.c_int]
     lib.so_profile_enable.restype = c.c_int
     lib.so_profile_read.argtypes = [c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
@@ -128,7 +141,7 @@ def node_weights(p: SoParams):
             np.array([complex(w[i].re, w[i].im) for i in range(k)]))
 
 
-PROF_PFAFF, PROF_FORM, PROF_PAIR, PROF_GRAD, PROF_RDM = 0, 1, 2, 3, 4
+PROF_PFAFF, PROF_FORM, PROF_PAIR, PROF_GRAD, PROF_RDM, PROF_VCE = 0, 1, 2, 3, 4, 5
 
 
 def profile_enable(on: bool = True) -> None:
@@ -272,6 +285,59 @@ def rdm1(Q: torch.Tensor, bits: torch.Tensor, *, trial: bool = True, with_majora
     if st != SO_OK:
         raise ShadowOvError(st, "so_rdm1")
     return rdm, maj
+
+
+def _vce_inputs(phi_alpha, phi_beta, n_core, n_active):
+    for t in (phi_alpha, phi_beta):
+        if not t.is_cuda or t.dtype != torch.complex128 or t.dim() != 3:
+            raise TypeError("phi_alpha and phi_beta must be complex128 device tensors [W, N_B, N_c + n_spin]")
+    W, NB, ea = phi_alpha.shape
+    if phi_beta.shape[0] != W or phi_beta.shape[1] != NB:
+        raise ValueError("phi_alpha and phi_beta must share W and N_B")
+    d = SoVceDims(NB, int(n_core), int(n_active), ea - int(n_core), phi_beta.shape[2] - int(n_core))
+    return W, d, phi_alpha.contiguous(), phi_beta.contiguous()
+
+
+def vce_walkers(phi_alpha: torch.Tensor, phi_beta: torch.Tensor, n_core: int, n_active: int):
+    """Active-space walkers and prefactors of full-space walkers (so_vce_walkers).
+    Returns (active_phi [W, 2 n_active, n_alpha + n_beta], prefactor [W])."""
+    W, d, pa, pb = _vce_inputs(phi_alpha, phi_beta, n_core, n_active)
+    act = torch.empty((W, 2 * d.n_active, d.n_alpha + d.n_beta), dtype=torch.complex128, device=pa.device)
+    pref = torch.empty(W, dtype=torch.complex128, device=pa.device)
+    stream = torch.cuda.current_stream(pa.device).cuda_stream
+    st = lib.so_vce_walkers(ctypes.byref(d), _dev_ptr(pa), _dev_ptr(pb), W, _dev_ptr(act), _dev_ptr(pref),
+                            ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_vce_walkers")
+    return act, pref
+
+
+def vce_overlap(phi_alpha: torch.Tensor, phi_beta: torch.Tensor, n_core: int, n_active: int, Q: torch.Tensor,
+                bits: torch.Tensor, *, n_nodes: int = 0, nodes: str = "unit", precision: str = "fp64",
+                paper_norm: bool = False, workspace: torch.Tensor | None = None):
+    """Full-space overlaps <Psi_T|phi_w> = c_w S_w(phi~_a) (so_vce_overlap).
+    Returns (overlap [W], prefactor [W], status int32 [W])."""
+    W, d, pa, pb = _vce_inputs(phi_alpha, phi_beta, n_core, n_active)
+    if not (Q.is_cuda and bits.is_cuda) or Q.dtype != torch.float64 or bits.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("Q must be float64 and bits 64-bit integers, on the device")
+    S = Q.shape[0]
+    Q, bits = Q.contiguous(), bits.contiguous()
+    p = make_params(2 * d.n_active, d.n_alpha + d.n_beta, n_nodes, nodes, precision, paper_norm)
+    nbytes = ctypes.c_size_t(0)
+    st = lib.so_vce_workspace_size(ctypes.byref(p), ctypes.byref(d), W, S, ctypes.byref(nbytes))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_vce_workspace_size")
+    ws = workspace if workspace is not None else _workspace(int(nbytes.value), pa.device)
+    out = torch.empty(W, dtype=torch.complex128, device=pa.device)
+    pref = torch.empty(W, dtype=torch.complex128, device=pa.device)
+    status = torch.zeros(W, dtype=torch.int32, device=pa.device)
+    stream = torch.cuda.current_stream(pa.device).cuda_stream
+    st = lib.so_vce_overlap(ctypes.byref(p), ctypes.byref(d), _dev_ptr(pa), _dev_ptr(pb), W, _dev_ptr(Q),
+                            _dev_ptr(bits), S, _dev_ptr(out), _dev_ptr(pref), _dev_ptr(status), _dev_ptr(ws),
+                            ws.numel(), ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_vce_overlap")
+    return out, pref, status
 
 
 class ShadowLogOverlap(torch.autograd.Function):

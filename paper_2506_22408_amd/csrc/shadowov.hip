@@ -43,6 +43,7 @@
 #include "so_force.h"
 #include "so_batch.h"
 #include "so_rdm.h"
+#include "so_vce.h"
 
 // --------------------------------------------------------------------------
 // k_reduce: S_w = (1/S) sum_s o_ws, fixed order: lane l sums s = l, l+64, ...
@@ -498,7 +499,7 @@ hipError_t launch_nodes(int M2, const double2 *Sb, const double2 *Pb, const Node
 }
 
 // ---- optional per-kernel timing (benchmarks): HIP events around launches
-enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_GRAD = 3, PROF_RDM = 4, PROF_NKIND = 5 };
+enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_GRAD = 3, PROF_RDM = 4, PROF_VCE = 5, PROF_NKIND = 6 };
 struct ProfRec { hipEvent_t a, b; int kind; int64_t units; };
 struct ProfState {
     bool on = false;
@@ -789,6 +790,34 @@ RdmPlan rdm_plan(int n, int64_t S) {
     return r;
 }
 
+// VCE dimensions: core and active blocks inside the basis, at most
+// SO_VCE_NAMAX active orbitals, and one walker's matrices within the LDS
+// budget of k_vce_prep.
+bool vce_dims_ok(const so_vce_dims *d, VceDims *v) {
+    if (!d) return false;
+    v->nb = d->n_basis; v->nc = d->n_core; v->na = d->n_active; v->nal = d->n_alpha; v->nbe = d->n_beta;
+    if (v->nc < 0 || v->na < 1 || v->na > SO_VCE_NAMAX || v->nal < 0 || v->nbe < 0) return false;
+    if (v->nal > v->na || v->nbe > v->na || v->nal + v->nbe < 1) return false;
+    if (v->nb < v->nc + v->na) return false;
+    return vce_lds_entries(*v) * sizeof(double2) <= SO_VCE_LDS_MAX;
+}
+
+hipError_t launch_vce_prep(const VceDims &v, const so_c64 *pa, const so_c64 *pb, int64_t W, double2 *act,
+                           double2 *pref, hipStream_t st) {
+    hipEvent_t ea = nullptr;
+    hipError_t e = prof_begin(st, &ea);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_vce_prep, dim3((unsigned)W), dim3(64), vce_lds_entries(v) * sizeof(double2), st, v,
+                       reinterpret_cast<const double2 *>(pa), reinterpret_cast<const double2 *>(pb), act, pref);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return prof_end(st, ea, PROF_VCE, W);
+}
+
+size_t vce_extra_bytes(int64_t W, int n, int eta) {
+    return align_up((size_t)W * n * eta * sizeof(double2)) + align_up((size_t)W * sizeof(double2));
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -953,6 +982,60 @@ so_status so_force_bias(const so_c64 *green, int64_t n_walkers, int n, const dou
     hipLaunchKernelGGL(k_force_bias, dim3((unsigned)n_walkers), dim3(256), 0, st,
                        reinterpret_cast<const double2 *>(green), n, L, n_gamma, std::sqrt(dt),
                        reinterpret_cast<double2 *>(xbar));
+    return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
+}
+
+so_status so_vce_walkers(const so_vce_dims *dims, const so_c64 *phi_alpha, const so_c64 *phi_beta,
+                         int64_t n_walkers, so_c64 *active_phi, so_c64 *prefactor, void *stream) {
+    VceDims v;
+    if (!vce_dims_ok(dims, &v) || !phi_alpha || !phi_beta || !active_phi || !prefactor || n_walkers < 1 ||
+        n_walkers > (int64_t)INT32_MAX)
+        return SO_ERR_ARG;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    return launch_vce_prep(v, phi_alpha, phi_beta, n_walkers, reinterpret_cast<double2 *>(active_phi),
+                           reinterpret_cast<double2 *>(prefactor), st) == hipSuccess
+               ? SO_OK
+               : SO_ERR_HIP;
+}
+
+so_status so_vce_workspace_size(const so_params *p, const so_vce_dims *dims, int64_t n_walkers,
+                                int64_t n_shadows, size_t *bytes) {
+    VceDims v;
+    if (!bytes || !p || !vce_dims_ok(dims, &v) || p->n != 2 * v.na || p->eta != v.nal + v.nbe) return SO_ERR_ARG;
+    size_t base = 0;
+    const so_status sv = so_workspace_size(p, n_walkers, n_shadows, 0, &base);
+    if (sv != SO_OK) return sv;
+    *bytes = align_up(base) + vce_extra_bytes(n_walkers, p->n, p->eta);
+    return SO_OK;
+}
+
+so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c64 *phi_alpha,
+                         const so_c64 *phi_beta, int64_t n_walkers, const double *Q, const uint64_t *bits,
+                         int64_t n_shadows, so_c64 *overlap, so_c64 *prefactor, int32_t *status,
+                         void *workspace, size_t workspace_bytes, void *stream) {
+    VceDims v;
+    // every check of shadow_overlap is made here, before anything is enqueued
+    if (!phi_alpha || !phi_beta || !overlap || !Q || !bits || !vce_dims_ok(dims, &v) || n_walkers < 1 ||
+        n_shadows < 1 || n_walkers > (int64_t)INT32_MAX || n_shadows > (int64_t)INT32_MAX)
+        return SO_ERR_ARG;
+    size_t need = 0;
+    const so_status sv = so_vce_workspace_size(p, dims, n_walkers, n_shadows, &need);
+    if (sv != SO_OK) return sv;
+    if (!workspace || workspace_bytes < need) return SO_ERR_WORKSPACE;
+    size_t base = 0;
+    (void)so_workspace_size(p, n_walkers, n_shadows, 0, &base);
+    char *ws = static_cast<char *>(workspace);
+    double2 *act = reinterpret_cast<double2 *>(ws + align_up(base));
+    double2 *pref = prefactor ? reinterpret_cast<double2 *>(prefactor)
+                              : reinterpret_cast<double2 *>(ws + align_up(base) +
+                                                            align_up((size_t)n_walkers * p->n * p->eta * sizeof(double2)));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (launch_vce_prep(v, phi_alpha, phi_beta, n_walkers, act, pref, st) != hipSuccess) return SO_ERR_HIP;
+    const so_status so = shadow_overlap(p, reinterpret_cast<const so_c64 *>(act), n_walkers, Q, bits, n_shadows,
+                                        overlap, nullptr, status, workspace, base, stream);
+    if (so != SO_OK) return so;
+    hipLaunchKernelGGL(k_vce_scale, dim3((unsigned)((n_walkers + 255) / 256)), dim3(256), 0, st, n_walkers, pref,
+                       reinterpret_cast<double2 *>(overlap));
     return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
 }
 
