@@ -71,8 +71,12 @@ def _load():
         lib.or_pair_grad.argtypes = [c.c_int, c.c_int, c.c_int, P, P, P, P, c.c_uint64, P, P]
         lib.or_grad_walkers.argtypes = [c.c_int, c.c_int, c.c_int, P, P, P, c.c_long, P, P, c.c_long,
                                         P, P, P, c.c_int]
+        lib.or_kmatrix.argtypes = [c.c_int, P, P]
+        lib.or_kmatrix.restype = None
+        lib.or_energy_pairs.argtypes = [c.c_int, c.c_int, c.c_int, P, P, P, c.c_long, P, P, c.c_long,
+                                        P, P, c.c_long, P, P, c.c_int, P, P, P, c.c_int]
         for f in ("or_pfaffian", "or_complement", "or_xmatrix", "or_pair_perp", "or_pair",
-                  "or_overlap_pairs", "or_pair_grad", "or_grad_walkers"):
+                  "or_overlap_pairs", "or_pair_grad", "or_grad_walkers", "or_energy_pairs"):
             getattr(lib, f).restype = c.c_int
         _lib = lib
     return _lib
@@ -272,6 +276,69 @@ def grad(phi, Q, bits, K=None, family="unit", nthreads=0):
     D = gsum / osum[:, None, None]
     G = D @ np.transpose(phi, (0, 2, 1))
     return osum / S, D, G
+
+
+def kmatrix(L) -> np.ndarray:
+    """Majorana matrix K of a one-body operator Lhat = sum_pq L_pq a_p^dag a_q
+    acting by commutation, [Lhat, gamma_rho] = sum_sigma K[rho, sigma]
+    gamma_sigma (0-based Majoranas 2r, 2r+1 of mode r)."""
+    L = _c128(L)
+    n = L.shape[0]
+    Km = np.zeros((2 * n, 2 * n), np.complex128)
+    _load().or_kmatrix(n, _ptr(L), _ptr(Km))
+    return Km
+
+
+def energy_pairs(phi, Q, bits, t, L, K=None, family="chebyshev", pairs=None, nthreads=0):
+    """Per-pair overlap estimates o_ws and local-energy numerators e_ws
+    ("Force bias and local energy": eqs. local_energy, ham_cholesky_decom,
+    energy_tb_diff, Pfaffian_der, Pfaffian_2nd_der).
+
+    H = sum_pq t_pq a_p^dag a_q + 1/2 sum_g Lhat_g^2, Lhat_g = sum_pq
+    L[p n + q, g] a_p^dag a_q; e_ws is the single-shadow estimate of
+    <Psi_T|H|phi_w>, from the first and second derivatives of the node
+    Pfaffians along e^{lambda Lhat}.  t [n, n] complex, L [n*n, n_gamma] real.
+    Returns (o, e), each [W, S] (or [P] for a (P, 2) list of pairs).
+
+    The default nodes are the paper's Chebyshev nodes.  The roots of unity
+    include z = -1, which for odd n - eta is a root of Pf(C_0 + z B) for
+    every walker and shadow: there the second-derivative formula multiplies
+    a vanishing Pfaffian by two diverging inverses and loses all accuracy."""
+    phi = _c128(phi)
+    Q = _f64(Q)
+    bits = np.ascontiguousarray(bits, dtype=np.uint64)
+    t = _c128(t)
+    L = _f64(L).reshape(phi.shape[1] ** 2, -1)
+    W, n, eta = phi.shape
+    S = Q.shape[0]
+    ng = L.shape[1]
+    z, w = node_weights(n, eta, K, family)
+    if pairs is None:
+        npairs, pw, ps = W * S, None, None
+    else:
+        pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+        npairs = pairs.shape[0]
+        pw = np.ascontiguousarray(pairs[:, 0])
+        ps = np.ascontiguousarray(pairs[:, 1])
+    o = np.zeros(npairs, np.complex128)
+    e = np.zeros(npairs, np.complex128)
+    status = np.zeros(npairs, np.int32)
+    _load().or_energy_pairs(n, eta, len(z), _ptr(z), _ptr(w), _ptr(phi), W, _ptr(Q), _ptr(bits), S,
+                            None if pw is None else _ptr(pw), None if ps is None else _ptr(ps), npairs,
+                            _ptr(t), _ptr(L), ng, _ptr(o), _ptr(e), _ptr(status), int(nthreads))
+    if status.any():
+        raise np.linalg.LinAlgError(f"oracle energy failed on {int((status != 0).sum())} pairs")
+    if pairs is None:
+        o, e = o.reshape(W, S), e.reshape(W, S)
+    return o, e
+
+
+def local_energy(phi, Q, bits, t, L, K=None, family="chebyshev", nthreads=0):
+    """Per walker: S_w, the numerator N_w = (1/S) sum_s e_ws and the local
+    energy E_L = N_w / S_w (eq. local_energy)."""
+    o, e = energy_pairs(phi, Q, bits, t, L, K, family, nthreads=nthreads)
+    Sw, Nw = o.mean(axis=1), e.mean(axis=1)
+    return Sw, Nw, Nw / Sw
 
 
 def force_bias(G, L, dt: float = 0.01) -> np.ndarray:

@@ -475,3 +475,198 @@ int or_grad_walkers(int n, int eta, int K, const cplx *nodes, const cplx *weight
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Local energy ("Force bias and local energy": eqs. local_energy,
+ * ham_cholesky_decom, energy_tb_diff, Pfaffian_der, Pfaffian_2nd_der).
+ *
+ * H = sum_pq t_pq a_p^dag a_q + 1/2 sum_g Lhat_g^2 with
+ * Lhat_g = sum_pq L^g_pq a_p^dag a_q (v_0 = the one-body part t and
+ * v_g = i Lhat_g in H = v_0 - 1/2 sum_g v_g^2).  A one-body operator Lhat
+ * moves the walker to e^{lambda Lhat}|phi>, a determinant whose defining
+ * operators are e^{lambda Lhat} b e^{-lambda Lhat}; on the Majorana
+ * coefficient rows of X this is X -> X e^{lambda K} with
+ * [Lhat, gamma_rho] = sum_sigma K[rho][sigma] gamma_sigma.  From
+ * [a_p^dag a_q, a_r^dag] = delta_qr a_p^dag and [a_p^dag a_q, a_r] =
+ * -delta_pr a_q, with gamma_2r = a_r + a_r^dag and
+ * gamma_2r+1 = -i (a_r - a_r^dag) (0-based):
+ *   K[2r][2q]   = (L_qr - L_rq)/2,   K[2r][2q+1]   = -i (L_rq + L_qr)/2,
+ *   K[2r+1][2q] = i (L_rq + L_qr)/2, K[2r+1][2q+1] = (L_qr - L_rq)/2.       */
+void or_kmatrix(int n, const cplx *L, cplx *Km)
+{
+    int d = 2 * n;
+    for (int i = 0; i < d * d; ++i) Km[i] = 0.0;
+    for (int r = 0; r < n; ++r)
+        for (int q = 0; q < n; ++q) {
+            cplx s = (L[(size_t)q * n + r] - L[(size_t)r * n + q]) / 2;
+            cplx t = (L[(size_t)r * n + q] + L[(size_t)q * n + r]) / 2;
+            Km[(size_t)(2 * r) * d + 2 * q] = s;
+            Km[(size_t)(2 * r) * d + 2 * q + 1] = -I * t;
+            Km[(size_t)(2 * r + 1) * d + 2 * q] = I * t;
+            Km[(size_t)(2 * r + 1) * d + 2 * q + 1] = s;
+        }
+}
+
+/* C = A B for complex d x d matrices (B given as complex) */
+static void cmul_dd(int d, const cplx *A, const cplx *B, cplx *C)
+{
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            cplx s = 0.0;
+            for (int k = 0; k < d; ++k) s += A[(size_t)i * d + k] * B[(size_t)k * d + j];
+            C[(size_t)i * d + j] = s;
+        }
+}
+
+/* Bd = X D X^T (m x m) for a complex d x d matrix D */
+static void sandwich(int m, int d, const cplx *X, const cplx *D, cplx *Bd)
+{
+    cplx *T = (cplx *)malloc(sizeof(cplx) * (size_t)m * d);
+    for (int i = 0; i < m; ++i)
+        for (int nu = 0; nu < d; ++nu) {
+            cplx s = 0.0;
+            for (int mu = 0; mu < d; ++mu) s += X[(size_t)i * d + mu] * D[(size_t)mu * d + nu];
+            T[(size_t)i * d + nu] = s;
+        }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            cplx s = 0.0;
+            for (int nu = 0; nu < d; ++nu) s += T[(size_t)i * d + nu] * X[(size_t)j * d + nu];
+            Bd[(size_t)i * m + j] = s;
+        }
+    free(T);
+}
+
+/* dB/dlambda and d^2B/dlambda^2 at lambda = 0 for B(lambda) =
+ * X e^{lambda K} C' e^{lambda K^T} X^T:
+ *   B1 = X (K C' + C' K^T) X^T,  B2 = X (K^2 C' + 2 K C' K^T + C' (K^T)^2) X^T. */
+static void bderivs(int m, int d, const cplx *X, const double *Cp, const cplx *Km, cplx *B1, cplx *B2)
+{
+    size_t dd = (size_t)d * d;
+    cplx *C = (cplx *)malloc(sizeof(cplx) * dd);
+    cplx *Kt = (cplx *)malloc(sizeof(cplx) * dd);
+    cplx *KC = (cplx *)malloc(sizeof(cplx) * dd);
+    cplx *CKt = (cplx *)malloc(sizeof(cplx) * dd);
+    cplx *KKC = (cplx *)malloc(sizeof(cplx) * dd);
+    cplx *KCKt = (cplx *)malloc(sizeof(cplx) * dd);
+    cplx *CKtKt = (cplx *)malloc(sizeof(cplx) * dd);
+    cplx *D = (cplx *)malloc(sizeof(cplx) * dd);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            C[(size_t)i * d + j] = Cp[(size_t)i * d + j];
+            Kt[(size_t)i * d + j] = Km[(size_t)j * d + i];
+        }
+    cmul_dd(d, Km, C, KC);
+    cmul_dd(d, C, Kt, CKt);
+    cmul_dd(d, Km, KC, KKC);
+    cmul_dd(d, KC, Kt, KCKt);
+    cmul_dd(d, CKt, Kt, CKtKt);
+    for (size_t i = 0; i < dd; ++i) D[i] = KC[i] + CKt[i];
+    sandwich(m, d, X, D, B1);
+    for (size_t i = 0; i < dd; ++i) D[i] = KKC[i] + 2.0 * KCKt[i] + CKtKt[i];
+    sandwich(m, d, X, D, B2);
+    free(C); free(Kt); free(KC); free(CKt); free(KKC); free(KCKt); free(CKtKt); free(D);
+}
+
+/* One pair: o = sum_k w_k Pf(A_k) and the numerator
+ *   e = sum_k w_k [ dPf_k[t] + 1/2 sum_g d2Pf_k[L_g] ],
+ *   dPf  = Pf/2 tr(A^{-1} A'),
+ *   d2Pf = Pf/2 { tr(A^{-1} A'') - tr(A^{-1} A' A^{-1} A') + 1/2 tr(A^{-1} A')^2 },
+ * A' = z B1, A'' = z B2 (the two lambdas of eq. Pfaffian_2nd_der move the
+ * walker along the same operator, so dA/dlambda_1 = dA/dlambda_2 = A' and
+ * d^2A/dlambda_1 dlambda_2 = A'').  Kt is the d x d K of t, Kg the ng K's
+ * of the L_g.  OR_ERR_SINGULAR if a node matrix is singular.               */
+int or_pair_energy(int n, int eta, int K, const cplx *nodes, const cplx *weights,
+                   const cplx *phi, const double *Q, uint64_t bits,
+                   const cplx *Kt, int ng, const cplx *Kg, cplx *o_out, cplx *e_out)
+{
+    int d = 2 * n, m = 2 * n - eta, nc = n - eta, nop = ng + 1;
+    size_t mm = (size_t)m * m;
+    cplx *perp = (cplx *)malloc(sizeof(cplx) * (size_t)n * (size_t)(nc > 0 ? nc : 1));
+    cplx *X = (cplx *)malloc(sizeof(cplx) * (size_t)m * d);
+    double *Cp = (double *)malloc(sizeof(double) * (size_t)d * d);
+    cplx *B = (cplx *)malloc(sizeof(cplx) * mm);
+    cplx *B1 = (cplx *)malloc(sizeof(cplx) * mm * nop);
+    cplx *B2 = (cplx *)malloc(sizeof(cplx) * mm * nop);
+    cplx *A = (cplx *)malloc(sizeof(cplx) * mm);
+    cplx *Ai = (cplx *)malloc(sizeof(cplx) * mm);
+    cplx *P = (cplx *)malloc(sizeof(cplx) * mm);
+    int st = or_complement(n, eta, phi, perp);
+    if (st == OR_OK) st = or_xmatrix(n, eta, phi, perp, X, NULL);
+    if (st == OR_OK) {
+        or_covariance(n, Q, bits, Cp);
+        bmatrix(m, d, X, Cp, B);
+        for (int op = 0; op < nop; ++op)
+            bderivs(m, d, X, Cp, op == 0 ? Kt : Kg + (size_t)(op - 1) * d * d, B1 + op * mm, B2 + op * mm);
+        cplx o = 0.0, e = 0.0;
+        for (int k = 0; k < K && st == OR_OK; ++k) {
+            cplx pk, z = nodes[k];
+            amatrix(n, eta, B, z, A);
+            or_pfaffian(m, A, &pk);
+            o += weights[k] * pk;
+            if (cinv(m, A, Ai) != OR_OK) { st = OR_ERR_SINGULAR; break; }
+            for (int op = 0; op < nop; ++op) {
+                const cplx *b1 = B1 + op * mm, *b2 = B2 + op * mm;
+                cplx tr1 = 0.0, tr2 = 0.0, trq = 0.0;
+                for (int i = 0; i < m; ++i)
+                    for (int j = 0; j < m; ++j) {
+                        tr1 += Ai[(size_t)i * m + j] * z * b1[(size_t)j * m + i];
+                        tr2 += Ai[(size_t)i * m + j] * z * b2[(size_t)j * m + i];
+                    }
+                if (op == 0) {
+                    e += weights[k] * pk / 2 * tr1;
+                    continue;
+                }
+                for (int i = 0; i < m; ++i)          /* P = A^{-1} A' */
+                    for (int j = 0; j < m; ++j) {
+                        cplx s = 0.0;
+                        for (int l = 0; l < m; ++l) s += Ai[(size_t)i * m + l] * z * b1[(size_t)l * m + j];
+                        P[(size_t)i * m + j] = s;
+                    }
+                for (int i = 0; i < m; ++i)
+                    for (int j = 0; j < m; ++j) trq += P[(size_t)i * m + j] * P[(size_t)j * m + i];
+                e += 0.5 * weights[k] * pk / 2 * (tr2 - trq + 0.5 * tr1 * tr1);
+            }
+        }
+        *o_out = o;
+        *e_out = e;
+    }
+    free(perp); free(X); free(Cp); free(B); free(B1); free(B2); free(A); free(Ai); free(P);
+    return st;
+}
+
+/* Pairs (list pw/ps, or all W x S walker-major) of o_ws and e_ws for the
+ * Hamiltonian (t [n][n] complex, L [n*n][ng] real with L[p n + q][g] =
+ * L^g_pq).  OpenMP over pairs.                                              */
+int or_energy_pairs(int n, int eta, int K, const cplx *nodes, const cplx *weights,
+                    const cplx *phi, long W, const double *Q, const uint64_t *bits, long S,
+                    const long *pw, const long *ps, long npairs,
+                    const cplx *t, const double *L, int ng,
+                    cplx *o_out, cplx *e_out, int *status, int nthreads)
+{
+    if (n < 1 || eta < 1 || eta > n || (eta & 1) || K < 1 || ng < 0) return OR_ERR_ARG;
+    int d = 2 * n;
+    size_t dd = (size_t)d * d;
+    cplx *Kt = (cplx *)malloc(sizeof(cplx) * dd);
+    cplx *Kg = (cplx *)malloc(sizeof(cplx) * dd * (size_t)(ng > 0 ? ng : 1));
+    cplx *Lg = (cplx *)malloc(sizeof(cplx) * (size_t)n * n);
+    or_kmatrix(n, t, Kt);
+    for (int g = 0; g < ng; ++g) {
+        for (int pq = 0; pq < n * n; ++pq) Lg[pq] = L[(size_t)pq * ng + g];
+        or_kmatrix(n, Lg, Kg + (size_t)g * dd);
+    }
+    long total = (pw && ps) ? npairs : W * S;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (long i = 0; i < total; ++i) {
+        long w = (pw && ps) ? pw[i] : i / S;
+        long s = (pw && ps) ? ps[i] : i % S;
+        int st = or_pair_energy(n, eta, K, nodes, weights, phi + (size_t)w * n * eta, Q + (size_t)s * dd,
+                                bits[s], Kt, ng, Kg, &o_out[i], &e_out[i]);
+        if (status) status[i] = st;
+    }
+    free(Kt); free(Kg); free(Lg);
+    return OR_OK;
+}
