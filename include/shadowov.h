@@ -277,6 +277,37 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
                          int64_t n_shadows, so_c64 *overlap, so_c64 *prefactor, int32_t *status,
                          void *workspace, size_t workspace_bytes, void *stream);
 
+/* Local energy E_L = <Psi_T|H|phi_w> / <Psi_T|phi_w> (section "Force bias
+ * and local energy": eqs. local_energy, ham_cholesky_decom, energy_tb_diff,
+ * Pfaffian_der, Pfaffian_2nd_der) for
+ *   H = sum_pq t_pq a_p^dag a_q + 1/2 sum_g Lhat_g^2,  Lhat_g = sum_pq L^g_pq a_p^dag a_q
+ * (the paper's H = v_0 - 1/2 sum_g v_g^2 with v_g = i Lhat_g), from the
+ * first and second derivatives of the node Pfaffians as the walker moves
+ * along e^{lambda Lhat}.  The node matrices must be invertible, so this
+ * entry point uses the paper's Chebyshev nodes whatever p->nodes says (the
+ * roots of unity contain z = -1, where every pair's Pfaffian vanishes when
+ * n - eta is odd); K = p->n_nodes or n + 1.
+ *   phi, Q, bits  as in shadow_overlap (device)
+ *   t        [n][n] complex128 (device), any one-body matrix
+ *   L        [n*n][n_gamma] float64 (device), L[p n + q][g] = L^g_pq, each L^g
+ *            real symmetric (the kernel relies on it); NULL if n_gamma = 0
+ *   overlap  [n_walkers] complex128 out (device) or NULL: S_w
+ *   numerator [n_walkers] complex128 out or NULL: the shadow estimate of
+ *            <Psi_T|H|phi_w>, N_w = (1/S) sum_s e_ws
+ *   energy   [n_walkers] complex128 out or NULL: N_w / S_w
+ *   status   [n_walkers] int32 out or NULL: SO_WSTAT_RANK / _NONFINITE, and
+ *            SO_WSTAT_SINGULAR if a node matrix of some pair was exactly
+ *            singular (that node's energy term is then left out)
+ * Supported: n <= 16, FP64 (SO_ERR_UNSUPPORTED otherwise); n_walkers <=
+ * 65535.  One 256-thread workgroup per pair; deterministic (fixed
+ * reduction order); no allocation; enqueued on `stream`. */
+so_status so_local_energy_workspace_size(const so_params *p, int64_t n_walkers, int64_t n_shadows, int n_gamma,
+                                         size_t *bytes);
+so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walkers, const double *Q,
+                          const uint64_t *bits, int64_t n_shadows, const so_c64 *t, const double *L, int n_gamma,
+                          so_c64 *overlap, so_c64 *numerator, so_c64 *energy, int32_t *status, void *workspace,
+                          size_t workspace_bytes, void *stream);
+
 /* Force bias of every walker ("Force bias and local energy", eq. force_bias,
  * with the Cholesky vectors L^gamma of eq. cholesky_vec):
  *   xbar[w][gamma] = -sqrt(dt) i sum_pq L[p n + q][gamma] G_w[p][q].
@@ -297,8 +328,8 @@ so_status so_force_bias(const so_c64 *green, int64_t n_walkers, int n, const dou
  * waits for the recorded events of one kind, returns their summed duration
  * in milliseconds, the number of launches and the number of walker x shadow
  * pairs those launches processed, and forgets them.  Kind 4 is so_rdm1's
- * contraction kernel (units: shadows) and kind 5 the VCE prologue kernel
- * (units: walkers).  Host only; events are
+ * contraction kernel (units: shadows), kind 5 the VCE prologue kernel
+ * (units: walkers) and kind 6 so_local_energy's pair kernel (units: pairs).  Host only; events are
  * created with hipEventCreate while enabled. */
 so_status so_profile_enable(int on);
 so_status so_profile_read(int kind, double *ms, int64_t *launches, int64_t *pairs);

@@ -90,6 +90,12 @@ def _load():
     lib.so_vce_overlap.argtypes = [c.POINTER(SoParams), c.POINTER(SoVceDims), P, P, c.c_int64, P, P, c.c_int64,
                                    P, P, P, P, c.c_size_t, P]
     lib.so_vce_overlap.restype = c.c_int
+    lib.so_local_energy_workspace_size.argtypes = [c.POINTER(SoParams), c.c_int64, c.c_int64, c.c_int,
+                                                   c.POINTER(c.c_size_t)]
+    lib.so_local_energy_workspace_size.restype = c.c_int
+    lib.so_local_energy.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, c.c_int, P, P, P, P,
+                                    P, c.c_size_t, P]
+    lib.so_local_energy.restype = c.c_int
     lib.so_profile_enable.argtypes = [c.c_int]
     lib.so_profile_enable.restype = c.c_int
     lib.so_profile_read.argtypes = [c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
@@ -141,7 +147,7 @@ def node_weights(p: SoParams):
             np.array([complex(w[i].re, w[i].im) for i in range(k)]))
 
 
-PROF_PFAFF, PROF_FORM, PROF_PAIR, PROF_GRAD, PROF_RDM, PROF_VCE = 0, 1, 2, 3, 4, 5
+PROF_PFAFF, PROF_FORM, PROF_PAIR, PROF_GRAD, PROF_RDM, PROF_VCE, PROF_ENERGY = 0, 1, 2, 3, 4, 5, 6
 
 
 def profile_enable(on: bool = True) -> None:
@@ -285,6 +291,36 @@ def rdm1(Q: torch.Tensor, bits: torch.Tensor, *, trial: bool = True, with_majora
     if st != SO_OK:
         raise ShadowOvError(st, "so_rdm1")
     return rdm, maj
+
+
+def local_energy(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, t: torch.Tensor, L: torch.Tensor, *,
+                 n_nodes: int = 0, paper_norm: bool = False, workspace: torch.Tensor | None = None):
+    """Local energies E_L = N_w / S_w (so_local_energy) for H = sum t_pq a_p^dag a_q
+    + 1/2 sum_g Lhat_g^2, with t [n, n] complex128 and L [n*n, n_gamma] float64
+    (each L^g real symmetric).  Returns (overlap [W], numerator [W],
+    energy [W], status int32 [W])."""
+    W, n, eta, S = _check_inputs(phi, Q, bits)
+    if not (t.is_cuda and L.is_cuda) or t.dtype != torch.complex128 or L.dtype != torch.float64:
+        raise TypeError("t must be complex128 and L float64, on the device")
+    if t.shape != (n, n) or L.dim() != 2 or L.shape[0] != n * n:
+        raise ValueError("t must be [n, n] and L [n*n, n_gamma]")
+    phi, Q, bits, t, L = phi.contiguous(), Q.contiguous(), bits.contiguous(), t.contiguous(), L.contiguous()
+    ng = L.shape[1]
+    p = make_params(n, eta, n_nodes, "chebyshev", "fp64", paper_norm)
+    nbytes = ctypes.c_size_t(0)
+    st = lib.so_local_energy_workspace_size(ctypes.byref(p), W, S, ng, ctypes.byref(nbytes))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_local_energy_workspace_size")
+    ws = workspace if workspace is not None else _workspace(int(nbytes.value), phi.device)
+    out = [torch.empty(W, dtype=torch.complex128, device=phi.device) for _ in range(3)]
+    status = torch.zeros(W, dtype=torch.int32, device=phi.device)
+    stream = torch.cuda.current_stream(phi.device).cuda_stream
+    st = lib.so_local_energy(ctypes.byref(p), _dev_ptr(phi), W, _dev_ptr(Q), _dev_ptr(bits), S, _dev_ptr(t),
+                             _dev_ptr(L) if ng else None, ng, _dev_ptr(out[0]), _dev_ptr(out[1]), _dev_ptr(out[2]),
+                             _dev_ptr(status), _dev_ptr(ws), ws.numel(), ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_local_energy")
+    return out[0], out[1], out[2], status
 
 
 def _vce_inputs(phi_alpha, phi_beta, n_core, n_active):

@@ -44,6 +44,7 @@
 #include "so_batch.h"
 #include "so_rdm.h"
 #include "so_vce.h"
+#include "so_energy.h"
 
 // --------------------------------------------------------------------------
 // k_reduce: S_w = (1/S) sum_s o_ws, fixed order: lane l sums s = l, l+64, ...
@@ -499,7 +500,7 @@ hipError_t launch_nodes(int M2, const double2 *Sb, const double2 *Pb, const Node
 }
 
 // ---- optional per-kernel timing (benchmarks): HIP events around launches
-enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_GRAD = 3, PROF_RDM = 4, PROF_VCE = 5, PROF_NKIND = 6 };
+enum { PROF_PFAFF = 0, PROF_FORM = 1, PROF_PAIR = 2, PROF_GRAD = 3, PROF_RDM = 4, PROF_VCE = 5, PROF_ENERGY = 6, PROF_NKIND = 7 };
 struct ProfRec { hipEvent_t a, b; int kind; int64_t units; };
 struct ProfState {
     bool on = false;
@@ -814,6 +815,34 @@ hipError_t launch_vce_prep(const VceDims &v, const so_c64 *pa, const so_c64 *pb,
     return prof_end(st, ea, PROF_VCE, W);
 }
 
+// Workspace of so_local_energy: walker matrices and shadow covariances in A
+// order, the Hamiltonian tables, the per-shadow M, per-pair values, status.
+struct EnLayout {
+    size_t off_X, off_C, off_V, off_K2, off_Kt, off_M, off_o, off_e, off_stat, total;
+};
+EnLayout energy_layout(int n, int64_t W, int64_t S) {
+    const int T = so_tiles(n), DP = 16 * T, d = 2 * n;
+    EnLayout L;
+    size_t o = 0;
+    L.off_X = o; o = align_up(o + (size_t)W * DP * DP * sizeof(double));
+    L.off_C = o; o = align_up(o + (size_t)S * DP * DP * sizeof(double));
+    L.off_V = o; o = align_up(o + (size_t)n * n * n * n * sizeof(double));
+    L.off_K2 = o; o = align_up(o + (size_t)n * n * sizeof(double));
+    L.off_Kt = o; o = align_up(o + (size_t)d * d * sizeof(double2));
+    L.off_M = o; o = align_up(o + (size_t)S * d * d * sizeof(double));
+    L.off_o = o; o = align_up(o + (size_t)W * S * sizeof(double2));
+    L.off_e = o; o = align_up(o + (size_t)W * S * sizeof(double2));
+    L.off_stat = o; o = align_up(o + (size_t)W * sizeof(int32_t));
+    L.total = o;
+    return L;
+}
+
+bool energy_args_ok(const so_params *p, int64_t W, int64_t S, int n_gamma, int *K) {
+    if (!params_ok(p, K) || W < 1 || S < 1 || n_gamma < 0) return false;
+    if (W > 65535 || S > (int64_t)INT32_MAX) return false;
+    return true;
+}
+
 size_t vce_extra_bytes(int64_t W, int n, int eta) {
     return align_up((size_t)W * n * eta * sizeof(double2)) + align_up((size_t)W * sizeof(double2));
 }
@@ -1036,6 +1065,79 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
     if (so != SO_OK) return so;
     hipLaunchKernelGGL(k_vce_scale, dim3((unsigned)((n_walkers + 255) / 256)), dim3(256), 0, st, n_walkers, pref,
                        reinterpret_cast<double2 *>(overlap));
+    return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
+}
+
+so_status so_local_energy_workspace_size(const so_params *p, int64_t n_walkers, int64_t n_shadows, int n_gamma,
+                                         size_t *bytes) {
+    int K;
+    if (!bytes || !energy_args_ok(p, n_walkers, n_shadows, n_gamma, &K)) return SO_ERR_ARG;
+    if (!so_supported(p->n, p->eta) || p->n > SO_EN_NMAX || p->precision != SO_PREC_FP64) return SO_ERR_UNSUPPORTED;
+    *bytes = energy_layout(p->n, n_walkers, n_shadows).total;
+    return SO_OK;
+}
+
+so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walkers, const double *Q,
+                          const uint64_t *bits, int64_t n_shadows, const so_c64 *t, const double *L, int n_gamma,
+                          so_c64 *overlap, so_c64 *numerator, so_c64 *energy, int32_t *status, void *workspace,
+                          size_t workspace_bytes, void *stream) {
+    int K;
+    if (!phi || !Q || !bits || !t || (n_gamma > 0 && !L) || !energy_args_ok(p, n_walkers, n_shadows, n_gamma, &K))
+        return SO_ERR_ARG;
+    if (!overlap && !numerator && !energy) return SO_ERR_ARG;
+    if (!so_supported(p->n, p->eta) || p->n > SO_EN_NMAX || p->precision != SO_PREC_FP64) return SO_ERR_UNSUPPORTED;
+    const int n = p->n, eta = p->eta, d = 2 * n, T = so_tiles(n);
+    const int64_t W = n_walkers, S = n_shadows;
+    const EnLayout Lo = energy_layout(n, W, S);
+    if (!workspace || workspace_bytes < Lo.total) return SO_ERR_WORKSPACE;
+    char *ws = static_cast<char *>(workspace);
+    double *Xa = reinterpret_cast<double *>(ws + Lo.off_X);
+    double *Ca = reinterpret_cast<double *>(ws + Lo.off_C);
+    double *Vt = reinterpret_cast<double *>(ws + Lo.off_V);
+    double *K2 = reinterpret_cast<double *>(ws + Lo.off_K2);
+    double2 *Kt = reinterpret_cast<double2 *>(ws + Lo.off_Kt);
+    double *Ms = reinterpret_cast<double *>(ws + Lo.off_M);
+    double2 *op = reinterpret_cast<double2 *>(ws + Lo.off_o);
+    double2 *ep = reinterpret_cast<double2 *>(ws + Lo.off_e);
+    int32_t *wst = status ? status : reinterpret_cast<int32_t *>(ws + Lo.off_stat);
+    // the paper's Chebyshev nodes, whatever p->nodes asks for (see so_energy.h)
+    so_params pc = *p;
+    pc.nodes = SO_NODES_CHEBYSHEV;
+    NodeTab nt;
+    build_nodetab(&pc, K, &nt);
+    EnTab tab;
+    std::memset(&tab, 0, sizeof(tab));
+    tab.K = K;
+    for (int k = 0; k < K; ++k) { tab.s[k] = nt.s[k]; tab.c[k] = nt.c[k]; tab.w[k] = nt.wf[k]; }
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
+                       reinterpret_cast<const double2 *>(phi), Xa, wst, nullptr);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q, bits, Ca);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    const int n4 = n * n * n * n;
+    hipLaunchKernelGGL(k_energy_v, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, n, n_gamma, L, Vt);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    hipLaunchKernelGGL(k_energy_small, dim3(1), dim3(256), 0, st, n, n_gamma, L,
+                       reinterpret_cast<const double2 *>(t), K2, Kt);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    if (T == 1) hipLaunchKernelGGL(k_energy_shadow<1>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms);
+    else hipLaunchKernelGGL(k_energy_shadow<2>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    hipEvent_t ea = nullptr;
+    if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
+    const dim3 grid((unsigned)S, (unsigned)W);
+    if (T == 1)
+        hipLaunchKernelGGL(k_energy_pair<1>, grid, dim3(SO_EN_THREADS), 0, st, n, eta, n_gamma, Xa, Ca, Ms, Vt, L,
+                           Kt, tab, S, op, ep, wst);
+    else
+        hipLaunchKernelGGL(k_energy_pair<2>, grid, dim3(SO_EN_THREADS), 0, st, n, eta, n_gamma, Xa, Ca, Ms, Vt, L,
+                           Kt, tab, S, op, ep, wst);
+    if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
+    if (prof_end(st, ea, PROF_ENERGY, W * S) != hipSuccess) return SO_ERR_HIP;
+    hipLaunchKernelGGL(k_energy_reduce, dim3((unsigned)W), dim3(256), 0, st, S, op, ep,
+                       reinterpret_cast<double2 *>(overlap), reinterpret_cast<double2 *>(numerator),
+                       reinterpret_cast<double2 *>(energy), wst);
     return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
 }
 

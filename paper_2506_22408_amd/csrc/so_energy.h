@@ -1,0 +1,435 @@
+// so_energy.h -- local energy from the shadows (section "Force bias and local
+// energy": eqs. local_energy, ham_cholesky_decom, energy_tb_diff,
+// Pfaffian_der, Pfaffian_2nd_der).
+//
+// H = sum_pq t_pq a_p^dag a_q + 1/2 sum_g Lhat_g^2, Lhat_g = sum_pq L^g_pq
+// a_p^dag a_q with real symmetric L^g.  A one-body operator moves the walker
+// to e^{lambda Lhat}|phi>, which acts on the Majorana rows of X as
+// X -> X e^{lambda K}, [Lhat, gamma_rho] = sum_sigma K[rho][sigma] gamma_sigma;
+// for a real symmetric L, K = L (x) sigma_y (2 x 2 blocks, sigma_y =
+// [[0,-i],[i,0]]), so K^T = -K.  Per node (A = c J + s B, Pf, A^{-1}), with
+//   Yt = X^T A^{-1} X,  Z = C' Yt,  W = C' Yt C'   (d x d),
+// the derivatives of eq. Pfaffian_2nd_der become
+//   tr(A^{-1} A'_g)        = 2 s tr(Z K_g),
+//   sum_g tr(A^{-1} A''_g) = s tr(Yt M),   M = sum_g (K_g^2 C' + 2 K_g C' K_g^T + C' K_g^T K_g^T),
+//   sum_g tr(A^{-1} A'_g A^{-1} A'_g) = s^2 [2 sum_g tr(Z K_g Z K_g) - 2 sum_g tr(Yt K_g W K_g)],
+// and with V_pqrs = sum_g L^g_pq L^g_rs
+//   sum_g tr(P K_g R K_g) = sum_pqrs V_pqrs tr(P^(sp) sigma_y R^(qr) sigma_y)
+// over the 2 x 2 blocks P^(sp), R^(qr): an n^4 contraction per node instead
+// of n_gamma products of d x d matrices.  M depends on the shadow only:
+//   M = (K2 (x) I) C' + C' (K2 (x) I) - 2 sum_qr V_pqrs sigma_y C'^(qr) sigma_y  (block (p, s)),
+// K2 = sum_g L^g L^g.  The node's energy is
+//   E = s tr(Z K_t) + 1/4 [s tr(Yt M) - sum_g tr(A^{-1}A'_g A^{-1}A'_g) + 1/2 sum_g tr(A^{-1}A'_g)^2],
+// K_t the Majorana matrix of t, and the pair's numerator e = sum_k w_k Pf_k E_k
+// beside o = sum_k w_k Pf_k.  The node matrices must be invertible: the
+// nodes are the paper's Chebyshev nodes (the roots of unity contain z = -1,
+// a root of every pair's polynomial when n - eta is odd).
+#pragma once
+#include "so_common.h"
+
+#define SO_EN_NMAX 16
+#define SO_EN_THREADS 256
+
+struct EnTab {
+    double2 s[SO_KMAX];   // node matrices c J + s B
+    double2 c[SO_KMAX];
+    double2 w[SO_KMAX];   // weights (interpolation, channel, prefactor, row-order sign)
+    int K;
+};
+
+// Vt[(s n + p) n^2 + q n + r] = V_pqrs = sum_g L[p n + q][g] L[r n + s][g]
+__global__ __launch_bounds__(256) void k_energy_v(int n, int ng, const double *__restrict__ L,
+                                                  double *__restrict__ Vt) {
+    const int n2 = n * n;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n2 * n2) return;
+    const int sp = e / n2, qr = e - sp * n2;
+    const int s = sp / n, p = sp - s * n, q = qr / n, r = qr - q * n;
+    const double *a = L + (size_t)(p * n + q) * ng;
+    const double *b = L + (size_t)(r * n + s) * ng;
+    double acc = 0.0;
+    for (int g = 0; g < ng; ++g) acc = fma(a[g], b[g], acc);
+    Vt[e] = acc;
+}
+
+// K2 = sum_g L^g L^g (n x n) and Kt, the Majorana matrix of t (d x d):
+//   Kt[2r][2q] = Kt[2r+1][2q+1] = (t_qr - t_rq)/2,
+//   Kt[2r][2q+1] = -i (t_rq + t_qr)/2,  Kt[2r+1][2q] = i (t_rq + t_qr)/2.
+// One block.
+__global__ __launch_bounds__(256) void k_energy_small(int n, int ng, const double *__restrict__ L,
+                                                      const double2 *__restrict__ t, double *__restrict__ K2,
+                                                      double2 *__restrict__ Kt) {
+    const int d = 2 * n;
+    for (int e = threadIdx.x; e < n * n; e += 256) {
+        const int p = e / n, s = e - p * n;
+        double acc = 0.0;
+        for (int q = 0; q < n; ++q)
+            for (int g = 0; g < ng; ++g) acc = fma(L[(size_t)(p * n + q) * ng + g], L[(size_t)(q * n + s) * ng + g], acc);
+        K2[e] = acc;
+    }
+    for (int e = threadIdx.x; e < d * d; e += 256) {
+        const int mu = e / d, nu = e - mu * d;
+        const int r = mu >> 1, a = mu & 1, q = nu >> 1, b = nu & 1;
+        const double2 tqr = t[q * n + r], trq = t[r * n + q];
+        double2 v;
+        if (a == b) v = c_scale(c_sub(tqr, trq), 0.5);
+        else {
+            const double2 h = c_scale(c_add(trq, tqr), 0.5);          // (t_rq + t_qr)/2
+            v = a == 0 ? c_make(h.y, -h.x) : c_make(-h.y, h.x);       // -i h or i h
+        }
+        Kt[e] = v;
+    }
+}
+
+// Per shadow: M = (K2 (x) I) C' + C' (K2 (x) I) - 2 sum_qr V_pqrs sigma_y C'^(qr) sigma_y,
+// with sigma_y c sigma_y = [[c11, -c10], [-c01, c00]] for a real 2 x 2 block c.
+// Ms [S][d][d] row-major.  One block per shadow; C' read from its A-order copy.
+template <int T>
+__global__ __launch_bounds__(256) void k_energy_shadow(int n, const double *__restrict__ Ca,
+                                                       const double *__restrict__ Vt, const double *__restrict__ K2,
+                                                       double *__restrict__ Ms) {
+    constexpr int DP = 16 * T;
+    __shared__ double C[DP * DP];
+    const int d = 2 * n, n2 = n * n;
+    const int64_t s0 = blockIdx.x;
+    const double *Cg = Ca + s0 * DP * DP;
+    for (int e = threadIdx.x; e < d * d; e += 256) {
+        const int mu = e / d, nu = e - mu * d;
+        C[mu * DP + nu] = Cg[ao_index(mu, nu, T)];
+    }
+    __syncthreads();
+    double *out = Ms + s0 * d * d;
+    for (int e = threadIdx.x; e < d * d; e += 256) {
+        const int mu = e / d, nu = e - mu * d;
+        const int p = mu >> 1, a = mu & 1, s = nu >> 1, b = nu & 1;
+        double acc = 0.0;
+        for (int q = 0; q < n; ++q) {
+            acc = fma(K2[p * n + q], C[(2 * q + a) * DP + nu], acc);
+            acc = fma(C[mu * DP + 2 * q + b], K2[q * n + s], acc);
+        }
+        const double sg = ((a + b) & 1) ? -1.0 : 1.0;
+        double v3 = 0.0;
+        const double *vrow = Vt + (size_t)(s * n + p) * n2;
+        for (int q = 0; q < n; ++q)
+            for (int r = 0; r < n; ++r) v3 = fma(vrow[q * n + r], C[(2 * q + 1 - a) * DP + 2 * r + 1 - b], v3);
+        out[e] = acc - 2.0 * sg * v3;
+    }
+}
+
+// block-wide sum of two complex values (all 256 threads get the result)
+__device__ __forceinline__ void en_sum2(double2 &a, double2 &b, double2 *red) {
+    const int t = threadIdx.x;
+    red[t] = a;
+    red[256 + t] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            red[t] = c_add(red[t], red[t + h]);
+            red[256 + t] = c_add(red[256 + t], red[256 + t + h]);
+        }
+        __syncthreads();
+    }
+    a = red[0];
+    b = red[256];
+    __syncthreads();
+}
+
+// index and value of the largest |x|^2 over the block (ties: smallest index)
+__device__ __forceinline__ int en_argmax(double v, int idx, double *rv, int *ri, double &best) {
+    const int t = threadIdx.x;
+    rv[t] = v;
+    ri[t] = idx;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            const double o = rv[t + h];
+            const int oi = ri[t + h];
+            if (o > rv[t] || (o == rv[t] && oi < ri[t])) { rv[t] = o; ri[t] = oi; }
+        }
+        __syncthreads();
+    }
+    best = rv[0];
+    const int r = ri[0];
+    __syncthreads();
+    return r;
+}
+
+// One block of 256 threads per (walker, shadow) pair; grid (S, W).
+//   Xa, Ca      walker matrices and shadow covariances in A order (so_prep.h)
+//   Ms          per-shadow M (d x d), Vt the n^4 table, L [n*n][ng], Kt (d x d)
+//   opair/epair [W][S] complex out: o_ws and the numerator e_ws
+template <int T>
+__global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, int ng, const double *__restrict__ Xa,
+                                                               const double *__restrict__ Ca,
+                                                               const double *__restrict__ Ms,
+                                                               const double *__restrict__ Vt,
+                                                               const double *__restrict__ L,
+                                                               const double2 *__restrict__ Kt, EnTab tab, int64_t S,
+                                                               double2 *__restrict__ opair,
+                                                               double2 *__restrict__ epair,
+                                                               int32_t *__restrict__ wst) {
+    constexpr int DM = 16 * T;
+    __shared__ double2 X[DM * DM];    // m x d
+    __shared__ double C[DM * DM];     // d x d
+    __shared__ double2 Bm[DM * DM];   // m x m
+    __shared__ double2 A[DM * DM];    // node matrix, then its inverse
+    __shared__ double2 Y[DM * DM];    // (C' X^T)^T, then A^{-1} X (m x d)
+    __shared__ double2 Yt[DM * DM];   // X^T A^{-1} X
+    __shared__ double2 Z[DM * DM];    // C' Yt
+    __shared__ double2 Wm[DM * DM];   // C' Yt C'
+    __shared__ double2 red[2 * SO_EN_THREADS];
+    __shared__ double rv[SO_EN_THREADS];
+    __shared__ int ri[SO_EN_THREADS];
+    __shared__ double2 fcol[DM];
+    __shared__ double2 zeta[SO_EN_NMAX * SO_EN_NMAX];
+    __shared__ int piv[DM];
+    const int t = threadIdx.x;
+    const int d = 2 * n, m = 2 * n - eta, ne = n - eta, n2 = n * n;
+    const int64_t s0 = blockIdx.x, w0 = blockIdx.y;
+    const double *Xg = Xa + w0 * DM * DM;
+    const double *Cg = Ca + s0 * DM * DM;
+    const double *Mg = Ms + s0 * d * d;
+    // X (m x d complex) from Xall = [Re X_O; Im X_O; X_U], C' (d x d)
+    for (int e = t; e < m * d; e += SO_EN_THREADS) {
+        const int i = e / d, mu = e - i * d;
+        X[i * DM + mu] = i < eta ? c_make(Xg[ao_index(i, mu, T)], Xg[ao_index(eta + i, mu, T)])
+                                 : c_make(Xg[ao_index(eta + i, mu, T)], 0.0);
+    }
+    for (int e = t; e < d * d; e += SO_EN_THREADS) {
+        const int mu = e / d, nu = e - mu * d;
+        C[mu * DM + nu] = Cg[ao_index(mu, nu, T)];
+    }
+    __syncthreads();
+    // B = X (C' X^T): Y[j][mu] = sum_nu C'[mu][nu] X[j][nu], B[i][j] = sum_mu X[i][mu] Y[j][mu]
+    for (int e = t; e < m * d; e += SO_EN_THREADS) {
+        const int j = e / d, mu = e - j * d;
+        double2 acc = c_make(0.0, 0.0);
+        for (int nu = 0; nu < d; ++nu) acc = c_add(acc, c_scale(X[j * DM + nu], C[mu * DM + nu]));
+        Y[j * DM + mu] = acc;
+    }
+    __syncthreads();
+    for (int e = t; e < m * m; e += SO_EN_THREADS) {
+        const int i = e / m, j = e - i * m;
+        double2 acc = c_make(0.0, 0.0);
+        for (int mu = 0; mu < d; ++mu) acc = c_fma(X[i * DM + mu], Y[j * DM + mu], acc);
+        Bm[i * DM + j] = acc;
+    }
+    __syncthreads();
+    double2 osum = c_make(0.0, 0.0), esum = c_make(0.0, 0.0);
+    bool singular = false;
+    auto build_a = [&](double2 sk, double2 ck) {
+        for (int e = t; e < m * m; e += SO_EN_THREADS) {
+            const int i = e / m, j = e - i * m;
+            double2 v = c_mul(sk, Bm[i * DM + j]);
+            if (i >= eta && j >= eta) {
+                const int u = i - eta, v2 = j - eta;
+                if (u < ne && v2 == 2 * ne - 1 - u) v = c_add(v, ck);
+                else if (u >= ne && v2 == 2 * ne - 1 - u) v = c_sub(v, ck);
+            }
+            A[i * DM + j] = v;
+        }
+        __syncthreads();
+    };
+    for (int k = 0; k < tab.K; ++k) {
+        const double2 sk = tab.s[k], ck = tab.c[k], wk = tab.w[k];
+        // ---- Pf(A) by Parlett-Reid with pivoting (A destroyed) ----
+        build_a(sk, ck);
+        double2 pf = c_make(1.0, 0.0);
+        for (int kk = 0; kk < m - 1; kk += 2) {
+            const int j = kk + 1 + t;
+            double best;
+            const int p = en_argmax(j < m ? c_abs2(A[kk * DM + j]) : -1.0, j < m ? j : m, rv, ri, best);
+            if (best == 0.0) { pf = c_make(0.0, 0.0); break; }
+            if (p != kk + 1) {
+                for (int c = t; c < m; c += SO_EN_THREADS) {
+                    const double2 x = A[(kk + 1) * DM + c];
+                    A[(kk + 1) * DM + c] = A[p * DM + c];
+                    A[p * DM + c] = x;
+                }
+                __syncthreads();
+                for (int r = t; r < m; r += SO_EN_THREADS) {
+                    const double2 x = A[r * DM + kk + 1];
+                    A[r * DM + kk + 1] = A[r * DM + p];
+                    A[r * DM + p] = x;
+                }
+                __syncthreads();
+                pf = c_neg(pf);
+            }
+            const double2 a = A[kk * DM + kk + 1];
+            pf = c_mul(pf, a);
+            const double2 ia = c_inv(a);
+            const int rem = m - kk - 2;
+            for (int e = t; e < rem * rem; e += SO_EN_THREADS) {
+                const int i = kk + 2 + e / rem, jj = kk + 2 + e % rem;
+                // A_ij += (A[k+1][i] A[k][j] - A[k][i] A[k+1][j]) / a
+                const double2 num = c_sub(c_mul(A[(kk + 1) * DM + i], A[kk * DM + jj]),
+                                          c_mul(A[kk * DM + i], A[(kk + 1) * DM + jj]));
+                A[i * DM + jj] = c_fma(num, ia, A[i * DM + jj]);
+            }
+            __syncthreads();
+        }
+        osum = c_fma(wk, pf, osum);
+        // ---- A^{-1} by Gauss-Jordan with partial pivoting (in place) ----
+        build_a(sk, ck);
+        bool sing = false;
+        for (int c = 0; c < m; ++c) {
+            const int r = c + t;
+            double best;
+            const int p = en_argmax(r < m ? c_abs2(A[r * DM + c]) : -1.0, r < m ? r : m, rv, ri, best);
+            if (best == 0.0) { sing = true; break; }
+            if (t == 0) piv[c] = p;
+            if (p != c) {
+                for (int j = t; j < m; j += SO_EN_THREADS) {
+                    const double2 x = A[c * DM + j];
+                    A[c * DM + j] = A[p * DM + j];
+                    A[p * DM + j] = x;
+                }
+                __syncthreads();
+            }
+            const double2 ip = c_inv(A[c * DM + c]);
+            for (int i = t; i < m; i += SO_EN_THREADS) fcol[i] = A[i * DM + c];
+            __syncthreads();
+            for (int j = t; j < m; j += SO_EN_THREADS) A[c * DM + j] = j == c ? ip : c_mul(A[c * DM + j], ip);
+            __syncthreads();
+            for (int e = t; e < m * m; e += SO_EN_THREADS) {
+                const int i = e / m, j = e - i * m;
+                if (i == c) continue;
+                A[i * DM + j] = j == c ? c_neg(c_mul(fcol[i], ip)) : c_sub(A[i * DM + j], c_mul(fcol[i], A[c * DM + j]));
+            }
+            __syncthreads();
+        }
+        if (sing) {
+            singular = true;
+            continue;
+        }
+        for (int c = m - 1; c >= 0; --c) {
+            const int p = piv[c];
+            if (p != c) {
+                for (int i = t; i < m; i += SO_EN_THREADS) {
+                    const double2 x = A[i * DM + c];
+                    A[i * DM + c] = A[i * DM + p];
+                    A[i * DM + p] = x;
+                }
+                __syncthreads();
+            }
+        }
+        // ---- Y = A^{-1} X, Yt = X^T Y, Z = C' Yt, W = Z C' ----
+        for (int e = t; e < m * d; e += SO_EN_THREADS) {
+            const int i = e / d, mu = e - i * d;
+            double2 acc = c_make(0.0, 0.0);
+            for (int l = 0; l < m; ++l) acc = c_fma(A[i * DM + l], X[l * DM + mu], acc);
+            Y[i * DM + mu] = acc;
+        }
+        __syncthreads();
+        for (int e = t; e < d * d; e += SO_EN_THREADS) {
+            const int a = e / d, b = e - a * d;
+            double2 acc = c_make(0.0, 0.0);
+            for (int i = 0; i < m; ++i) acc = c_fma(X[i * DM + a], Y[i * DM + b], acc);
+            Yt[a * DM + b] = acc;
+        }
+        __syncthreads();
+        for (int e = t; e < d * d; e += SO_EN_THREADS) {
+            const int a = e / d, b = e - a * d;
+            double2 acc = c_make(0.0, 0.0);
+            for (int c = 0; c < d; ++c) acc = c_add(acc, c_scale(Yt[c * DM + b], C[a * DM + c]));
+            Z[a * DM + b] = acc;
+        }
+        __syncthreads();
+        for (int e = t; e < d * d; e += SO_EN_THREADS) {
+            const int a = e / d, b = e - a * d;
+            double2 acc = c_make(0.0, 0.0);
+            for (int c = 0; c < d; ++c) acc = c_add(acc, c_scale(Z[a * DM + c], C[c * DM + b]));
+            Wm[a * DM + b] = acc;
+        }
+        // zeta_pq = tr(Z^(qp) sigma_y) = i (Z[2q][2p+1] - Z[2q+1][2p])
+        for (int e = t; e < n2; e += SO_EN_THREADS) {
+            const int p = e / n, q = e - p * n;
+            const double2 df = c_sub(Z[(2 * q) * DM + 2 * p + 1], Z[(2 * q + 1) * DM + 2 * p]);
+            zeta[e] = c_make(-df.y, df.x);
+        }
+        __syncthreads();
+        // one-body s tr(Z Kt) and s tr(Yt M)
+        double2 one = c_make(0.0, 0.0), bs = c_make(0.0, 0.0);
+        for (int e = t; e < d * d; e += SO_EN_THREADS) {
+            const int a = e / d, b = e - a * d;
+            one = c_fma(Z[a * DM + b], Kt[b * d + a], one);
+            bs = c_add(bs, c_scale(Yt[a * DM + b], Mg[b * d + a]));
+        }
+        en_sum2(one, bs, red);
+        // sum_g (tr(Z K_g))^2 with tr(Z K_g) = sum_pq L^g_pq zeta_pq
+        double2 asq = c_make(0.0, 0.0), dummy = c_make(0.0, 0.0);
+        for (int g = t; g < ng; g += SO_EN_THREADS) {
+            double2 tg = c_make(0.0, 0.0);
+            for (int pq = 0; pq < n2; ++pq) tg = c_add(tg, c_scale(zeta[pq], L[(size_t)pq * ng + g]));
+            asq = c_fma(tg, tg, asq);
+        }
+        en_sum2(asq, dummy, red);
+        // c1 = sum V_pqrs tr(Z^(sp) sy Z^(qr) sy), c2 = sum V_pqrs tr(Yt^(sp) sy W^(qr) sy);
+        // tr(P sy R sy) = P00 R11 - P01 R01 - P10 R10 + P11 R00 for 2 x 2 blocks
+        double2 c1 = c_make(0.0, 0.0), c2 = c_make(0.0, 0.0);
+        if (t < n2) {
+            const int q = t / n, r = t - q * n;
+            const double2 z00 = Z[(2 * q) * DM + 2 * r], z01 = Z[(2 * q) * DM + 2 * r + 1];
+            const double2 z10 = Z[(2 * q + 1) * DM + 2 * r], z11 = Z[(2 * q + 1) * DM + 2 * r + 1];
+            const double2 w00 = Wm[(2 * q) * DM + 2 * r], w01 = Wm[(2 * q) * DM + 2 * r + 1];
+            const double2 w10 = Wm[(2 * q + 1) * DM + 2 * r], w11 = Wm[(2 * q + 1) * DM + 2 * r + 1];
+            for (int sp = 0; sp < n2; ++sp) {
+                const int s = sp / n, p = sp - s * n;
+                const double v = Vt[(size_t)sp * n2 + t];
+                const double2 *zs = Z + (2 * s) * DM + 2 * p;
+                const double2 *ys = Yt + (2 * s) * DM + 2 * p;
+                double2 f1 = c_mul(zs[0], z11);
+                f1 = c_sub(f1, c_mul(zs[1], z01));
+                f1 = c_sub(f1, c_mul(zs[DM], z10));
+                f1 = c_fma(zs[DM + 1], z00, f1);
+                double2 f2 = c_mul(ys[0], w11);
+                f2 = c_sub(f2, c_mul(ys[1], w01));
+                f2 = c_sub(f2, c_mul(ys[DM], w10));
+                f2 = c_fma(ys[DM + 1], w00, f2);
+                c1 = c_add(c1, c_scale(f1, v));
+                c2 = c_add(c2, c_scale(f2, v));
+            }
+        }
+        en_sum2(c1, c2, red);
+        const double2 s2 = c_mul(sk, sk);
+        const double2 csum = c_scale(c_mul(s2, c_sub(c1, c2)), 2.0);
+        const double2 asum = c_scale(c_mul(s2, asq), 4.0);
+        // E = s tr(Z Kt) + 1/4 [s tr(Yt M) - csum + asum / 2]
+        double2 E = c_mul(sk, one);
+        E = c_add(E, c_scale(c_add(c_sub(c_mul(sk, bs), csum), c_scale(asum, 0.5)), 0.25));
+        esum = c_fma(c_mul(wk, pf), E, esum);
+    }
+    if (t == 0) {
+        const int64_t ix = w0 * S + s0;
+        opair[ix] = osum;
+        epair[ix] = esum;
+        if (singular && wst) atomicOr(wst + w0, SO_WSTAT_SINGULAR);
+    }
+}
+
+// Per walker, in a fixed order: S_w = (1/S) sum_s o_ws, N_w = (1/S) sum_s e_ws,
+// E_w = N_w / S_w.  One block of 256 threads per walker.
+__global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, const double2 *__restrict__ opair,
+                                                       const double2 *__restrict__ epair, double2 *__restrict__ overlap,
+                                                       double2 *__restrict__ numer, double2 *__restrict__ energy,
+                                                       int32_t *__restrict__ wst) {
+    __shared__ double2 red[512];
+    const int t = threadIdx.x;
+    const int64_t w = blockIdx.x;
+    double2 so = c_make(0.0, 0.0), se = c_make(0.0, 0.0);
+    for (int64_t s = t; s < S; s += 256) {
+        so = c_add(so, opair[w * S + s]);
+        se = c_add(se, epair[w * S + s]);
+    }
+    en_sum2(so, se, red);
+    if (t == 0) {
+        const double inv = 1.0 / (double)S;
+        so = c_scale(so, inv);
+        se = c_scale(se, inv);
+        if (overlap) overlap[w] = so;
+        if (numer) numer[w] = se;
+        if (energy) energy[w] = c_mul(se, c_inv(so));
+        if (wst && !(isfinite(so.x) && isfinite(so.y) && isfinite(se.x) && isfinite(se.y)))
+            wst[w] |= SO_WSTAT_NONFINITE;
+    }
+}

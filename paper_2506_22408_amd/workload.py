@@ -17,6 +17,8 @@ Recipe (numpy ``default_rng(seed)``, PCG64, drawn in this order):
                  (uniform over even-parity strings); bit j is b_{j+1} [S] u64
   L        Cholesky-like vectors, N(0, 0.1^2), symmetrised per index pair
                                                                   [n*n, n_gamma]
+  t        (local-energy workloads) one-body matrix, N(0, 0.1^2),
+           symmetrised, drawn after L                             [n, n] c128
 
 Full-space walkers for the virtual-correlation-energy path (make_vce), drawn
 after nothing else from their own seed: alpha, then beta orbitals, each the
@@ -78,6 +80,7 @@ class Workload:
     Q: np.ndarray
     bits: np.ndarray
     L: np.ndarray | None = None
+    t: np.ndarray | None = None
 
     @property
     def W(self) -> int:
@@ -88,14 +91,20 @@ class Workload:
         return self.Q.shape[0]
 
 
+def one_body(rng, n: int, scale: float = 0.1) -> np.ndarray:
+    h = rng.standard_normal((n, n)) * scale
+    return np.ascontiguousarray(0.5 * (h + h.T)).astype(np.complex128)
+
+
 def make(name: str, n: int, eta: int, W: int, S: int, seed: int, n_gamma: int = 0,
-         orthonormal: bool = True) -> Workload:
+         orthonormal: bool = True, with_t: bool = False) -> Workload:
     rng = np.random.default_rng(seed)
     phi = walkers(rng, W, n, eta, orthonormal)
     Q = haar_so(rng, S, 2 * n)
     bits = even_bits(rng, S, n)
     L = cholesky_like(rng, n, n_gamma) if n_gamma else None
-    return Workload(name, n, eta, phi, Q, bits, L)
+    t = one_body(rng, n) if with_t else None
+    return Workload(name, n, eta, phi, Q, bits, L, t)
 
 
 # The five workloads: small plain, paper-sized, uneven batch, gradient, precision.
@@ -104,6 +113,7 @@ CONFIGS = {
     "paper_n16": dict(n=16, eta=8, W=1024, S=10000, seed=2),
     "grad_n16": dict(n=16, eta=8, W=1024, S=10000, seed=4, n_gamma=200),
     "precision_n24": dict(n=24, eta=12, W=2048, S=50000, seed=5),
+    "energy_n16": dict(n=16, eta=8, W=128, S=1000, seed=7, n_gamma=200, with_t=True),
 }
 UNEVEN = [dict(n=8, eta=4, W=4096, S=2000, seed=30),
           dict(n=12, eta=6, W=2048, S=5000, seed=31),
