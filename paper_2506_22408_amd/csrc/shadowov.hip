@@ -1127,12 +1127,18 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     hipEvent_t ea = nullptr;
     if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
     const dim3 grid((unsigned)S, (unsigned)W);
-    if (T == 1)
-        hipLaunchKernelGGL(k_energy_pair<1>, grid, dim3(SO_EN_THREADS), 0, st, n, eta, n_gamma, Xa, Ca, Ms, Vt, L,
-                           Kt, tab, S, op, ep, wst);
-    else
-        hipLaunchKernelGGL(k_energy_pair<2>, grid, dim3(SO_EN_THREADS), 0, st, n, eta, n_gamma, Xa, Ca, Ms, Vt, L,
-                           Kt, tab, S, op, ep, wst);
+    const size_t lds = energy_lds_bytes(n, eta);
+    if (T == 1) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_energy_pair<1>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_energy_pair<1>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xa, Ca, Ms, Vt, Kt, tab, S,
+                           op, ep, wst);
+    } else {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_energy_pair<2>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_energy_pair<2>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xa, Ca, Ms, Vt, Kt, tab, S,
+                           op, ep, wst);
+    }
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     if (prof_end(st, ea, PROF_ENERGY, W * S) != hipSuccess) return SO_ERR_HIP;
     hipLaunchKernelGGL(k_energy_reduce, dim3((unsigned)W), dim3(256), 0, st, S, op, ep,

@@ -8,7 +8,7 @@
 // X -> X e^{lambda K}, [Lhat, gamma_rho] = sum_sigma K[rho][sigma] gamma_sigma;
 // for a real symmetric L, K = L (x) sigma_y (2 x 2 blocks, sigma_y =
 // [[0,-i],[i,0]]), so K^T = -K.  Per node (A = c J + s B, Pf, A^{-1}), with
-//   Yt = X^T A^{-1} X,  Z = C' Yt,  W = C' Yt C'   (d x d),
+//   Yt = X^T A^{-1} X,  Z = C' Yt,  W = C' Yt C' = Z C'   (d x d),
 // the derivatives of eq. Pfaffian_2nd_der become
 //   tr(A^{-1} A'_g)        = 2 s tr(Z K_g),
 //   sum_g tr(A^{-1} A''_g) = s tr(Yt M),   M = sum_g (K_g^2 C' + 2 K_g C' K_g^T + C' K_g^T K_g^T),
@@ -116,75 +116,88 @@ __global__ __launch_bounds__(256) void k_energy_shadow(int n, const double *__re
     }
 }
 
-// block-wide sum of two complex values (all 256 threads get the result)
+__device__ __forceinline__ double en_wsum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// block-wide sum of two complex values (all threads get the result): a
+// fixed-order reduction within each wave, then the four wave sums in order
 __device__ __forceinline__ void en_sum2(double2 &a, double2 &b, double2 *red) {
-    const int t = threadIdx.x;
-    red[t] = a;
-    red[256 + t] = b;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h) {
-            red[t] = c_add(red[t], red[t + h]);
-            red[256 + t] = c_add(red[256 + t], red[256 + t + h]);
-        }
-        __syncthreads();
+    const int t = threadIdx.x, wv = t >> 6;
+    const double ar = en_wsum(a.x), ai = en_wsum(a.y), br = en_wsum(b.x), bi = en_wsum(b.y);
+    if ((t & 63) == 0) {
+        red[wv] = c_make(ar, ai);
+        red[4 + wv] = c_make(br, bi);
     }
-    a = red[0];
-    b = red[256];
+    __syncthreads();
+    a = c_add(c_add(red[0], red[1]), c_add(red[2], red[3]));
+    b = c_add(c_add(red[4], red[5]), c_add(red[6], red[7]));
     __syncthreads();
 }
 
-// index and value of the largest |x|^2 over the block (ties: smallest index)
+// index and value of the largest |x|^2 among the first 64 threads (the
+// candidates of a pivot search never exceed 32; ties: smallest index),
+// broadcast to the block through one barrier.
 __device__ __forceinline__ int en_argmax(double v, int idx, double *rv, int *ri, double &best) {
     const int t = threadIdx.x;
-    rv[t] = v;
-    ri[t] = idx;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (t < h) {
-            const double o = rv[t + h];
-            const int oi = ri[t + h];
-            if (o > rv[t] || (o == rv[t] && oi < ri[t])) { rv[t] = o; ri[t] = oi; }
+    if (t < 64) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(v, o);
+            const int oi = __shfl_xor(idx, o);
+            if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
         }
-        __syncthreads();
+        if (t == 0) { rv[0] = v; ri[0] = idx; }
     }
-    best = rv[0];
-    const int r = ri[0];
     __syncthreads();
-    return r;
+    best = rv[0];
+    return ri[0];
+}
+
+// LDS of k_energy_pair, in complex entries (C' counts half): X [m][d],
+// C' [d][d] real, B [m][m], A [max(m^2, 2 n^2)] (the node matrix and its
+// inverse, then zeta and its transpose), YZ [d][d] (A^{-1} X, then Z),
+// Yt [d][d].  At n = 16, eta = 8 this is 72 KB: two blocks per CU.
+__host__ __device__ inline size_t energy_lds_bytes(int n, int eta) {
+    const size_t d = 2 * n, m = 2 * n - eta, n2 = (size_t)n * n;
+    const size_t asz = m * m > 2 * n2 ? m * m : 2 * n2;
+    return 16 * (m * d + m * m + asz + 2 * d * d) + 8 * d * d;
 }
 
 // One block of 256 threads per (walker, shadow) pair; grid (S, W).
 //   Xa, Ca      walker matrices and shadow covariances in A order (so_prep.h)
-//   Ms          per-shadow M (d x d), Vt the n^4 table, L [n*n][ng], Kt (d x d)
+//   Ms          per-shadow M (d x d), Vt the n^4 table, Kt (d x d)
 //   opair/epair [W][S] complex out: o_ws and the numerator e_ws
+// Matrices are row-major with their own row length (d or m).
 template <int T>
-__global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, int ng, const double *__restrict__ Xa,
+__global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, const double *__restrict__ Xa,
                                                                const double *__restrict__ Ca,
                                                                const double *__restrict__ Ms,
                                                                const double *__restrict__ Vt,
-                                                               const double *__restrict__ L,
                                                                const double2 *__restrict__ Kt, EnTab tab, int64_t S,
                                                                double2 *__restrict__ opair,
                                                                double2 *__restrict__ epair,
                                                                int32_t *__restrict__ wst) {
-    constexpr int DM = 16 * T;
-    __shared__ double2 X[DM * DM];    // m x d
-    __shared__ double C[DM * DM];     // d x d
-    __shared__ double2 Bm[DM * DM];   // m x m
-    __shared__ double2 A[DM * DM];    // node matrix, then its inverse
-    __shared__ double2 Y[DM * DM];    // (C' X^T)^T, then A^{-1} X (m x d)
-    __shared__ double2 Yt[DM * DM];   // X^T A^{-1} X
-    __shared__ double2 Z[DM * DM];    // C' Yt
-    __shared__ double2 Wm[DM * DM];   // C' Yt C'
-    __shared__ double2 red[2 * SO_EN_THREADS];
-    __shared__ double rv[SO_EN_THREADS];
-    __shared__ int ri[SO_EN_THREADS];
+    constexpr int DM = 16 * T;                      // bound on d and m
+    constexpr int NE = DM * DM / SO_EN_THREADS;     // bound on elements per thread
+    extern __shared__ double2 esm[];
+    __shared__ double2 red[8];
+    __shared__ double rv[1];
+    __shared__ int ri[1];
     __shared__ double2 fcol[DM];
-    __shared__ double2 zeta[SO_EN_NMAX * SO_EN_NMAX];
     __shared__ int piv[DM];
     const int t = threadIdx.x;
     const int d = 2 * n, m = 2 * n - eta, ne = n - eta, n2 = n * n;
+    const int asz = m * m > 2 * n2 ? m * m : 2 * n2;
+    double2 *X = esm;                 // m x d
+    double2 *Bm = X + m * d;          // m x m
+    double2 *A = Bm + m * m;          // m x m; later zeta (n2) and zetaT (n2)
+    double2 *YZ = A + asz;            // d x d
+    double2 *Yt = YZ + d * d;         // d x d
+    double *C = reinterpret_cast<double *>(Yt + d * d);   // d x d
+    double2 *zeta = A, *zetaT = A + n2;
     const int64_t s0 = blockIdx.x, w0 = blockIdx.y;
     const double *Xg = Xa + w0 * DM * DM;
     const double *Cg = Ca + s0 * DM * DM;
@@ -192,27 +205,27 @@ __global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, i
     // X (m x d complex) from Xall = [Re X_O; Im X_O; X_U], C' (d x d)
     for (int e = t; e < m * d; e += SO_EN_THREADS) {
         const int i = e / d, mu = e - i * d;
-        X[i * DM + mu] = i < eta ? c_make(Xg[ao_index(i, mu, T)], Xg[ao_index(eta + i, mu, T)])
-                                 : c_make(Xg[ao_index(eta + i, mu, T)], 0.0);
+        X[e] = i < eta ? c_make(Xg[ao_index(i, mu, T)], Xg[ao_index(eta + i, mu, T)])
+                       : c_make(Xg[ao_index(eta + i, mu, T)], 0.0);
     }
     for (int e = t; e < d * d; e += SO_EN_THREADS) {
         const int mu = e / d, nu = e - mu * d;
-        C[mu * DM + nu] = Cg[ao_index(mu, nu, T)];
+        C[e] = Cg[ao_index(mu, nu, T)];
     }
     __syncthreads();
-    // B = X (C' X^T): Y[j][mu] = sum_nu C'[mu][nu] X[j][nu], B[i][j] = sum_mu X[i][mu] Y[j][mu]
+    // B = X (C' X^T): YZ[j][mu] = sum_nu C'[mu][nu] X[j][nu], B[i][j] = sum_mu X[i][mu] YZ[j][mu]
     for (int e = t; e < m * d; e += SO_EN_THREADS) {
         const int j = e / d, mu = e - j * d;
         double2 acc = c_make(0.0, 0.0);
-        for (int nu = 0; nu < d; ++nu) acc = c_add(acc, c_scale(X[j * DM + nu], C[mu * DM + nu]));
-        Y[j * DM + mu] = acc;
+        for (int nu = 0; nu < d; ++nu) acc = c_add(acc, c_scale(X[j * d + nu], C[mu * d + nu]));
+        YZ[e] = acc;
     }
     __syncthreads();
     for (int e = t; e < m * m; e += SO_EN_THREADS) {
         const int i = e / m, j = e - i * m;
         double2 acc = c_make(0.0, 0.0);
-        for (int mu = 0; mu < d; ++mu) acc = c_fma(X[i * DM + mu], Y[j * DM + mu], acc);
-        Bm[i * DM + j] = acc;
+        for (int mu = 0; mu < d; ++mu) acc = c_fma(X[i * d + mu], YZ[j * d + mu], acc);
+        Bm[e] = acc;
     }
     __syncthreads();
     double2 osum = c_make(0.0, 0.0), esum = c_make(0.0, 0.0);
@@ -220,13 +233,13 @@ __global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, i
     auto build_a = [&](double2 sk, double2 ck) {
         for (int e = t; e < m * m; e += SO_EN_THREADS) {
             const int i = e / m, j = e - i * m;
-            double2 v = c_mul(sk, Bm[i * DM + j]);
+            double2 v = c_mul(sk, Bm[e]);
             if (i >= eta && j >= eta) {
                 const int u = i - eta, v2 = j - eta;
                 if (u < ne && v2 == 2 * ne - 1 - u) v = c_add(v, ck);
                 else if (u >= ne && v2 == 2 * ne - 1 - u) v = c_sub(v, ck);
             }
-            A[i * DM + j] = v;
+            A[e] = v;
         }
         __syncthreads();
     };
@@ -238,33 +251,33 @@ __global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, i
         for (int kk = 0; kk < m - 1; kk += 2) {
             const int j = kk + 1 + t;
             double best;
-            const int p = en_argmax(j < m ? c_abs2(A[kk * DM + j]) : -1.0, j < m ? j : m, rv, ri, best);
+            const int p = en_argmax(j < m ? c_abs2(A[kk * m + j]) : -1.0, j < m ? j : m, rv, ri, best);
             if (best == 0.0) { pf = c_make(0.0, 0.0); break; }
             if (p != kk + 1) {
                 for (int c = t; c < m; c += SO_EN_THREADS) {
-                    const double2 x = A[(kk + 1) * DM + c];
-                    A[(kk + 1) * DM + c] = A[p * DM + c];
-                    A[p * DM + c] = x;
+                    const double2 x = A[(kk + 1) * m + c];
+                    A[(kk + 1) * m + c] = A[p * m + c];
+                    A[p * m + c] = x;
                 }
                 __syncthreads();
                 for (int r = t; r < m; r += SO_EN_THREADS) {
-                    const double2 x = A[r * DM + kk + 1];
-                    A[r * DM + kk + 1] = A[r * DM + p];
-                    A[r * DM + p] = x;
+                    const double2 x = A[r * m + kk + 1];
+                    A[r * m + kk + 1] = A[r * m + p];
+                    A[r * m + p] = x;
                 }
                 __syncthreads();
                 pf = c_neg(pf);
             }
-            const double2 a = A[kk * DM + kk + 1];
+            const double2 a = A[kk * m + kk + 1];
             pf = c_mul(pf, a);
             const double2 ia = c_inv(a);
             const int rem = m - kk - 2;
             for (int e = t; e < rem * rem; e += SO_EN_THREADS) {
                 const int i = kk + 2 + e / rem, jj = kk + 2 + e % rem;
                 // A_ij += (A[k+1][i] A[k][j] - A[k][i] A[k+1][j]) / a
-                const double2 num = c_sub(c_mul(A[(kk + 1) * DM + i], A[kk * DM + jj]),
-                                          c_mul(A[kk * DM + i], A[(kk + 1) * DM + jj]));
-                A[i * DM + jj] = c_fma(num, ia, A[i * DM + jj]);
+                const double2 num = c_sub(c_mul(A[(kk + 1) * m + i], A[kk * m + jj]),
+                                          c_mul(A[kk * m + i], A[(kk + 1) * m + jj]));
+                A[i * m + jj] = c_fma(num, ia, A[i * m + jj]);
             }
             __syncthreads();
         }
@@ -275,26 +288,26 @@ __global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, i
         for (int c = 0; c < m; ++c) {
             const int r = c + t;
             double best;
-            const int p = en_argmax(r < m ? c_abs2(A[r * DM + c]) : -1.0, r < m ? r : m, rv, ri, best);
+            const int p = en_argmax(r < m ? c_abs2(A[r * m + c]) : -1.0, r < m ? r : m, rv, ri, best);
             if (best == 0.0) { sing = true; break; }
             if (t == 0) piv[c] = p;
             if (p != c) {
                 for (int j = t; j < m; j += SO_EN_THREADS) {
-                    const double2 x = A[c * DM + j];
-                    A[c * DM + j] = A[p * DM + j];
-                    A[p * DM + j] = x;
+                    const double2 x = A[c * m + j];
+                    A[c * m + j] = A[p * m + j];
+                    A[p * m + j] = x;
                 }
                 __syncthreads();
             }
-            const double2 ip = c_inv(A[c * DM + c]);
-            for (int i = t; i < m; i += SO_EN_THREADS) fcol[i] = A[i * DM + c];
+            const double2 ip = c_inv(A[c * m + c]);
+            for (int i = t; i < m; i += SO_EN_THREADS) fcol[i] = A[i * m + c];
             __syncthreads();
-            for (int j = t; j < m; j += SO_EN_THREADS) A[c * DM + j] = j == c ? ip : c_mul(A[c * DM + j], ip);
+            for (int j = t; j < m; j += SO_EN_THREADS) A[c * m + j] = j == c ? ip : c_mul(A[c * m + j], ip);
             __syncthreads();
             for (int e = t; e < m * m; e += SO_EN_THREADS) {
                 const int i = e / m, j = e - i * m;
                 if (i == c) continue;
-                A[i * DM + j] = j == c ? c_neg(c_mul(fcol[i], ip)) : c_sub(A[i * DM + j], c_mul(fcol[i], A[c * DM + j]));
+                A[e] = j == c ? c_neg(c_mul(fcol[i], ip)) : c_sub(A[e], c_mul(fcol[i], A[c * m + j]));
             }
             __syncthreads();
         }
@@ -306,91 +319,129 @@ __global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, i
             const int p = piv[c];
             if (p != c) {
                 for (int i = t; i < m; i += SO_EN_THREADS) {
-                    const double2 x = A[i * DM + c];
-                    A[i * DM + c] = A[i * DM + p];
-                    A[i * DM + p] = x;
+                    const double2 x = A[i * m + c];
+                    A[i * m + c] = A[i * m + p];
+                    A[i * m + p] = x;
                 }
                 __syncthreads();
             }
         }
-        // ---- Y = A^{-1} X, Yt = X^T Y, Z = C' Yt, W = Z C' ----
-        for (int e = t; e < m * d; e += SO_EN_THREADS) {
-            const int i = e / d, mu = e - i * d;
-            double2 acc = c_make(0.0, 0.0);
-            for (int l = 0; l < m; ++l) acc = c_fma(A[i * DM + l], X[l * DM + mu], acc);
-            Y[i * DM + mu] = acc;
+        // ---- YZ = A^{-1} X (m x d), Yt = X^T YZ, then YZ = Z = C' Yt ----
+        // (a compile-time bound on the elements per thread, so that one
+        // thread's independent accumulations interleave)
+        {
+            double2 acc[NE];
+#pragma unroll
+            for (int u = 0; u < NE; ++u) acc[u] = c_make(0.0, 0.0);
+            for (int l = 0; l < m; ++l)
+#pragma unroll
+                for (int u = 0; u < NE; ++u) {
+                    const int e = t + u * SO_EN_THREADS, i = e / d, mu = e - i * d;
+                    if (e < m * d) acc[u] = c_fma(A[i * m + l], X[l * d + mu], acc[u]);
+                }
+#pragma unroll
+            for (int u = 0; u < NE; ++u)
+                if (t + u * SO_EN_THREADS < m * d) YZ[t + u * SO_EN_THREADS] = acc[u];
         }
         __syncthreads();
-        for (int e = t; e < d * d; e += SO_EN_THREADS) {
-            const int a = e / d, b = e - a * d;
-            double2 acc = c_make(0.0, 0.0);
-            for (int i = 0; i < m; ++i) acc = c_fma(X[i * DM + a], Y[i * DM + b], acc);
-            Yt[a * DM + b] = acc;
+        {
+            double2 acc[NE];
+#pragma unroll
+            for (int u = 0; u < NE; ++u) acc[u] = c_make(0.0, 0.0);
+            for (int i = 0; i < m; ++i)
+#pragma unroll
+                for (int u = 0; u < NE; ++u) {
+                    const int e = t + u * SO_EN_THREADS, a = e / d, b = e - a * d;
+                    if (e < d * d) acc[u] = c_fma(X[i * d + a], YZ[i * d + b], acc[u]);
+                }
+#pragma unroll
+            for (int u = 0; u < NE; ++u)
+                if (t + u * SO_EN_THREADS < d * d) Yt[t + u * SO_EN_THREADS] = acc[u];
         }
         __syncthreads();
-        for (int e = t; e < d * d; e += SO_EN_THREADS) {
-            const int a = e / d, b = e - a * d;
-            double2 acc = c_make(0.0, 0.0);
-            for (int c = 0; c < d; ++c) acc = c_add(acc, c_scale(Yt[c * DM + b], C[a * DM + c]));
-            Z[a * DM + b] = acc;
+        {
+            double2 acc[NE];
+#pragma unroll
+            for (int u = 0; u < NE; ++u) acc[u] = c_make(0.0, 0.0);
+            for (int c = 0; c < d; ++c)
+#pragma unroll
+                for (int u = 0; u < NE; ++u) {
+                    const int e = t + u * SO_EN_THREADS, a = e / d, b = e - a * d;
+                    if (e < d * d) acc[u] = c_add(acc[u], c_scale(Yt[c * d + b], C[a * d + c]));
+                }
+#pragma unroll
+            for (int u = 0; u < NE; ++u)
+                if (t + u * SO_EN_THREADS < d * d) YZ[t + u * SO_EN_THREADS] = acc[u];
         }
         __syncthreads();
-        for (int e = t; e < d * d; e += SO_EN_THREADS) {
-            const int a = e / d, b = e - a * d;
-            double2 acc = c_make(0.0, 0.0);
-            for (int c = 0; c < d; ++c) acc = c_add(acc, c_scale(Z[a * DM + c], C[c * DM + b]));
-            Wm[a * DM + b] = acc;
-        }
-        // zeta_pq = tr(Z^(qp) sigma_y) = i (Z[2q][2p+1] - Z[2q+1][2p])
+        double2 *Z = YZ;
+        // zeta_pq = tr(Z^(qp) sigma_y) = i (Z[2q][2p+1] - Z[2q+1][2p]), and its transpose
         for (int e = t; e < n2; e += SO_EN_THREADS) {
             const int p = e / n, q = e - p * n;
-            const double2 df = c_sub(Z[(2 * q) * DM + 2 * p + 1], Z[(2 * q + 1) * DM + 2 * p]);
-            zeta[e] = c_make(-df.y, df.x);
+            const double2 df = c_sub(Z[(2 * q) * d + 2 * p + 1], Z[(2 * q + 1) * d + 2 * p]);
+            const double2 z = c_make(-df.y, df.x);
+            zeta[e] = z;
+            zetaT[q * n + p] = z;
         }
         __syncthreads();
         // one-body s tr(Z Kt) and s tr(Yt M)
         double2 one = c_make(0.0, 0.0), bs = c_make(0.0, 0.0);
         for (int e = t; e < d * d; e += SO_EN_THREADS) {
             const int a = e / d, b = e - a * d;
-            one = c_fma(Z[a * DM + b], Kt[b * d + a], one);
-            bs = c_add(bs, c_scale(Yt[a * DM + b], Mg[b * d + a]));
+            one = c_fma(Z[e], Kt[b * d + a], one);
+            bs = c_add(bs, c_scale(Yt[e], Mg[b * d + a]));
         }
         en_sum2(one, bs, red);
-        // sum_g (tr(Z K_g))^2 with tr(Z K_g) = sum_pq L^g_pq zeta_pq
-        double2 asq = c_make(0.0, 0.0), dummy = c_make(0.0, 0.0);
-        for (int g = t; g < ng; g += SO_EN_THREADS) {
-            double2 tg = c_make(0.0, 0.0);
-            for (int pq = 0; pq < n2; ++pq) tg = c_add(tg, c_scale(zeta[pq], L[(size_t)pq * ng + g]));
-            asq = c_fma(tg, tg, asq);
-        }
-        en_sum2(asq, dummy, red);
-        // c1 = sum V_pqrs tr(Z^(sp) sy Z^(qr) sy), c2 = sum V_pqrs tr(Yt^(sp) sy W^(qr) sy);
+        // c1 = sum V_pqrs tr(Z^(sp) sy Z^(qr) sy), c2 = sum V_pqrs tr(Yt^(sp) sy W^(qr) sy),
+        // asq = sum V_pqrs zeta_pq zeta_rs (= sum_g (tr(Z K_g))^2, tr(Z K_g) = sum_pq L^g_pq zeta_pq);
         // tr(P sy R sy) = P00 R11 - P01 R01 - P10 R10 + P11 R00 for 2 x 2 blocks
-        double2 c1 = c_make(0.0, 0.0), c2 = c_make(0.0, 0.0);
+        double2 c1 = c_make(0.0, 0.0), c2 = c_make(0.0, 0.0), asq = c_make(0.0, 0.0);
         if (t < n2) {
             const int q = t / n, r = t - q * n;
-            const double2 z00 = Z[(2 * q) * DM + 2 * r], z01 = Z[(2 * q) * DM + 2 * r + 1];
-            const double2 z10 = Z[(2 * q + 1) * DM + 2 * r], z11 = Z[(2 * q + 1) * DM + 2 * r + 1];
-            const double2 w00 = Wm[(2 * q) * DM + 2 * r], w01 = Wm[(2 * q) * DM + 2 * r + 1];
-            const double2 w10 = Wm[(2 * q + 1) * DM + 2 * r], w11 = Wm[(2 * q + 1) * DM + 2 * r + 1];
-            for (int sp = 0; sp < n2; ++sp) {
+            const double2 z00 = Z[(2 * q) * d + 2 * r], z01 = Z[(2 * q) * d + 2 * r + 1];
+            const double2 z10 = Z[(2 * q + 1) * d + 2 * r], z11 = Z[(2 * q + 1) * d + 2 * r + 1];
+            // this thread's block of W = Z C'
+            double2 w00 = c_make(0.0, 0.0), w01 = w00, w10 = w00, w11 = w00;
+            for (int c = 0; c < d; ++c) {
+                const double c0 = C[c * d + 2 * r], c1v = C[c * d + 2 * r + 1];
+                const double2 za = Z[(2 * q) * d + c], zb = Z[(2 * q + 1) * d + c];
+                w00 = c_add(w00, c_scale(za, c0));
+                w01 = c_add(w01, c_scale(za, c1v));
+                w10 = c_add(w10, c_scale(zb, c0));
+                w11 = c_add(w11, c_scale(zb, c1v));
+            }
+            const double *vcol = Vt + t;
+            const double2 *zq = zetaT + q * n;   // zeta_pq at zq[p]
+            const double2 *zr = zetaT + r;       // zeta_rs at zr[s n]
+            auto term = [&](int sp, double v) {
                 const int s = sp / n, p = sp - s * n;
-                const double v = Vt[(size_t)sp * n2 + t];
-                const double2 *zs = Z + (2 * s) * DM + 2 * p;
-                const double2 *ys = Yt + (2 * s) * DM + 2 * p;
+                asq = c_fma(c_scale(zq[p], v), zr[s * n], asq);
+                const double2 *zs = Z + (2 * s) * d + 2 * p;
+                const double2 *ys = Yt + (2 * s) * d + 2 * p;
                 double2 f1 = c_mul(zs[0], z11);
                 f1 = c_sub(f1, c_mul(zs[1], z01));
-                f1 = c_sub(f1, c_mul(zs[DM], z10));
-                f1 = c_fma(zs[DM + 1], z00, f1);
+                f1 = c_sub(f1, c_mul(zs[d], z10));
+                f1 = c_fma(zs[d + 1], z00, f1);
                 double2 f2 = c_mul(ys[0], w11);
                 f2 = c_sub(f2, c_mul(ys[1], w01));
-                f2 = c_sub(f2, c_mul(ys[DM], w10));
-                f2 = c_fma(ys[DM + 1], w00, f2);
+                f2 = c_sub(f2, c_mul(ys[d], w10));
+                f2 = c_fma(ys[d + 1], w00, f2);
                 c1 = c_add(c1, c_scale(f1, v));
                 c2 = c_add(c2, c_scale(f2, v));
+            };
+            int sp = 0;
+            for (; sp + 8 <= n2; sp += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = vcol[(size_t)(sp + u) * n2];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) term(sp + u, v[u]);
             }
+            for (; sp < n2; ++sp) term(sp, vcol[(size_t)sp * n2]);
         }
         en_sum2(c1, c2, red);
+        double2 dummy = c_make(0.0, 0.0);
+        en_sum2(asq, dummy, red);
         const double2 s2 = c_mul(sk, sk);
         const double2 csum = c_scale(c_mul(s2, c_sub(c1, c2)), 2.0);
         const double2 asum = c_scale(c_mul(s2, asq), 4.0);
@@ -398,6 +449,7 @@ __global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, i
         double2 E = c_mul(sk, one);
         E = c_add(E, c_scale(c_add(c_sub(c_mul(sk, bs), csum), c_scale(asum, 0.5)), 0.25));
         esum = c_fma(c_mul(wk, pf), E, esum);
+        __syncthreads();   // zeta lives in A, which the next node rebuilds
     }
     if (t == 0) {
         const int64_t ix = w0 * S + s0;
@@ -413,7 +465,7 @@ __global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, const double2 
                                                        const double2 *__restrict__ epair, double2 *__restrict__ overlap,
                                                        double2 *__restrict__ numer, double2 *__restrict__ energy,
                                                        int32_t *__restrict__ wst) {
-    __shared__ double2 red[512];
+    __shared__ double2 red[8];
     const int t = threadIdx.x;
     const int64_t w = blockIdx.x;
     double2 so = c_make(0.0, 0.0), se = c_make(0.0, 0.0);
