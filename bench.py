@@ -22,8 +22,10 @@ single-precision formation), ``precision_n24`` (FP64 and mixed on the n = 24
 workload with sampled pair errors against the oracle), ``grad`` (derivative
 and force bias, with its own oracle baseline), ``rdm1`` (density matrix from
 the shadows, HBM-bound), ``vce`` (full-space overlaps through the
-virtual-correlation-energy prologue) and ``uneven`` (four geometries in one
-batched call, graph-replayed, FP64 and mixed, beside separate calls).
+virtual-correlation-energy prologue), ``energy`` (local energies from the
+second Pfaffian derivatives, with its own oracle baseline) and ``uneven``
+(four geometries in one batched call, graph-replayed, FP64 and mixed,
+beside separate calls).
 """
 from __future__ import annotations
 
@@ -351,6 +353,76 @@ def vce_leg(args, B, wl, torch, np):
             "prologue_share": pro_s / per}
 
 
+def energy_flops_per_pair(n, eta, K):
+    """FP64 flops per walker x shadow pair of the local-energy kernel's own
+    formulation (complex multiply-add = 8, real x complex = 4): formation, and
+    per node the Pfaffian (m^3/3 complex MACs), the Gauss-Jordan inverse (m^3),
+    A^{-1} X, X^T A^{-1} X, C' Yt and the W blocks, the two traces, and the
+    n^4 contraction with V (two 2 x 2 block traces and the square term:
+    82 flops per (p, q, r, s))."""
+    m, d = 2 * n - eta, 2 * n
+    node = (8 * m ** 3 / 3 + 8 * m ** 3 + 8 * m * m * d + 8 * m * d * d + 4 * d ** 3 + 4 * d ** 3
+            + 82 * n ** 4 + 12 * d * d)
+    return 8 * m * d * d + 8 * m * m * d + K * node
+
+
+def energy_leg(args, B, wl, torch, np):
+    """Local energies (so_local_energy) on n = 16, eta = 8, 128 walkers x
+    1,000 shadows, 200 Cholesky-like vectors and a one-body matrix: per pair
+    17 Chebyshev nodes, each with a Pfaffian, an inverse and an n^4
+    contraction.  Value = walker x shadow local-energy terms per second."""
+    dev = torch.device("cuda:0")
+    w = wl.config("energy_n16")
+    ts = [torch.from_numpy(x).to(dev) for x in (w.phi, w.Q, w.bits.view(np.int64), w.t, w.L)]
+    S_, N_, E_, st = B.local_energy(*ts)
+    torch.cuda.synchronize()
+    B.profile_enable(True)
+    B.profile_read(B.PROF_ENERGY)
+    t0 = time.perf_counter()
+    for _ in range(args.energy_steps):
+        S_, N_, E_, st = B.local_energy(*ts)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / args.energy_steps
+    ms, launches, units = B.profile_read(B.PROF_ENERGY)
+    B.profile_enable(False)
+    if int(st.abs().sum()) != 0 or not bool(torch.isfinite(E_.real).all()):
+        raise RuntimeError("local-energy run reported a numerical status")
+    K = w.n + 1
+    fl = energy_flops_per_pair(w.n, w.eta, K)
+    kern_s = ms / 1e3 / launches
+    achieved = fl * (units / launches) / kern_s / 1e12
+    rec = {"metric": "walker×shadow local-energy terms/s", "value": w.W * w.S / per, "unit": "pairs/s",
+           "steps": args.energy_steps, "ms_per_step": per * 1e3, "dtype": "f64",
+           "config": {"workload": "energy_n16", "n": w.n, "eta": w.eta, "walkers": w.W, "shadows": w.S,
+                      "n_gamma": w.L.shape[1], "nodes": K, "node_family": "chebyshev"},
+           "mean_energy_real": float(E_.real.mean()),
+           "roofline": {"bound": "alu", "kernel": "k_energy_pair", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "flops_per_pair": fl,
+                        "avg_launch_ms": kern_s * 1e3, "pairs_per_launch": units / launches}}
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_energy_baseline(w, np)
+    return rec
+
+
+def cpu_energy_baseline(w, np, target_s=10.0):
+    """The oracle's local-energy route (per Cholesky vector, eq.
+    Pfaffian_2nd_der with m x m products) on the first pairs of the same
+    workload (walker-major), sized from a 16-pair pilot to about target_s
+    seconds on all host threads."""
+    import oracle
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    allp = np.stack([np.arange(w.W * w.S) // w.S, np.arange(w.W * w.S) % w.S], 1)
+    t = time.perf_counter()
+    oracle.energy_pairs(w.phi, w.Q, w.bits, w.t, w.L, pairs=allp[:16], nthreads=nthreads)
+    pilot = max(time.perf_counter() - t, 1e-3) / 16
+    npairs = int(max(16, min(len(allp), target_s / pilot)))
+    t = time.perf_counter()
+    oracle.energy_pairs(w.phi, w.Q, w.bits, w.t, w.L, pairs=allp[:npairs], nthreads=nthreads)
+    dt = time.perf_counter() - t
+    return {"value": npairs / dt, "unit": "pairs/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"the first {npairs} walker x shadow pairs of energy_n16 ({dt:.1f} s)"}
+
+
 def cpu_grad_baseline(wl, target_s=15.0):
     """The oracle's gradient on 16 walkers (one per host thread on the GPU
     host) x the first s shadows, s sized from a 64-shadow pilot to about
@@ -385,6 +457,8 @@ def main():
     ap.add_argument("--no-rdm", action="store_true", help="skip the density-matrix leg")
     ap.add_argument("--rdm-steps", type=int, default=5)
     ap.add_argument("--no-vce", action="store_true", help="skip the full-space (VCE) leg")
+    ap.add_argument("--no-energy", action="store_true", help="skip the local-energy leg")
+    ap.add_argument("--energy-steps", type=int, default=2)
     ap.add_argument("--vce-steps", type=int, default=3)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device to device, three times (scales the HBM counters)")
@@ -498,6 +572,8 @@ def main():
         rec["rdm1"] = rdm_leg(args, B, wl, torch, np, Q, bits)
     if not args.no_vce:
         rec["vce"] = vce_leg(args, B, wl, torch, np)
+    if not args.no_energy:
+        rec["energy"] = energy_leg(args, B, wl, torch, np)
     if not args.no_uneven:
         rec["uneven"] = uneven_leg(args, B, wl, torch, np)
     if not args.no_cpu_baseline:
