@@ -122,11 +122,21 @@ def grad_leg(args, B, wl, torch, np):
     if int(status.abs().sum()) != 0 or not bool(torch.isfinite(xbar.real).all()):
         raise RuntimeError("derivative run reported a numerical status")
     per = (t1 - t0) / args.grad_steps
+    # algorithmic flops per pair: the forward count plus the adjoint by node
+    # inverses, K 8 m^3, and the product of the adjoint with C' X^T, 16 n m^2
+    K, m = g.n + 1, 2 * g.n - g.eta
+    fl = (formation_flops_per_pair(g.n, g.eta) + pfaffian_flops_per_pair(g.n, g.eta, K) + K * 8.0 * m ** 3
+          + 16.0 * g.n * m * m)
+    kern_s = gms / 1e3 / glaunch
+    achieved = fl * (gpairs / glaunch) / kern_s / 1e12
     return {"metric": "grad evals/s", "value": g.W * g.S / per, "unit": "walker x shadow adjoint contributions/s",
             "walkers_per_s": g.W / per, "ms_per_step": per * 1e3, "steps": args.grad_steps,
             "config": {"workload": "grad_n16", "n": g.n, "eta": g.eta, "walkers": g.W, "shadows": g.S,
                        "n_gamma": g.L.shape[1]},
-            "kernels": {"k_grad_pair": {"ms_per_step": gms / args.grad_steps}}}
+            "kernels": {"k_grad_pair": {"ms_per_step": gms / args.grad_steps}},
+            "roofline": {"bound": "alu", "kernel": "k_grad_pair", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "flops_per_pair": fl,
+                         "avg_launch_ms": kern_s * 1e3, "pairs_per_launch": gpairs / glaunch}}
 
 
 def uneven_leg(args, B, wl, torch, np):
