@@ -283,10 +283,13 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
  *   H = sum_pq t_pq a_p^dag a_q + 1/2 sum_g Lhat_g^2,  Lhat_g = sum_pq L^g_pq a_p^dag a_q
  * (the paper's H = v_0 - 1/2 sum_g v_g^2 with v_g = i Lhat_g), from the
  * first and second derivatives of the node Pfaffians as the walker moves
- * along e^{lambda Lhat}.  The node matrices must be invertible, so this
- * entry point uses the paper's Chebyshev nodes whatever p->nodes says (the
- * roots of unity contain z = -1, where every pair's Pfaffian vanishes when
- * n - eta is odd); K = p->n_nodes or n + 1.
+ * along e^{lambda Lhat}.  The node matrices must be invertible, and
+ * z = -1 is a root of every pair's Pfaffian when n - eta is odd; this entry
+ * point therefore uses its own nodes, whatever p->nodes and p->n_nodes say:
+ * Pf(C_0 + z B) = z^{eta/2} R(z) with deg R = n - eta for every walker along
+ * e^{lambda Lhat}, so n - eta + 1 nodes z_k = exp(2 pi i (k + 1/3) /
+ * (n - eta + 1)), which avoid +-1 and +-i, determine the estimator and its
+ * derivatives.
  *   phi, Q, bits  as in shadow_overlap (device)
  *   t        [n][n] complex128 (device), any one-body matrix
  *   L        [n*n][n_gamma] float64 (device), L[p n + q][g] = L^g_pq, each L^g

@@ -294,7 +294,7 @@ def rdm1(Q: torch.Tensor, bits: torch.Tensor, *, trial: bool = True, with_majora
 
 
 def local_energy(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, t: torch.Tensor, L: torch.Tensor, *,
-                 n_nodes: int = 0, paper_norm: bool = False, workspace: torch.Tensor | None = None):
+                 paper_norm: bool = False, workspace: torch.Tensor | None = None):
     """Local energies E_L = N_w / S_w (so_local_energy) for H = sum t_pq a_p^dag a_q
     + 1/2 sum_g Lhat_g^2, with t [n, n] complex128 and L [n*n, n_gamma] float64
     (each L^g real symmetric).  Returns (overlap [W], numerator [W],
@@ -306,7 +306,7 @@ def local_energy(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, t: torc
         raise ValueError("t must be [n, n] and L [n*n, n_gamma]")
     phi, Q, bits, t, L = phi.contiguous(), Q.contiguous(), bits.contiguous(), t.contiguous(), L.contiguous()
     ng = L.shape[1]
-    p = make_params(n, eta, n_nodes, "chebyshev", "fp64", paper_norm)
+    p = make_params(n, eta, 0, "unit", "fp64", paper_norm)   # the library picks the energy's own nodes
     nbytes = ctypes.c_size_t(0)
     st = lib.so_local_energy_workspace_size(ctypes.byref(p), W, S, ng, ctypes.byref(nbytes))
     if st != SO_OK:

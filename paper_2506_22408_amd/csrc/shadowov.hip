@@ -233,18 +233,24 @@ void compute_weights(const so_params *p, int K, double2 *z, double2 *w) {
 // v_j = (pref psign/(ne+1)) sum_x mu_{m/2-x} e_j^{-x}.  Q(e_j) is
 // pfo Pf(S + e_j J).  psign is the sign of the permutation from the paper's
 // selected order to the stored one.
-void build_nodetab(const so_params *p, int K, NodeTab *t) {
-    double2 z[SO_KMAX], w[SO_KMAX];
-    compute_weights(p, K, z, w);
-    const int n = p->n, eta = p->eta, m = mvalue(n, eta), ne = n - eta;
-    // paper order: occupied 0..eta-1, then (eta+2u, eta+2u+1) for empty u
+// Sign of the permutation from the paper's row order (occupied 0..eta-1,
+// then eta+2u, eta+2u+1 for empty u) to the kernels' order (so_prep.h).
+double row_order_sign(int n, int eta) {
+    const int m = mvalue(n, eta), ne = n - eta;
     int perm[2 * SO_NMAX];
     for (int i = 0; i < eta; ++i) perm[i] = i;
     for (int u = 0; u < ne; ++u) { perm[eta + 2 * u] = eta + u; perm[eta + 2 * u + 1] = eta + 2 * ne - 1 - u; }
     int inv = 0;
     for (int i = 0; i < m; ++i)
         for (int j = i + 1; j < m; ++j) inv += perm[i] > perm[j];
-    const double psign = (inv & 1) ? -1.0 : 1.0;
+    return (inv & 1) ? -1.0 : 1.0;
+}
+
+void build_nodetab(const so_params *p, int K, NodeTab *t) {
+    double2 z[SO_KMAX], w[SO_KMAX];
+    compute_weights(p, K, z, w);
+    const int n = p->n, eta = p->eta, m = mvalue(n, eta), ne = n - eta;
+    const double psign = row_order_sign(n, eta);
     std::memset(t, 0, sizeof(*t));
     t->K = K;
     const long double two_pi = 6.283185307179586476925286766559005768L;
@@ -837,6 +843,38 @@ EnLayout energy_layout(int n, int64_t W, int64_t S) {
     return L;
 }
 
+// Nodes of the local energy.  Pf(C_0 + z B) = z^{eta/2} R(z) with deg R = n - eta
+// (its coefficients vanish below x = eta/2), for the walker and for every
+// walker along e^{lambda Lhat}, which keeps eta particles; so K' = n - eta + 1
+// nodes determine R, its lambda-derivatives and the estimator.  They sit on
+// the unit circle a third of a step off the roots of unity,
+// z_k = exp(2 pi i (k + 1/3) / K'), which never meets +-1 or +-i (z = -1 is a
+// root of every pair's Pfaffian when n - eta is odd), and
+//   w_k = pref psign / K' sum_{x = eta/2}^{ell} mu_x z_k^{-x}.
+void energy_nodetab(const so_params *p, EnTab *t) {
+    const int n = p->n, eta = p->eta, ell = n - eta / 2, Kp = n - eta + 1;
+    long double mu[SO_KMAX];
+    cld pref;
+    estimator_terms(p, SO_KMAX, mu, &pref);
+    const double psign = row_order_sign(n, eta);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    std::memset(t, 0, sizeof(*t));
+    t->K = Kp;
+    for (int k = 0; k < Kp; ++k) {
+        const long double th = two_pi * ((long double)k + 1.0L / 3.0L) / Kp;
+        long double sr = 0.0L, si = 0.0L;
+        for (int x = eta / 2; x <= ell; ++x) {
+            sr += mu[x] * cosl(-x * th);
+            si += mu[x] * sinl(-x * th);
+        }
+        sr /= Kp;
+        si /= Kp;
+        t->s[k] = make_double2((double)cosl(th), (double)sinl(th));
+        t->c[k] = make_double2(1.0, 0.0);
+        t->w[k] = make_double2((double)(pref.re * sr - pref.im * si) * psign, (double)(pref.re * si + pref.im * sr) * psign);
+    }
+}
+
 bool energy_args_ok(const so_params *p, int64_t W, int64_t S, int n_gamma, int *K) {
     if (!params_ok(p, K) || W < 1 || S < 1 || n_gamma < 0) return false;
     if (W > 65535 || S > (int64_t)INT32_MAX) return false;
@@ -1100,15 +1138,9 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     double2 *op = reinterpret_cast<double2 *>(ws + Lo.off_o);
     double2 *ep = reinterpret_cast<double2 *>(ws + Lo.off_e);
     int32_t *wst = status ? status : reinterpret_cast<int32_t *>(ws + Lo.off_stat);
-    // the paper's Chebyshev nodes, whatever p->nodes asks for (see so_energy.h)
-    so_params pc = *p;
-    pc.nodes = SO_NODES_CHEBYSHEV;
-    NodeTab nt;
-    build_nodetab(&pc, K, &nt);
+    // n - eta + 1 nodes off the roots of unity, whatever p->nodes asks for
     EnTab tab;
-    std::memset(&tab, 0, sizeof(tab));
-    tab.K = K;
-    for (int k = 0; k < K; ++k) { tab.s[k] = nt.s[k]; tab.c[k] = nt.c[k]; tab.w[k] = nt.wf[k]; }
+    energy_nodetab(p, &tab);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
                        reinterpret_cast<const double2 *>(phi), Xa, wst, nullptr);

@@ -21,9 +21,9 @@
 // K2 = sum_g L^g L^g.  The node's energy is
 //   E = s tr(Z K_t) + 1/4 [s tr(Yt M) - sum_g tr(A^{-1}A'_g A^{-1}A'_g) + 1/2 sum_g tr(A^{-1}A'_g)^2],
 // K_t the Majorana matrix of t, and the pair's numerator e = sum_k w_k Pf_k E_k
-// beside o = sum_k w_k Pf_k.  The node matrices must be invertible: the
-// nodes are the paper's Chebyshev nodes (the roots of unity contain z = -1,
-// a root of every pair's polynomial when n - eta is odd).
+// beside o = sum_k w_k Pf_k.  The node matrices must be invertible, so the
+// nodes avoid z = -1, a root of every pair's Pfaffian when n - eta is odd;
+// the host places n - eta + 1 of them a third of a step off the roots of unity.
 #pragma once
 #include "so_common.h"
 

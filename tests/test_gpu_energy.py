@@ -3,12 +3,12 @@ eq. Pfaffian_2nd_der route ("Force bias and local energy").
 
 The kernel evaluates the same second derivatives through the d x d matrices
 X^T A^{-1} X, C' X^T A^{-1} X and C' X^T A^{-1} X C' and an n^4 contraction
-with V = sum_g L^g (x) L^g.  The oracle instead forms the m x m matrices A',
-A'' per Cholesky vector.  Both use the paper's Chebyshev nodes, whose
-weights grow with n (sum |w_k| ~ 3e5 at n = 16), so FP64 rounding of the
-node values reaches the sums as ~1e-11 of their scale on either side.  The
-tests hold S_w and N_w within 1e-9 of the mean magnitude of the pair terms
-and E_L within 1e-8 relative.
+with V = sum_g L^g (x) L^g, at n - eta + 1 nodes on the unit circle.  The
+oracle instead forms the m x m matrices A', A'' per Cholesky vector at the
+paper's n + 1 Chebyshev nodes, whose weights grow with n (sum |w_k| ~ 3e5 at
+n = 16), so FP64 rounding of the node values reaches the oracle's sums as
+~1e-11 of their scale.  The tests hold S_w and N_w within 1e-9 of the mean
+magnitude of the pair terms and E_L within 1e-8 relative.
 """
 import ctypes
 
@@ -71,8 +71,8 @@ def test_energy_matches_oracle(B, n, eta, W, S, ng):
 
 
 def test_energy_overlap_agrees_with_main_path(B):
-    """The energy call's S_w (Chebyshev nodes, full-size Pfaffians) and
-    shadow_overlap's (reduced pencil, roots of unity) are the same estimator:
+    """The energy call's S_w (n - eta + 1 full-size Pfaffians off the roots of
+    unity) and shadow_overlap's (reduced pencil, roots of unity) are the same estimator:
     equal within 1e-10 of the scale mean_s |o_ws| of the averaged terms."""
     w = wl.make("eo", 12, 6, 3, 20, seed=31, n_gamma=6, with_t=True)
     Sg, _, _, st = run(B, w, w.t, w.L)
