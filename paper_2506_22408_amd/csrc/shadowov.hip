@@ -824,7 +824,7 @@ hipError_t launch_vce_prep(const VceDims &v, const so_c64 *pa, const so_c64 *pb,
 // Workspace of so_local_energy: walker matrices and shadow covariances in A
 // order, the Hamiltonian tables, the per-shadow M, per-pair values, status.
 struct EnLayout {
-    size_t off_X, off_C, off_V, off_K2, off_Kt, off_M, off_o, off_e, off_stat, total;
+    size_t off_X, off_C, off_V, off_K2, off_Kt, off_M, off_o, off_e, off_stat, off_Xr, off_Cr, total;
 };
 EnLayout energy_layout(int n, int64_t W, int64_t S) {
     const int T = so_tiles(n), DP = 16 * T, d = 2 * n;
@@ -839,6 +839,8 @@ EnLayout energy_layout(int n, int64_t W, int64_t S) {
     L.off_o = o; o = align_up(o + (size_t)W * S * sizeof(double2));
     L.off_e = o; o = align_up(o + (size_t)W * S * sizeof(double2));
     L.off_stat = o; o = align_up(o + (size_t)W * sizeof(int32_t));
+    L.off_Xr = o; o = align_up(o + (size_t)W * (2 * n - 2) * d * sizeof(double2));   // m <= 2n - 2
+    L.off_Cr = o; o = align_up(o + (size_t)S * d * d * sizeof(double));
     L.total = o;
     return L;
 }
@@ -1138,6 +1140,8 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     double2 *op = reinterpret_cast<double2 *>(ws + Lo.off_o);
     double2 *ep = reinterpret_cast<double2 *>(ws + Lo.off_e);
     int32_t *wst = status ? status : reinterpret_cast<int32_t *>(ws + Lo.off_stat);
+    double2 *Xr = reinterpret_cast<double2 *>(ws + Lo.off_Xr);
+    double *Cr = reinterpret_cast<double *>(ws + Lo.off_Cr);
     // n - eta + 1 nodes off the roots of unity, whatever p->nodes asks for
     EnTab tab;
     energy_nodetab(p, &tab);
@@ -1153,8 +1157,13 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     hipLaunchKernelGGL(k_energy_small, dim3(1), dim3(256), 0, st, n, n_gamma, L,
                        reinterpret_cast<const double2 *>(t), K2, Kt);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
-    if (T == 1) hipLaunchKernelGGL(k_energy_shadow<1>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms);
-    else hipLaunchKernelGGL(k_energy_shadow<2>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms);
+    if (T == 1) {
+        hipLaunchKernelGGL(k_energy_shadow<1>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms, Cr);
+        hipLaunchKernelGGL(k_energy_walker<1>, dim3((unsigned)W), dim3(256), 0, st, n, eta, Xa, Xr);
+    } else {
+        hipLaunchKernelGGL(k_energy_shadow<2>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms, Cr);
+        hipLaunchKernelGGL(k_energy_walker<2>, dim3((unsigned)W), dim3(256), 0, st, n, eta, Xa, Xr);
+    }
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     hipEvent_t ea = nullptr;
     if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
@@ -1163,12 +1172,12 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     if (T == 1) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_energy_pair<1>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_energy_pair<1>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xa, Ca, Ms, Vt, Kt, tab, S,
+        hipLaunchKernelGGL(k_energy_pair<1>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xr, Cr, Ms, Vt, Kt, tab, S,
                            op, ep, wst);
     } else {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_energy_pair<2>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_energy_pair<2>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xa, Ca, Ms, Vt, Kt, tab, S,
+        hipLaunchKernelGGL(k_energy_pair<2>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xr, Cr, Ms, Vt, Kt, tab, S,
                            op, ep, wst);
     }
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;

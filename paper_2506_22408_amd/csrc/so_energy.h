@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_energy_small(int n, int ng, const doubl
 template <int T>
 __global__ __launch_bounds__(256) void k_energy_shadow(int n, const double *__restrict__ Ca,
                                                        const double *__restrict__ Vt, const double *__restrict__ K2,
-                                                       double *__restrict__ Ms) {
+                                                       double *__restrict__ Ms, double *__restrict__ Cr) {
     constexpr int DP = 16 * T;
     __shared__ double C[DP * DP];
     const int d = 2 * n, n2 = n * n;
@@ -95,7 +95,9 @@ __global__ __launch_bounds__(256) void k_energy_shadow(int n, const double *__re
     const double *Cg = Ca + s0 * DP * DP;
     for (int e = threadIdx.x; e < d * d; e += 256) {
         const int mu = e / d, nu = e - mu * d;
-        C[mu * DP + nu] = Cg[ao_index(mu, nu, T)];
+        const double c = Cg[ao_index(mu, nu, T)];
+        C[mu * DP + nu] = c;
+        Cr[s0 * d * d + e] = c;
     }
     __syncthreads();
     double *out = Ms + s0 * d * d;
@@ -120,6 +122,21 @@ __device__ __forceinline__ double en_wsum(double x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
     return x;
+}
+
+// Row-major complex copy of the walker matrix X (m x d) from Xall in A order.
+template <int T>
+__global__ __launch_bounds__(256) void k_energy_walker(int n, int eta, const double *__restrict__ Xa,
+                                                       double2 *__restrict__ Xr) {
+    constexpr int DP = 16 * T;
+    const int d = 2 * n, m = 2 * n - eta;
+    const int64_t w0 = blockIdx.x;
+    const double *Xg = Xa + w0 * DP * DP;
+    for (int e = threadIdx.x; e < m * d; e += 256) {
+        const int i = e / d, mu = e - i * d;
+        Xr[w0 * m * d + e] = i < eta ? c_make(Xg[ao_index(i, mu, T)], Xg[ao_index(eta + i, mu, T)])
+                                     : c_make(Xg[ao_index(eta + i, mu, T)], 0.0);
+    }
 }
 
 // block-wide sum of two complex values (all threads get the result): a
@@ -156,14 +173,14 @@ __device__ __forceinline__ int en_argmax(double v, int idx, double *rv, int *ri,
     return ri[0];
 }
 
-// LDS of k_energy_pair, in complex entries (C' counts half): X [m][d],
-// C' [d][d] real, B [m][m], A [max(m^2, 2 n^2)] (the node matrix and its
-// inverse, then zeta and its transpose), YZ [d][d] (A^{-1} X, then Z),
-// Yt [d][d].  At n = 16, eta = 8 this is 72 KB: two blocks per CU.
+// LDS of k_energy_pair, in complex entries: B [m][m], A [max(m^2, 2 n^2)]
+// (the node matrix and its inverse, then zeta and its transpose), YZ [d][d]
+// (A^{-1} X, then Z), Yt [d][d].  X and C' are read through the caches from
+// row-major copies.  At n = 16, eta = 8 this is 52 KB: three blocks per CU.
 __host__ __device__ inline size_t energy_lds_bytes(int n, int eta) {
     const size_t d = 2 * n, m = 2 * n - eta, n2 = (size_t)n * n;
     const size_t asz = m * m > 2 * n2 ? m * m : 2 * n2;
-    return 16 * (m * d + m * m + asz + 2 * d * d) + 8 * d * d;
+    return 16 * (m * m + asz + 2 * d * d);
 }
 
 // One block of 256 threads per (walker, shadow) pair; grid (S, W).
@@ -172,8 +189,8 @@ __host__ __device__ inline size_t energy_lds_bytes(int n, int eta) {
 //   opair/epair [W][S] complex out: o_ws and the numerator e_ws
 // Matrices are row-major with their own row length (d or m).
 template <int T>
-__global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, const double *__restrict__ Xa,
-                                                               const double *__restrict__ Ca,
+__global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta, const double2 *__restrict__ Xr,
+                                                               const double *__restrict__ Cr,
                                                                const double *__restrict__ Ms,
                                                                const double *__restrict__ Vt,
                                                                const double2 *__restrict__ Kt, EnTab tab, int64_t S,
@@ -191,28 +208,15 @@ __global__ __launch_bounds__(SO_EN_THREADS) void k_energy_pair(int n, int eta, c
     const int t = threadIdx.x;
     const int d = 2 * n, m = 2 * n - eta, ne = n - eta, n2 = n * n;
     const int asz = m * m > 2 * n2 ? m * m : 2 * n2;
-    double2 *X = esm;                 // m x d
-    double2 *Bm = X + m * d;          // m x m
+    double2 *Bm = esm;                // m x m
     double2 *A = Bm + m * m;          // m x m; later zeta (n2) and zetaT (n2)
     double2 *YZ = A + asz;            // d x d
     double2 *Yt = YZ + d * d;         // d x d
-    double *C = reinterpret_cast<double *>(Yt + d * d);   // d x d
     double2 *zeta = A, *zetaT = A + n2;
     const int64_t s0 = blockIdx.x, w0 = blockIdx.y;
-    const double *Xg = Xa + w0 * DM * DM;
-    const double *Cg = Ca + s0 * DM * DM;
+    const double2 *X = Xr + w0 * m * d;    // m x d, row-major (global, cached)
+    const double *C = Cr + s0 * d * d;     // d x d, row-major (global, cached)
     const double *Mg = Ms + s0 * d * d;
-    // X (m x d complex) from Xall = [Re X_O; Im X_O; X_U], C' (d x d)
-    for (int e = t; e < m * d; e += SO_EN_THREADS) {
-        const int i = e / d, mu = e - i * d;
-        X[e] = i < eta ? c_make(Xg[ao_index(i, mu, T)], Xg[ao_index(eta + i, mu, T)])
-                       : c_make(Xg[ao_index(eta + i, mu, T)], 0.0);
-    }
-    for (int e = t; e < d * d; e += SO_EN_THREADS) {
-        const int mu = e / d, nu = e - mu * d;
-        C[e] = Cg[ao_index(mu, nu, T)];
-    }
-    __syncthreads();
     // B = X (C' X^T): YZ[j][mu] = sum_nu C'[mu][nu] X[j][nu], B[i][j] = sum_mu X[i][mu] YZ[j][mu]
     for (int e = t; e < m * d; e += SO_EN_THREADS) {
         const int j = e / d, mu = e - j * d;

@@ -70,6 +70,18 @@ def test_energy_matches_oracle(B, n, eta, W, S, ng):
     check(Sg, Ng, Eg, o, e)
 
 
+@pytest.mark.parametrize("n,eta,W,S,ng", [(6, 2, 2, 5, 4), (10, 6, 2, 4, 6), (16, 8, 1, 3, 12)])
+def test_energy_non_orthonormal_walkers(B, n, eta, W, S, ng):
+    """Walkers between re-orthonormalisations are general full-rank matrices;
+    the estimator is multilinear in their columns, and so are both routes."""
+    print(f"energy non-orthonormal n={n} eta={eta}", flush=True)
+    w = wl.make("en", n, eta, W, S, seed=700 + n, n_gamma=ng, orthonormal=False, with_t=True)
+    Sg, Ng, Eg, st = run(B, w, w.t, w.L)
+    assert not st.any()
+    o, e = oracle.energy_pairs(w.phi, w.Q, w.bits, w.t, w.L)
+    check(Sg, Ng, Eg, o, e)
+
+
 def test_energy_overlap_agrees_with_main_path(B):
     """The energy call's S_w (n - eta + 1 full-size Pfaffians off the roots of
     unity) and shadow_overlap's (reduced pencil, roots of unity) are the same estimator:
