@@ -402,9 +402,51 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
         double2 c1 = c_make(0.0, 0.0), c2 = c_make(0.0, 0.0), asq = c_make(0.0, 0.0);
         if (t < n2) {
             const int q = t / n, r = t - q * n;
+            // c1 = sum_sp V tr(Z^(sp) sy Z^(qr) sy) is linear in Z^(sp): with
+            // a_ab = sum_sp V_pqrs Z^(sp)_ab,  c1 = z11 a00 - z01 a01 - z10 a10 + z00 a11;
+            // likewise c2 from b_ab = sum_sp V_pqrs Yt^(sp)_ab and this thread's W block,
+            // and asq = sum_s zeta_rs sum_p V_pqrs zeta_pq
+            const double *vcol = Vt + t;
+            const double2 *zq = zetaT + q * n;   // zeta_pq at zq[p]
+            const double2 *zr = zetaT + r;       // zeta_rs at zr[s n]
+            double2 a00 = c_make(0.0, 0.0), a01 = a00, a10 = a00, a11 = a00;
+            double2 b00 = a00, b01 = a00, b10 = a00, b11 = a00;
+            for (int s = 0; s < n; ++s) {
+                const double2 *zrow = Z + (2 * s) * d;
+                const double2 *yrow = Yt + (2 * s) * d;
+                const double *vs = vcol + (size_t)(s * n) * n2;
+                double2 as = c_make(0.0, 0.0);
+                auto term = [&](int p, double v) {
+                    const double2 *zs = zrow + 2 * p;
+                    const double2 *ys = yrow + 2 * p;
+                    a00 = c_add(a00, c_scale(zs[0], v));
+                    a01 = c_add(a01, c_scale(zs[1], v));
+                    a10 = c_add(a10, c_scale(zs[d], v));
+                    a11 = c_add(a11, c_scale(zs[d + 1], v));
+                    b00 = c_add(b00, c_scale(ys[0], v));
+                    b01 = c_add(b01, c_scale(ys[1], v));
+                    b10 = c_add(b10, c_scale(ys[d], v));
+                    b11 = c_add(b11, c_scale(ys[d + 1], v));
+                    as = c_add(as, c_scale(zq[p], v));
+                };
+                int p = 0;
+                for (; p + 4 <= n; p += 4) {
+                    double v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = vs[(size_t)(p + u) * n2];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) term(p + u, v[u]);
+                }
+                for (; p < n; ++p) term(p, vs[(size_t)p * n2]);
+                asq = c_fma(as, zr[s * n], asq);
+            }
+            // this thread's blocks Z^(qr) and W^(qr) (W = Z C')
             const double2 z00 = Z[(2 * q) * d + 2 * r], z01 = Z[(2 * q) * d + 2 * r + 1];
             const double2 z10 = Z[(2 * q + 1) * d + 2 * r], z11 = Z[(2 * q + 1) * d + 2 * r + 1];
-            // this thread's block of W = Z C'
+            c1 = c_mul(z11, a00);
+            c1 = c_sub(c1, c_mul(z01, a01));
+            c1 = c_sub(c1, c_mul(z10, a10));
+            c1 = c_fma(z00, a11, c1);
             double2 w00 = c_make(0.0, 0.0), w01 = w00, w10 = w00, w11 = w00;
             for (int c = 0; c < d; ++c) {
                 const double c0 = C[c * d + 2 * r], c1v = C[c * d + 2 * r + 1];
@@ -414,34 +456,10 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
                 w10 = c_add(w10, c_scale(zb, c0));
                 w11 = c_add(w11, c_scale(zb, c1v));
             }
-            const double *vcol = Vt + t;
-            const double2 *zq = zetaT + q * n;   // zeta_pq at zq[p]
-            const double2 *zr = zetaT + r;       // zeta_rs at zr[s n]
-            auto term = [&](int sp, double v) {
-                const int s = sp / n, p = sp - s * n;
-                asq = c_fma(c_scale(zq[p], v), zr[s * n], asq);
-                const double2 *zs = Z + (2 * s) * d + 2 * p;
-                const double2 *ys = Yt + (2 * s) * d + 2 * p;
-                double2 f1 = c_mul(zs[0], z11);
-                f1 = c_sub(f1, c_mul(zs[1], z01));
-                f1 = c_sub(f1, c_mul(zs[d], z10));
-                f1 = c_fma(zs[d + 1], z00, f1);
-                double2 f2 = c_mul(ys[0], w11);
-                f2 = c_sub(f2, c_mul(ys[1], w01));
-                f2 = c_sub(f2, c_mul(ys[d], w10));
-                f2 = c_fma(ys[d + 1], w00, f2);
-                c1 = c_add(c1, c_scale(f1, v));
-                c2 = c_add(c2, c_scale(f2, v));
-            };
-            int sp = 0;
-            for (; sp + 8 <= n2; sp += 8) {
-                double v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = vcol[(size_t)(sp + u) * n2];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) term(sp + u, v[u]);
-            }
-            for (; sp < n2; ++sp) term(sp, vcol[(size_t)sp * n2]);
+            c2 = c_mul(w11, b00);
+            c2 = c_sub(c2, c_mul(w01, b01));
+            c2 = c_sub(c2, c_mul(w10, b10));
+            c2 = c_fma(w00, b11, c2);
         }
         en_sum2(c1, c2, red);
         double2 dummy = c_make(0.0, 0.0);
