@@ -75,6 +75,10 @@ enum { SO_NODES_UNIT = 0, SO_NODES_CHEBYSHEV = 1 };
 enum { SO_PREC_FP64 = 0, SO_PREC_MIXED = 1 };
 
 #define SO_FLAG_PAPER_NORM 1u /* omit the factor 2 (paper's o_p as printed) */
+#define SO_FLAG_LOG_OUTPUT 2u /* overlap[w] receives log S_w = log|S_w| + i Arg S_w
+                                 (principal branch) instead of S_w; S_w == 0 sets
+                                 SO_WSTAT_ZERO.  shadow_overlap, shadow_overlap_grad,
+                                 shadow_overlap_batched, so_vce_overlap */
 
 typedef struct {
     int n;          /* modes = qubits = spin orbitals; see so_max_n() */

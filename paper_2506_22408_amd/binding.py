@@ -21,6 +21,7 @@ SO_OK, SO_ERR_ARG, SO_ERR_UNSUPPORTED, SO_ERR_HIP, SO_ERR_WORKSPACE = 0, -1, -2,
 SO_NODES = {"unit": 0, "chebyshev": 1}
 SO_PREC = {"fp64": 0, "mixed": 1}
 SO_FLAG_PAPER_NORM = 1
+SO_FLAG_LOG_OUTPUT = 2
 SO_WSTAT_RANK, SO_WSTAT_NONFINITE, SO_WSTAT_ZERO, SO_WSTAT_FALLBACK_LOST, SO_WSTAT_SINGULAR = 1, 2, 4, 8, 16
 
 
@@ -120,9 +121,9 @@ def status_string(code: int) -> str:
 
 
 def make_params(n: int, eta: int, n_nodes: int = 0, nodes: str = "unit", precision: str = "fp64",
-                paper_norm: bool = False) -> SoParams:
-    return SoParams(int(n), int(eta), int(n_nodes), SO_NODES[nodes], SO_PREC[precision],
-                    SO_FLAG_PAPER_NORM if paper_norm else 0)
+                paper_norm: bool = False, log_output: bool = False) -> SoParams:
+    flags = (SO_FLAG_PAPER_NORM if paper_norm else 0) | (SO_FLAG_LOG_OUTPUT if log_output else 0)
+    return SoParams(int(n), int(eta), int(n_nodes), SO_NODES[nodes], SO_PREC[precision], flags)
 
 
 def workspace_size(p: SoParams, W: int, S: int, with_grad: bool = False) -> int:
@@ -200,13 +201,13 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def shadow_overlap(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_nodes: int = 0,
                    nodes: str = "unit", precision: str = "fp64", paper_norm: bool = False,
-                   return_pairs: bool = False, workspace: torch.Tensor | None = None):
-    """S_w = (1/S) sum_s o_ws for every walker (complex128 [W]); with
-    ``return_pairs`` also the [W,S] pair estimates.  Returns (overlap, pairs
-    or None, status int32 [W])."""
+                   log_output: bool = False, return_pairs: bool = False, workspace: torch.Tensor | None = None):
+    """S_w = (1/S) sum_s o_ws for every walker (complex128 [W]; log S_w with
+    ``log_output``); with ``return_pairs`` also the [W,S] pair estimates.
+    Returns (overlap, pairs or None, status int32 [W])."""
     W, n, eta, S = _check_inputs(phi, Q, bits)
     phi, Q, bits = phi.contiguous(), Q.contiguous(), bits.contiguous()
-    p = make_params(n, eta, n_nodes, nodes, precision, paper_norm)
+    p = make_params(n, eta, n_nodes, nodes, precision, paper_norm, log_output)
     nbytes = workspace_size(p, W, S)
     ws = workspace if workspace is not None else _workspace(nbytes, phi.device)
     out = torch.empty(W, dtype=torch.complex128, device=phi.device)
@@ -223,12 +224,13 @@ def shadow_overlap(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_
 
 def shadow_overlap_grad(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_nodes: int = 0,
                         nodes: str = "unit", precision: str = "fp64", paper_norm: bool = False,
-                        with_green: bool = True, workspace: torch.Tensor | None = None):
+                        log_output: bool = False, with_green: bool = True,
+                        workspace: torch.Tensor | None = None):
     """S_w, D_w = d log S_w / d Phi_w (holomorphic) and G_w = D_w Phi_w^T.
     Returns (overlap [W], dlog [W,n,eta], green [W,n,n] or None, status [W])."""
     W, n, eta, S = _check_inputs(phi, Q, bits)
     phi, Q, bits = phi.contiguous(), Q.contiguous(), bits.contiguous()
-    p = make_params(n, eta, n_nodes, nodes, precision, paper_norm)
+    p = make_params(n, eta, n_nodes, nodes, precision, paper_norm, log_output)
     nbytes = workspace_size(p, W, S, with_grad=True)
     ws = workspace if workspace is not None else _workspace(nbytes, phi.device)
     out = torch.empty(W, dtype=torch.complex128, device=phi.device)
@@ -350,15 +352,16 @@ def vce_walkers(phi_alpha: torch.Tensor, phi_beta: torch.Tensor, n_core: int, n_
 
 def vce_overlap(phi_alpha: torch.Tensor, phi_beta: torch.Tensor, n_core: int, n_active: int, Q: torch.Tensor,
                 bits: torch.Tensor, *, n_nodes: int = 0, nodes: str = "unit", precision: str = "fp64",
-                paper_norm: bool = False, workspace: torch.Tensor | None = None):
-    """Full-space overlaps <Psi_T|phi_w> = c_w S_w(phi~_a) (so_vce_overlap).
-    Returns (overlap [W], prefactor [W], status int32 [W])."""
+                paper_norm: bool = False, log_output: bool = False, workspace: torch.Tensor | None = None):
+    """Full-space overlaps <Psi_T|phi_w> = c_w S_w(phi~_a) (so_vce_overlap; their
+    principal logarithm with ``log_output``).  Returns (overlap [W],
+    prefactor [W], status int32 [W])."""
     W, d, pa, pb = _vce_inputs(phi_alpha, phi_beta, n_core, n_active)
     if not (Q.is_cuda and bits.is_cuda) or Q.dtype != torch.float64 or bits.dtype not in (torch.int64, torch.uint64):
         raise TypeError("Q must be float64 and bits 64-bit integers, on the device")
     S = Q.shape[0]
     Q, bits = Q.contiguous(), bits.contiguous()
-    p = make_params(2 * d.n_active, d.n_alpha + d.n_beta, n_nodes, nodes, precision, paper_norm)
+    p = make_params(2 * d.n_active, d.n_alpha + d.n_beta, n_nodes, nodes, precision, paper_norm, log_output)
     nbytes = ctypes.c_size_t(0)
     st = lib.so_vce_workspace_size(ctypes.byref(p), ctypes.byref(d), W, S, ctypes.byref(nbytes))
     if st != SO_OK:
@@ -384,11 +387,11 @@ class ShadowLogOverlap(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, phi, Q, bits, n_nodes=0, nodes="unit"):
-        out, dlog, _, status = shadow_overlap_grad(phi.detach(), Q, bits, n_nodes=n_nodes, nodes=nodes,
-                                                   with_green=False)
+        logS, dlog, _, status = shadow_overlap_grad(phi.detach(), Q, bits, n_nodes=n_nodes, nodes=nodes,
+                                                    log_output=True, with_green=False)
         ctx.save_for_backward(dlog)
         ctx.mark_non_differentiable(status)
-        return torch.log(out), status
+        return logS, status
 
     @staticmethod
     def backward(ctx, grad_out, grad_status):
@@ -429,7 +432,8 @@ class Batch:
             self.pairs.append(pairs)
             a = arr[k]
             a.params = make_params(n, eta, pr.get("n_nodes", 0), pr.get("nodes", "unit"),
-                                   pr.get("precision", "fp64"), pr.get("paper_norm", False))
+                                   pr.get("precision", "fp64"), pr.get("paper_norm", False),
+                                   pr.get("log_output", False))
             a.phi, a.n_walkers, a.Q, a.bits, a.n_shadows = phi.data_ptr(), W, Q.data_ptr(), bits.data_ptr(), S
             a.overlap, a.status = out.data_ptr(), st.data_ptr()
             a.pair_out = pairs.data_ptr() if pairs is not None else None

@@ -52,7 +52,8 @@
 // get NaN.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_reduce(const double2 *__restrict__ pairs, int64_t S,
-                                               double2 *__restrict__ out, int32_t *__restrict__ wstat) {
+                                               double2 *__restrict__ out, int32_t *__restrict__ wstat,
+                                               int logout) {
     const int w = blockIdx.x;
     const int lane = threadIdx.x;
     const double2 *pw = pairs + (size_t)w * S;
@@ -70,6 +71,10 @@ __global__ __launch_bounds__(64) void k_reduce(const double2 *__restrict__ pairs
         int32_t st = wstat[w];
         if (st & SO_WSTAT_RANK) r = c_make(NAN, NAN);
         if (!isfinite(r.x) || !isfinite(r.y)) st |= SO_WSTAT_NONFINITE;
+        if (logout) {
+            if (r.x == 0.0 && r.y == 0.0) st |= SO_WSTAT_ZERO;
+            r = c_log(r);
+        }
         out[w] = r;
         wstat[w] = st;
     }
@@ -120,7 +125,7 @@ bool params_ok(const so_params *p, int *K_out) {
     if (p->eta < 2 || p->eta > p->n || (p->eta & 1)) return false;
     if (p->nodes != SO_NODES_UNIT && p->nodes != SO_NODES_CHEBYSHEV) return false;
     if (p->precision != SO_PREC_FP64 && p->precision != SO_PREC_MIXED) return false;
-    if (p->flags & ~SO_FLAG_PAPER_NORM) return false;
+    if (p->flags & ~(SO_FLAG_PAPER_NORM | SO_FLAG_LOG_OUTPUT)) return false;
     const int ell = p->n - p->eta / 2;
     const int K = p->n_nodes ? p->n_nodes : p->n + 1;
     if (K < ell + 1 || K > SO_KMAX) return false;
@@ -551,6 +556,7 @@ struct ProbPlan {
     const double2 *Xa, *Ca;   // FP64 operands (full-size path; formation unless mixed)
     double *Xw, *Cw;
     bool mix;                 // mixed precision: single-precision formation operands
+    bool logout;              // SO_FLAG_LOG_OUTPUT
     float *X32, *C32;
     const void *Xf, *Cf;      // the formation's operands
     int32_t *wst;
@@ -574,6 +580,7 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
     P->W = W;
     P->S = S;
     P->mix = p->precision == SO_PREC_MIXED;
+    P->logout = (p->flags & SO_FLAG_LOG_OUTPUT) != 0;
     P->L = make_layout(p->n, p->eta, W, S, false, P->mix);
     if (!ws || bytes < P->L.total) return SO_ERR_WORKSPACE;
     build_nodetab(p, K, &P->tab);
@@ -647,7 +654,8 @@ hipError_t enqueue_finish(const ProbPlan &P, hipStream_t st) {
                        P.L.fb_cap, P.S, P.fbB, P.pairs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3((unsigned)P.W), dim3(64), 0, st, P.pairs, P.S, P.overlap, P.wst);
+    hipLaunchKernelGGL(k_reduce, dim3((unsigned)P.W), dim3(64), 0, st, P.pairs, P.S, P.overlap, P.wst,
+                       P.logout ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1005,7 +1013,7 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
     hipLaunchKernelGGL(k_grad_walker, dim3((unsigned)W), dim3(64), 0, st, n, eta,
                        reinterpret_cast<const double2 *>(phi), Xa, Fp, Op, L.Gy, S,
                        reinterpret_cast<double2 *>(overlap), reinterpret_cast<double2 *>(dlog),
-                       reinterpret_cast<double2 *>(green), wst);
+                       reinterpret_cast<double2 *>(green), wst, (p->flags & SO_FLAG_LOG_OUTPUT) ? 1 : 0);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     return SO_OK;
 }
@@ -1104,7 +1112,7 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
                                         overlap, nullptr, status, workspace, base, stream);
     if (so != SO_OK) return so;
     hipLaunchKernelGGL(k_vce_scale, dim3((unsigned)((n_walkers + 255) / 256)), dim3(256), 0, st, n_walkers, pref,
-                       reinterpret_cast<double2 *>(overlap));
+                       reinterpret_cast<double2 *>(overlap), (p->flags & SO_FLAG_LOG_OUTPUT) ? 1 : 0);
     return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
 }
 
@@ -1125,6 +1133,7 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     if (!phi || !Q || !bits || !t || (n_gamma > 0 && !L) || !energy_args_ok(p, n_walkers, n_shadows, n_gamma, &K))
         return SO_ERR_ARG;
     if (!overlap && !numerator && !energy) return SO_ERR_ARG;
+    if (p->flags & SO_FLAG_LOG_OUTPUT) return SO_ERR_UNSUPPORTED;
     if (!so_supported(p->n, p->eta) || p->n > SO_EN_NMAX || p->precision != SO_PREC_FP64) return SO_ERR_UNSUPPORTED;
     const int n = p->n, eta = p->eta, d = 2 * n, T = so_tiles(n);
     const int64_t W = n_walkers, S = n_shadows;

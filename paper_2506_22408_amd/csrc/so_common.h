@@ -25,6 +25,8 @@ __device__ __forceinline__ double2 c_fma(double2 a, double2 b, double2 c) {
 }
 __device__ __forceinline__ double c_abs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
 __device__ __forceinline__ double2 c_sel(bool p, double2 a, double2 b) { return c_make(p ? a.x : b.x, p ? a.y : b.y); }
+// principal complex logarithm, log|a| + i Arg a with Arg in (-pi, pi]
+__device__ __forceinline__ double2 c_log(double2 a) { return c_make(log(hypot(a.x, a.y)), atan2(a.y, a.x)); }
 // 1/a for a != 0 (scaled to avoid overflow of |a|^2)
 __device__ __forceinline__ double2 c_inv(double2 a) {
     const double s = fmax(fabs(a.x), fabs(a.y));

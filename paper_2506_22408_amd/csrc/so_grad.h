@@ -524,7 +524,7 @@ __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double
                                                     const double *__restrict__ Xa, const double2 *__restrict__ Fpart,
                                                     const double2 *__restrict__ Opart, int Gy, int64_t S_total,
                                                     double2 *__restrict__ overlap, double2 *__restrict__ dlog,
-                                                    double2 *__restrict__ green, int32_t *__restrict__ wstat) {
+                                                    double2 *__restrict__ green, int32_t *__restrict__ wstat, int logout) {
     __shared__ double2 Fs[2 * SO_GRAD_NMAX * SO_GRAD_MMAX];
     __shared__ double2 Ph[SO_GRAD_NMAX * SO_GRAD_NMAX];        // Phi (n x eta)
     __shared__ double2 Gm[SO_GRAD_NMAX * 2 * SO_GRAD_NMAX];    // [Phi^H Phi | I] (eta x 2 eta)
@@ -611,7 +611,7 @@ __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double
         if (zero) st |= SO_WSTAT_ZERO;
         if (!ok) st |= SO_WSTAT_RANK;
         if (!isfinite(r.x) || !isfinite(r.y)) st |= SO_WSTAT_NONFINITE;
-        overlap[w] = r;
+        overlap[w] = logout ? c_log(r) : r;
         wstat[w] = st;
     }
 }

@@ -169,9 +169,19 @@ __global__ __launch_bounds__(64) void k_vce_prep(VceDims v, const double2 *__res
     if (t == 0) pref[w] = ptot;
 }
 
-// overlap[w] *= pref[w]
+// overlap[w] *= pref[w]; in log form overlap[w] += log pref[w], the phase
+// brought back to (-pi, pi]
 __global__ __launch_bounds__(256) void k_vce_scale(int64_t W, const double2 *__restrict__ pref,
-                                                   double2 *__restrict__ overlap) {
+                                                   double2 *__restrict__ overlap, int logout) {
     const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (w < W) overlap[w] = c_mul(pref[w], overlap[w]);
+    if (w >= W) return;
+    if (!logout) {
+        overlap[w] = c_mul(pref[w], overlap[w]);
+        return;
+    }
+    const double two_pi = 6.283185307179586;
+    double2 v = c_add(c_log(pref[w]), overlap[w]);
+    v.y -= two_pi * rint(v.y / two_pi);
+    if (v.y <= -0.5 * two_pi) v.y += two_pi;
+    overlap[w] = v;
 }

@@ -1,0 +1,90 @@
+"""SO_FLAG_LOG_OUTPUT: the library writes log S_w = log|S_w| + i Arg S_w
+(principal branch) in its final kernels, for shadow_overlap,
+shadow_overlap_grad, the batched entry point and so_vce_overlap.  Checked
+against the complex logarithm of the plain outputs of the same calls
+(identical S_w bits go into both), to 1e-14 absolute in log|S| and Arg."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2506_22408_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2506_22408_amd import binding
+    return binding
+
+
+def td(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda:0"))
+
+
+def close_log(lg, plain):
+    ref = np.log(plain)
+    d = lg - ref
+    d = d.real + 1j * ((d.imag + np.pi) % (2 * np.pi) - np.pi)   # the branch cut may split +-pi
+    assert np.all(np.abs(d) <= 1e-14 * np.maximum(1.0, np.abs(ref)))
+    assert np.all(lg.imag > -np.pi) and np.all(lg.imag <= np.pi)
+
+
+@pytest.mark.parametrize("n,eta", [(8, 4), (16, 8), (11, 4)])
+def test_overlap_log_output(B, n, eta):
+    w = wl.make("lg", n, eta, 6, 40, seed=60 + n)
+    args = (td(w.phi), td(w.Q), td(w.bits.view(np.int64)))
+    a, _, sa = B.shadow_overlap(*args)
+    b, _, sb = B.shadow_overlap(*args, log_output=True)
+    torch.cuda.synchronize()
+    assert not sa.any() and not sb.any()
+    close_log(b.cpu().numpy(), a.cpu().numpy())
+
+
+def test_grad_log_output(B):
+    w = wl.make("lgg", 8, 4, 4, 30, seed=61)
+    args = (td(w.phi), td(w.Q), td(w.bits.view(np.int64)))
+    a, da, _, _ = B.shadow_overlap_grad(*args)
+    b, db, _, _ = B.shadow_overlap_grad(*args, log_output=True)
+    torch.cuda.synchronize()
+    close_log(b.cpu().numpy(), a.cpu().numpy())
+    assert torch.equal(da, db)
+    # the autograd wrapper returns the library's log
+    lg, _ = B.log_overlap(*args)
+    assert torch.equal(lg, b)
+
+
+def test_batched_log_output(B):
+    ws = [wl.make(f"lb{k}", n, n // 2, 3, 20, seed=62 + k) for k, n in enumerate((8, 12))]
+    probs = [dict(phi=td(w.phi), Q=td(w.Q), bits=td(w.bits.view(np.int64)), log_output=True) for w in ws]
+    bt = B.Batch(probs)
+    bt.run()
+    for k, w in enumerate(ws):
+        a, _, _ = B.shadow_overlap(td(w.phi), td(w.Q), td(w.bits.view(np.int64)), log_output=True)
+        torch.cuda.synchronize()
+        assert torch.equal(bt.overlap[k], a)
+
+
+def test_vce_log_output(B):
+    v = wl.make_vce("lv", 20, 4, 4, 2, 2, 5, 30, seed=63)
+    args = (td(v.phi_alpha), td(v.phi_beta), v.n_core, v.n_active, td(v.Q), td(v.bits.view(np.int64)))
+    a, _, _ = B.vce_overlap(*args)
+    b, _, _ = B.vce_overlap(*args, log_output=True)
+    torch.cuda.synchronize()
+    close_log(b.cpu().numpy(), a.cpu().numpy())
+
+
+def test_log_output_zero_overlap_sets_status(B):
+    """A walker whose core block has a zero row has full overlap exactly 0;
+    in log form that is -inf with SO_WSTAT_ZERO."""
+    rng = np.random.default_rng(64)
+    pa, pb = wl.walkers(rng, 2, 12, 5), wl.walkers(rng, 2, 12, 5)
+    pa[1, 0, :] = 0.0
+    Q = wl.haar_so(rng, 7, 16)
+    bits = wl.even_bits(rng, 7, 8)
+    o, _, st = B.vce_overlap(td(pa), td(pb), 3, 4, td(Q), td(bits.view(np.int64)), log_output=True)
+    torch.cuda.synchronize()
+    o, st = o.cpu().numpy(), st.cpu().numpy()
+    assert np.isfinite(o[0]) and st[0] == 0
+    # the active-space S_w is finite and the prefactor zero: log form gives -inf real part
+    assert np.isneginf(o[1].real)
