@@ -368,11 +368,12 @@ def energy_flops_per_pair(n, eta, K):
     formulation (complex multiply-add = 8, real x complex = 4): formation, and
     per node the Pfaffian (m^3/3 complex MACs), the Gauss-Jordan inverse (m^3),
     A^{-1} X, X^T A^{-1} X, C' Yt and the W blocks, the two traces, and the
-    n^4 contraction with V (two 2 x 2 block traces and the square term:
-    82 flops per (p, q, r, s))."""
+    n^4 contraction with V (the block sums sum_sp V Z^(sp) and sum_sp V Yt^(sp),
+    eight real x complex products, and the square term's one: 36 flops per
+    (p, q, r, s))."""
     m, d = 2 * n - eta, 2 * n
     node = (8 * m ** 3 / 3 + 8 * m ** 3 + 8 * m * m * d + 8 * m * d * d + 4 * d ** 3 + 4 * d ** 3
-            + 82 * n ** 4 + 12 * d * d)
+            + 36 * n ** 4 + 12 * d * d)
     return 8 * m * d * d + 8 * m * m * d + K * node
 
 
