@@ -54,6 +54,8 @@ def check(Sg, Ng, Eg, o, e):
 CASES = [  # n, eta, W, S, n_gamma
     (4, 2, 3, 5, 4), (5, 2, 2, 6, 3), (6, 4, 3, 7, 5), (8, 4, 4, 9, 10), (8, 2, 2, 5, 6), (7, 4, 2, 4, 0),
     (10, 4, 2, 5, 8), (12, 6, 2, 4, 12), (16, 8, 2, 3, 20), (16, 4, 1, 2, 10), (15, 8, 1, 3, 7), (13, 2, 1, 2, 5),
+    (4, 4, 2, 3, 3), (6, 6, 1, 3, 4),      # no empty mode: n - eta + 1 = 1 node
+    (5, 2, 1, 1, 2),                       # one walker, one shadow
 ]
 
 
