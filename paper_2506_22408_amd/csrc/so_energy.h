@@ -203,7 +203,6 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
     __shared__ double2 red[8];
     __shared__ double rv[1];
     __shared__ int ri[1];
-    __shared__ double2 fcol[DM];
     __shared__ int piv[DM];
     const int t = threadIdx.x;
     const int d = 2 * n, m = 2 * n - eta, ne = n - eta, n2 = n * n;
@@ -249,19 +248,34 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
     };
     for (int k = 0; k < tab.K; ++k) {
         const double2 sk = tab.s[k], ck = tab.c[k], wk = tab.w[k];
-        // ---- Pf(A) by Parlett-Reid with pivoting (A destroyed) ----
+        // ---- Pf(A) and YZ = A^{-1} X by one pairwise (Parlett-Reid) elimination
+        // with partial pivoting that carries X as right-hand sides (A destroyed).
+        // Step k eliminates the 2 x 2 pivot [[0, a], [-a, 0]] (a = A[k][k+1]):
+        //   A_ij += (A[k+1][i] A[k][j] - A[k][i] A[k+1][j]) / a,   i, j >= k+2,
+        //   X_i  += (A[k+1][i] X_k  - A[k][i] X_{k+1}) / a,        i >= k+2,
+        // and Pf(A) is the signed product of the pivots.  Rows k, k+1 keep their
+        // values as pivot rows, which the back substitution then uses. ----
         build_a(sk, ck);
+        for (int e = t; e < m * d; e += SO_EN_THREADS) YZ[e] = X[e];
+        __syncthreads();
         double2 pf = c_make(1.0, 0.0);
+        bool sing = false;
         for (int kk = 0; kk < m - 1; kk += 2) {
             const int j = kk + 1 + t;
             double best;
             const int p = en_argmax(j < m ? c_abs2(A[kk * m + j]) : -1.0, j < m ? j : m, rv, ri, best);
-            if (best == 0.0) { pf = c_make(0.0, 0.0); break; }
+            if (best == 0.0) { pf = c_make(0.0, 0.0); sing = true; break; }
+            if (t == 0) piv[kk] = p;
             if (p != kk + 1) {
                 for (int c = t; c < m; c += SO_EN_THREADS) {
                     const double2 x = A[(kk + 1) * m + c];
                     A[(kk + 1) * m + c] = A[p * m + c];
                     A[p * m + c] = x;
+                }
+                for (int c = t; c < d; c += SO_EN_THREADS) {
+                    const double2 x = YZ[(kk + 1) * d + c];
+                    YZ[(kk + 1) * d + c] = YZ[p * d + c];
+                    YZ[p * d + c] = x;
                 }
                 __syncthreads();
                 for (int r = t; r < m; r += SO_EN_THREADS) {
@@ -278,76 +292,53 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
             const int rem = m - kk - 2;
             for (int e = t; e < rem * rem; e += SO_EN_THREADS) {
                 const int i = kk + 2 + e / rem, jj = kk + 2 + e % rem;
-                // A_ij += (A[k+1][i] A[k][j] - A[k][i] A[k+1][j]) / a
                 const double2 num = c_sub(c_mul(A[(kk + 1) * m + i], A[kk * m + jj]),
                                           c_mul(A[kk * m + i], A[(kk + 1) * m + jj]));
                 A[i * m + jj] = c_fma(num, ia, A[i * m + jj]);
             }
+            for (int e = t; e < rem * d; e += SO_EN_THREADS) {
+                const int i = kk + 2 + e / d, mu = e % d;
+                const double2 num = c_sub(c_mul(A[(kk + 1) * m + i], YZ[kk * d + mu]),
+                                          c_mul(A[kk * m + i], YZ[(kk + 1) * d + mu]));
+                YZ[i * d + mu] = c_fma(num, ia, YZ[i * d + mu]);
+            }
             __syncthreads();
         }
         osum = c_fma(wk, pf, osum);
-        // ---- A^{-1} by Gauss-Jordan with partial pivoting (in place) ----
-        build_a(sk, ck);
-        bool sing = false;
-        for (int c = 0; c < m; ++c) {
-            const int r = c + t;
-            double best;
-            const int p = en_argmax(r < m ? c_abs2(A[r * m + c]) : -1.0, r < m ? r : m, rv, ri, best);
-            if (best == 0.0) { sing = true; break; }
-            if (t == 0) piv[c] = p;
-            if (p != c) {
-                for (int j = t; j < m; j += SO_EN_THREADS) {
-                    const double2 x = A[c * m + j];
-                    A[c * m + j] = A[p * m + j];
-                    A[p * m + j] = x;
-                }
-                __syncthreads();
-            }
-            const double2 ip = c_inv(A[c * m + c]);
-            for (int i = t; i < m; i += SO_EN_THREADS) fcol[i] = A[i * m + c];
-            __syncthreads();
-            for (int j = t; j < m; j += SO_EN_THREADS) A[c * m + j] = j == c ? ip : c_mul(A[c * m + j], ip);
-            __syncthreads();
-            for (int e = t; e < m * m; e += SO_EN_THREADS) {
-                const int i = e / m, j = e - i * m;
-                if (i == c) continue;
-                A[e] = j == c ? c_neg(c_mul(fcol[i], ip)) : c_sub(A[e], c_mul(fcol[i], A[c * m + j]));
-            }
-            __syncthreads();
-        }
         if (sing) {
             singular = true;
             continue;
         }
-        for (int c = m - 1; c >= 0; --c) {
-            const int p = piv[c];
-            if (p != c) {
-                for (int i = t; i < m; i += SO_EN_THREADS) {
-                    const double2 x = A[i * m + c];
-                    A[i * m + c] = A[i * m + p];
-                    A[i * m + p] = x;
+        // back substitution, last pivot pair first: with r = X~ - sum_{j >= k+2} A[.][j] Y_j
+        // over rows k, k+1, the 2 x 2 pivot gives Y_k = -r_{k+1} / a, Y_{k+1} = r_k / a
+        for (int kk = m - 2; kk >= 0; kk -= 2) {
+            const double2 ia = c_inv(A[kk * m + kk + 1]);
+            for (int mu = t; mu < d; mu += SO_EN_THREADS) {
+                double2 r0 = YZ[kk * d + mu], r1 = YZ[(kk + 1) * d + mu];
+                for (int jj = kk + 2; jj < m; ++jj) {
+                    const double2 yj = YZ[jj * d + mu];
+                    r0 = c_sub(r0, c_mul(A[kk * m + jj], yj));
+                    r1 = c_sub(r1, c_mul(A[(kk + 1) * m + jj], yj));
+                }
+                YZ[kk * d + mu] = c_neg(c_mul(r1, ia));
+                YZ[(kk + 1) * d + mu] = c_mul(r0, ia);
+            }
+            __syncthreads();
+        }
+        // undo the symmetric interchanges on the solution, last first
+        for (int kk = m - 2; kk >= 0; kk -= 2) {
+            const int p = piv[kk];
+            if (p != kk + 1) {
+                for (int mu = t; mu < d; mu += SO_EN_THREADS) {
+                    const double2 x = YZ[(kk + 1) * d + mu];
+                    YZ[(kk + 1) * d + mu] = YZ[p * d + mu];
+                    YZ[p * d + mu] = x;
                 }
                 __syncthreads();
             }
         }
-        // ---- YZ = A^{-1} X (m x d), Yt = X^T YZ, then YZ = Z = C' Yt ----
-        // (a compile-time bound on the elements per thread, so that one
-        // thread's independent accumulations interleave)
-        {
-            double2 acc[NE];
-#pragma unroll
-            for (int u = 0; u < NE; ++u) acc[u] = c_make(0.0, 0.0);
-            for (int l = 0; l < m; ++l)
-#pragma unroll
-                for (int u = 0; u < NE; ++u) {
-                    const int e = t + u * SO_EN_THREADS, i = e / d, mu = e - i * d;
-                    if (e < m * d) acc[u] = c_fma(A[i * m + l], X[l * d + mu], acc[u]);
-                }
-#pragma unroll
-            for (int u = 0; u < NE; ++u)
-                if (t + u * SO_EN_THREADS < m * d) YZ[t + u * SO_EN_THREADS] = acc[u];
-        }
-        __syncthreads();
+        // ---- Yt = X^T YZ, then YZ = Z = C' Yt (a compile-time bound on the
+        // elements per thread, so that one thread's accumulations interleave) ----
         {
             double2 acc[NE];
 #pragma unroll
@@ -400,66 +391,97 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
         // asq = sum V_pqrs zeta_pq zeta_rs (= sum_g (tr(Z K_g))^2, tr(Z K_g) = sum_pq L^g_pq zeta_pq);
         // tr(P sy R sy) = P00 R11 - P01 R01 - P10 R10 + P11 R00 for 2 x 2 blocks
         double2 c1 = c_make(0.0, 0.0), c2 = c_make(0.0, 0.0), asq = c_make(0.0, 0.0);
-        if (t < n2) {
-            const int q = t / n, r = t - q * n;
-            // c1 = sum_sp V tr(Z^(sp) sy Z^(qr) sy) is linear in Z^(sp): with
-            // a_ab = sum_sp V_pqrs Z^(sp)_ab,  c1 = z11 a00 - z01 a01 - z10 a10 + z00 a11;
-            // likewise c2 from b_ab = sum_sp V_pqrs Yt^(sp)_ab and this thread's W block,
-            // and asq = sum_s zeta_rs sum_p V_pqrs zeta_pq
-            const double *vcol = Vt + t;
-            const double2 *zq = zetaT + q * n;   // zeta_pq at zq[p]
-            const double2 *zr = zetaT + r;       // zeta_rs at zr[s n]
-            double2 a00 = c_make(0.0, 0.0), a01 = a00, a10 = a00, a11 = a00;
-            double2 b00 = a00, b01 = a00, b10 = a00, b11 = a00;
-            for (int s = 0; s < n; ++s) {
-                const double2 *zrow = Z + (2 * s) * d;
-                const double2 *yrow = Yt + (2 * s) * d;
-                const double *vs = vcol + (size_t)(s * n) * n2;
-                double2 as = c_make(0.0, 0.0);
-                auto term = [&](int p, double v) {
-                    const double2 *zs = zrow + 2 * p;
-                    const double2 *ys = yrow + 2 * p;
-                    a00 = c_add(a00, c_scale(zs[0], v));
-                    a01 = c_add(a01, c_scale(zs[1], v));
-                    a10 = c_add(a10, c_scale(zs[d], v));
-                    a11 = c_add(a11, c_scale(zs[d + 1], v));
-                    b00 = c_add(b00, c_scale(ys[0], v));
-                    b01 = c_add(b01, c_scale(ys[1], v));
-                    b10 = c_add(b10, c_scale(ys[d], v));
-                    b11 = c_add(b11, c_scale(ys[d + 1], v));
-                    as = c_add(as, c_scale(zq[p], v));
-                };
-                int p = 0;
-                for (; p + 4 <= n; p += 4) {
-                    double v[4];
+        // c1 = sum_sp V tr(Z^(sp) sy Z^(qr) sy) is linear in Z^(sp): with
+        // a_ab = sum_sp V_pqrs Z^(sp)_ab,  c1 = sum_qr z11 a00 - z01 a01 - z10 a10 + z00 a11;
+        // likewise c2 from b_ab = sum_sp V_pqrs Yt^(sp)_ab and the W^(qr) blocks, and
+        // asq = sum_qr sum_s zeta_rs sum_p V_pqrs zeta_pq.  The first half of the
+        // threads accumulates a (and asq), the second half b, each thread for the
+        // two columns (q, r) = t' and t' + half: one LDS read of a 2 x 2 block then
+        // feeds both columns.
+        {
+            constexpr int half = SO_EN_THREADS / 2;
+            const bool bset = t >= half;
+            const int ca = bset ? t - half : t, cb = ca + half;
+            const bool hb = cb < n2;
+            auto contract = [&](auto with_as) {
+                constexpr bool AS = decltype(with_as)::value;
+                const int qa = ca / n, ra = ca - qa * n;
+                const int qb = hb ? cb / n : qa, rb = hb ? cb - qb * n : ra;
+                const double *va = Vt + ca, *vb = Vt + (hb ? cb : ca);
+                const double2 *src = AS ? Z : Yt;
+                double2 x00 = c_make(0.0, 0.0), x01 = x00, x10 = x00, x11 = x00;
+                double2 y00 = x00, y01 = x00, y10 = x00, y11 = x00;
+                double2 asa = x00, asb = x00;
+                for (int s = 0; s < n; ++s) {
+                    const double2 *row = src + (2 * s) * d;
+                    const size_t so = (size_t)(s * n) * n2;
+                    double2 pa = c_make(0.0, 0.0), pb = pa;
+                    auto term = [&](int p, double v, double w) {
+                        const double2 *blk = row + 2 * p;
+                        const double2 e00 = blk[0], e01 = blk[1], e10 = blk[d], e11 = blk[d + 1];
+                        x00 = c_add(x00, c_scale(e00, v));
+                        x01 = c_add(x01, c_scale(e01, v));
+                        x10 = c_add(x10, c_scale(e10, v));
+                        x11 = c_add(x11, c_scale(e11, v));
+                        y00 = c_add(y00, c_scale(e00, w));
+                        y01 = c_add(y01, c_scale(e01, w));
+                        y10 = c_add(y10, c_scale(e10, w));
+                        y11 = c_add(y11, c_scale(e11, w));
+                        if constexpr (AS) {
+                            pa = c_add(pa, c_scale(zetaT[qa * n + p], v));
+                            pb = c_add(pb, c_scale(zetaT[qb * n + p], w));
+                        }
+                    };
+                    int p = 0;
+                    for (; p + 4 <= n; p += 4) {
+                        double v[4], w[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) v[u] = vs[(size_t)(p + u) * n2];
+                        for (int u = 0; u < 4; ++u) {
+                            v[u] = va[so + (size_t)(p + u) * n2];
+                            w[u] = vb[so + (size_t)(p + u) * n2];
+                        }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) term(p + u, v[u]);
+                        for (int u = 0; u < 4; ++u) term(p + u, v[u], w[u]);
+                    }
+                    for (; p < n; ++p) term(p, va[so + (size_t)p * n2], vb[so + (size_t)p * n2]);
+                    if constexpr (AS) {
+                        asq = c_fma(pa, zetaT[s * n + ra], asq);
+                        if (hb) asq = c_fma(pb, zetaT[s * n + rb], asq);
+                    }
                 }
-                for (; p < n; ++p) term(p, vs[(size_t)p * n2]);
-                asq = c_fma(as, zr[s * n], asq);
+                // combine with the column's own block: Z^(qr) for c1, W^(qr) = (Z C')^(qr) for c2
+                auto fin = [&](int q, int r, double2 f00, double2 f01, double2 f10, double2 f11) {
+                    double2 g00, g01, g10, g11;
+                    if constexpr (AS) {
+                        g00 = Z[(2 * q) * d + 2 * r];
+                        g01 = Z[(2 * q) * d + 2 * r + 1];
+                        g10 = Z[(2 * q + 1) * d + 2 * r];
+                        g11 = Z[(2 * q + 1) * d + 2 * r + 1];
+                    } else {
+                        g00 = c_make(0.0, 0.0), g01 = g00, g10 = g00, g11 = g00;
+                        for (int c = 0; c < d; ++c) {
+                            const double k0 = C[c * d + 2 * r], k1 = C[c * d + 2 * r + 1];
+                            const double2 za = Z[(2 * q) * d + c], zb = Z[(2 * q + 1) * d + c];
+                            g00 = c_add(g00, c_scale(za, k0));
+                            g01 = c_add(g01, c_scale(za, k1));
+                            g10 = c_add(g10, c_scale(zb, k0));
+                            g11 = c_add(g11, c_scale(zb, k1));
+                        }
+                    }
+                    double2 v = c_mul(g11, f00);
+                    v = c_sub(v, c_mul(g01, f01));
+                    v = c_sub(v, c_mul(g10, f10));
+                    return c_fma(g00, f11, v);
+                };
+                double2 acc = fin(qa, ra, x00, x01, x10, x11);
+                if (hb) acc = c_add(acc, fin(qb, rb, y00, y01, y10, y11));
+                if constexpr (AS) c1 = acc;
+                else c2 = acc;
+            };
+            if (ca < n2) {
+                if (bset) contract(std::integral_constant<bool, false>{});
+                else contract(std::integral_constant<bool, true>{});
             }
-            // this thread's blocks Z^(qr) and W^(qr) (W = Z C')
-            const double2 z00 = Z[(2 * q) * d + 2 * r], z01 = Z[(2 * q) * d + 2 * r + 1];
-            const double2 z10 = Z[(2 * q + 1) * d + 2 * r], z11 = Z[(2 * q + 1) * d + 2 * r + 1];
-            c1 = c_mul(z11, a00);
-            c1 = c_sub(c1, c_mul(z01, a01));
-            c1 = c_sub(c1, c_mul(z10, a10));
-            c1 = c_fma(z00, a11, c1);
-            double2 w00 = c_make(0.0, 0.0), w01 = w00, w10 = w00, w11 = w00;
-            for (int c = 0; c < d; ++c) {
-                const double c0 = C[c * d + 2 * r], c1v = C[c * d + 2 * r + 1];
-                const double2 za = Z[(2 * q) * d + c], zb = Z[(2 * q + 1) * d + c];
-                w00 = c_add(w00, c_scale(za, c0));
-                w01 = c_add(w01, c_scale(za, c1v));
-                w10 = c_add(w10, c_scale(zb, c0));
-                w11 = c_add(w11, c_scale(zb, c1v));
-            }
-            c2 = c_mul(w11, b00);
-            c2 = c_sub(c2, c_mul(w01, b01));
-            c2 = c_sub(c2, c_mul(w10, b10));
-            c2 = c_fma(w00, b11, c2);
         }
         en_sum2(c1, c2, red);
         double2 dummy = c_make(0.0, 0.0);
