@@ -366,13 +366,14 @@ def vce_leg(args, B, wl, torch, np):
 def energy_flops_per_pair(n, eta, K):
     """FP64 flops per walker x shadow pair of the local-energy kernel's own
     formulation (complex multiply-add = 8, real x complex = 4): formation, and
-    per node the Pfaffian (m^3/3 complex MACs), the Gauss-Jordan inverse (m^3),
-    A^{-1} X, X^T A^{-1} X, C' Yt and the W blocks, the two traces, and the
+    per node the Pfaffian elimination (m^3/3 complex MACs) with X carried as
+    right-hand sides and the back substitution (m^2 d together), X^T A^{-1} X,
+    C' Yt and the W blocks, the two traces, and the
     n^4 contraction with V (the block sums sum_sp V Z^(sp) and sum_sp V Yt^(sp),
     eight real x complex products, and the square term's one: 36 flops per
     (p, q, r, s))."""
     m, d = 2 * n - eta, 2 * n
-    node = (8 * m ** 3 / 3 + 8 * m ** 3 + 8 * m * m * d + 8 * m * d * d + 4 * d ** 3 + 4 * d ** 3
+    node = (8 * m ** 3 / 3 + 8 * m * m * d + 8 * m * d * d + 4 * d ** 3 + 4 * d ** 3
             + 36 * n ** 4 + 12 * d * d)
     return 8 * m * d * d + 8 * m * m * d + K * node
 
@@ -380,7 +381,7 @@ def energy_flops_per_pair(n, eta, K):
 def energy_leg(args, B, wl, torch, np):
     """Local energies (so_local_energy) on n = 16, eta = 8, 128 walkers x
     1,000 shadows, 200 Cholesky-like vectors and a one-body matrix: per pair
-    n - eta + 1 = 9 nodes, each with a Pfaffian, an inverse and an n^4
+    n - eta + 1 = 9 nodes, each with a Pfaffian, a solve and an n^4
     contraction.  Value = walker x shadow local-energy terms per second."""
     dev = torch.device("cuda:0")
     w = wl.config("energy_n16")
