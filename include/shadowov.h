@@ -302,9 +302,10 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
  *   numerator [n_walkers] complex128 out or NULL: the shadow estimate of
  *            <Psi_T|H|phi_w>, N_w = (1/S) sum_s e_ws
  *   energy   [n_walkers] complex128 out or NULL: N_w / S_w
- *   status   [n_walkers] int32 out or NULL: SO_WSTAT_RANK / _NONFINITE, and
- *            SO_WSTAT_SINGULAR if a node matrix of some pair was exactly
- *            singular (that node's energy term is then left out)
+ *   status   [n_walkers] int32 out or NULL: SO_WSTAT_RANK (S_w, N_w, E_w
+ *            are then NaN) / _NONFINITE, and SO_WSTAT_SINGULAR if a node
+ *            matrix of some pair was exactly singular (that node's energy
+ *            term is then left out)
  * Supported: n <= 16, FP64 (SO_ERR_UNSUPPORTED otherwise); n_walkers <=
  * 65535.  One 256-thread workgroup per pair; deterministic (fixed
  * reduction order); no allocation; enqueued on `stream`. */

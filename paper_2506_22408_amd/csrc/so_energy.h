@@ -504,7 +504,8 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
 }
 
 // Per walker, in a fixed order: S_w = (1/S) sum_s o_ws, N_w = (1/S) sum_s e_ws,
-// E_w = N_w / S_w.  One block of 256 threads per walker.
+// E_w = N_w / S_w; NaN for a walker flagged rank-deficient, as in the overlap
+// path.  One block of 256 threads per walker.
 __global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, const double2 *__restrict__ opair,
                                                        const double2 *__restrict__ epair, double2 *__restrict__ overlap,
                                                        double2 *__restrict__ numer, double2 *__restrict__ energy,
@@ -522,6 +523,7 @@ __global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, const double2 
         const double inv = 1.0 / (double)S;
         so = c_scale(so, inv);
         se = c_scale(se, inv);
+        if (wst && (wst[w] & SO_WSTAT_RANK)) so = se = c_make(NAN, NAN);
         if (overlap) overlap[w] = so;
         if (numer) numer[w] = se;
         if (energy) energy[w] = c_mul(se, c_inv(so));

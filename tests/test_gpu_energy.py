@@ -84,6 +84,26 @@ def test_energy_non_orthonormal_walkers(B, n, eta, W, S, ng):
     check(Sg, Ng, Eg, o, e)
 
 
+def test_energy_flagged_walkers(B):
+    """A rank-deficient walker is flagged and its outputs are NaN; a non-finite
+    one is flagged; the other walkers keep the oracle's values."""
+    n, eta = 8, 4
+    w = wl.make("ef", n, eta, 4, 5, seed=77, n_gamma=6, with_t=True)
+    phi = w.phi.copy()
+    phi[1][:, 3] = phi[1][:, 0]
+    phi[2][0, 0] = np.nan
+    S_, N_, E_, st = B.local_energy(td(phi), td(w.Q), td(w.bits.view(np.int64)), td(w.t), td(w.L))
+    torch.cuda.synchronize()
+    Sg, Ng, Eg, st = (x.cpu().numpy() for x in (S_, N_, E_, st))
+    assert st[1] & B.SO_WSTAT_RANK
+    assert np.isnan(Sg[1]) and np.isnan(Ng[1]) and np.isnan(Eg[1])
+    assert st[2] & B.SO_WSTAT_NONFINITE and not np.isfinite(Sg[2])
+    assert not st[[0, 3]].any()
+    keep = [0, 3]
+    o, e = oracle.energy_pairs(w.phi[keep], w.Q, w.bits, w.t, w.L)
+    check(Sg[keep], Ng[keep], Eg[keep], o, e)
+
+
 def test_energy_overlap_agrees_with_main_path(B):
     """The energy call's S_w (n - eta + 1 full-size Pfaffians off the roots of
     unity) and shadow_overlap's (reduced pencil, roots of unity) are the same estimator:
