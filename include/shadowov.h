@@ -306,7 +306,7 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
  *            are then NaN) / _NONFINITE, and SO_WSTAT_SINGULAR if a node
  *            matrix of some pair was exactly singular (that node's energy
  *            term is then left out)
- * Supported: n <= 16, FP64 (SO_ERR_UNSUPPORTED otherwise); n_walkers <=
+ * Supported: n <= 24, FP64 (SO_ERR_UNSUPPORTED otherwise); n_walkers <=
  * 65535.  One 256-thread workgroup per pair; deterministic (fixed
  * reduction order); no allocation; enqueued on `stream`. */
 so_status so_local_energy_workspace_size(const so_params *p, int64_t n_walkers, int64_t n_shadows, int n_gamma,

@@ -1169,9 +1169,12 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     if (T == 1) {
         hipLaunchKernelGGL(k_energy_shadow<1>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms, Cr);
         hipLaunchKernelGGL(k_energy_walker<1>, dim3((unsigned)W), dim3(256), 0, st, n, eta, Xa, Xr);
-    } else {
+    } else if (T == 2) {
         hipLaunchKernelGGL(k_energy_shadow<2>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms, Cr);
         hipLaunchKernelGGL(k_energy_walker<2>, dim3((unsigned)W), dim3(256), 0, st, n, eta, Xa, Xr);
+    } else {
+        hipLaunchKernelGGL(k_energy_shadow<3>, dim3((unsigned)S), dim3(256), 0, st, n, Ca, Vt, K2, Ms, Cr);
+        hipLaunchKernelGGL(k_energy_walker<3>, dim3((unsigned)W), dim3(256), 0, st, n, eta, Xa, Xr);
     }
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     hipEvent_t ea = nullptr;
@@ -1183,10 +1186,15 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k_energy_pair<1>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xr, Cr, Ms, Vt, Kt, tab, S,
                            op, ep, wst);
-    } else {
+    } else if (T == 2) {
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_energy_pair<2>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(k_energy_pair<2>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xr, Cr, Ms, Vt, Kt, tab, S,
+                           op, ep, wst);
+    } else {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_energy_pair<3>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_energy_pair<3>, grid, dim3(SO_EN_THREADS), lds, st, n, eta, Xr, Cr, Ms, Vt, Kt, tab, S,
                            op, ep, wst);
     }
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;

@@ -27,7 +27,7 @@
 #pragma once
 #include "so_common.h"
 
-#define SO_EN_NMAX 16
+#define SO_EN_NMAX 24
 #define SO_EN_THREADS 256
 
 struct EnTab {
@@ -176,7 +176,8 @@ __device__ __forceinline__ int en_argmax(double v, int idx, double *rv, int *ri,
 // LDS of k_energy_pair, in complex entries: B [m][m], A [max(m^2, 2 n^2)]
 // (the node matrix and its inverse, then zeta and its transpose), YZ [d][d]
 // (A^{-1} X, then Z), Yt [d][d].  X and C' are read through the caches from
-// row-major copies.  At n = 16, eta = 8 this is 52 KB: three blocks per CU.
+// row-major copies.  At n = 16, eta = 8 this is 52 KB: three blocks per CU;
+// at most 141 KB (n = 24, eta = 2): one block.
 __host__ __device__ inline size_t energy_lds_bytes(int n, int eta) {
     const size_t d = 2 * n, m = 2 * n - eta, n2 = (size_t)n * n;
     const size_t asz = m * m > 2 * n2 ? m * m : 2 * n2;
@@ -396,12 +397,12 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
         // likewise c2 from b_ab = sum_sp V_pqrs Yt^(sp)_ab and the W^(qr) blocks, and
         // asq = sum_qr sum_s zeta_rs sum_p V_pqrs zeta_pq.  The first half of the
         // threads accumulates a (and asq), the second half b, each thread for the
-        // two columns (q, r) = t' and t' + half: one LDS read of a 2 x 2 block then
-        // feeds both columns.
-        {
+        // two columns (q, r) = c0 + t' and c0 + t' + half of each chunk of 256
+        // columns c0: one LDS read of a 2 x 2 block then feeds both columns.
+        for (int c0 = 0; c0 < n2; c0 += SO_EN_THREADS) {
             constexpr int half = SO_EN_THREADS / 2;
             const bool bset = t >= half;
-            const int ca = bset ? t - half : t, cb = ca + half;
+            const int ca = c0 + (bset ? t - half : t), cb = ca + half;
             const bool hb = cb < n2;
             auto contract = [&](auto with_as) {
                 constexpr bool AS = decltype(with_as)::value;
@@ -475,8 +476,8 @@ __global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta
                 };
                 double2 acc = fin(qa, ra, x00, x01, x10, x11);
                 if (hb) acc = c_add(acc, fin(qb, rb, y00, y01, y10, y11));
-                if constexpr (AS) c1 = acc;
-                else c2 = acc;
+                if constexpr (AS) c1 = c_add(c1, acc);
+                else c2 = c_add(c2, acc);
             };
             if (ca < n2) {
                 if (bset) contract(std::integral_constant<bool, false>{});

@@ -143,11 +143,25 @@ def test_energy_deterministic(B):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("n,eta,W,S,ng", [(20, 8, 1, 2, 3), (24, 12, 1, 2, 4), (24, 20, 2, 2, 2), (18, 4, 1, 1, 2)])
+def test_energy_beyond_16_modes(B, n, eta, W, S, ng):
+    """n = 17..24: three 16-column tiles and more than 256 (q, r) columns in the
+    V contraction.  n - eta is even here, so the oracle takes the roots of unity
+    (its Chebyshev weights grow too large at these n for a 1e-9 comparison)."""
+    print(f"energy n={n} eta={eta} W={W} S={S} ng={ng}", flush=True)
+    w = wl.make("eb", n, eta, W, S, seed=500 + n + eta, n_gamma=ng, with_t=True)
+    Sg, Ng, Eg, st = run(B, w, w.t, w.L)
+    assert not st.any()
+    o, e = oracle.energy_pairs(w.phi, w.Q, w.bits, w.t, w.L, family="unit")
+    check(Sg, Ng, Eg, o, e)
+
+
 def test_energy_argument_errors(B):
-    w = wl.make("ea", 18, 4, 1, 2, seed=6, n_gamma=2, with_t=True)
+    # n above the library's limit of 24 modes is an invalid shape everywhere
+    w = wl.make("ea", 25, 4, 1, 2, seed=6, n_gamma=2, with_t=True)
     with pytest.raises(B.ShadowOvError) as e:
         run(B, w, w.t, w.L)
-    assert e.value.code == B.SO_ERR_UNSUPPORTED
+    assert e.value.code == B.SO_ERR_ARG
     w = wl.make("eb", 8, 4, 2, 3, seed=6, n_gamma=2, with_t=True)
     p = B.make_params(8, 4, precision="mixed")
     nb = ctypes.c_size_t(0)
