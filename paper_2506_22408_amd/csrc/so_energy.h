@@ -188,9 +188,12 @@ __host__ __device__ inline size_t energy_lds_bytes(int n, int eta) {
 //   Xa, Ca      walker matrices and shadow covariances in A order (so_prep.h)
 //   Ms          per-shadow M (d x d), Vt the n^4 table, Kt (d x d)
 //   opair/epair [W][S] complex out: o_ws and the numerator e_ws
-// Matrices are row-major with their own row length (d or m).
+// Matrices are row-major with their own row length (d or m).  Up to 16 modes
+// three blocks share a CU (168 VGPRs, some spills).  Beyond, the node matrices
+// mostly leave LDS for one or two blocks (115 KB at n = 24, eta = 12), and the
+// register budget of two blocks avoids the spills (1.26x at that shape).
 template <int T>
-__global__ __launch_bounds__(SO_EN_THREADS, 3) void k_energy_pair(int n, int eta, const double2 *__restrict__ Xr,
+__global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(int n, int eta, const double2 *__restrict__ Xr,
                                                                const double *__restrict__ Cr,
                                                                const double *__restrict__ Ms,
                                                                const double *__restrict__ Vt,
