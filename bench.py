@@ -417,6 +417,24 @@ def energy_leg(args, B, wl, torch, np):
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "flops_per_pair": fl,
                         "executed_tflops": executed, "executed_frac": executed / PEAK_FP64_TFLOPS,
                         "avg_launch_ms": kern_s * 1e3, "pairs_per_launch": units / launches}}
+    # context: the same call at 24 modes (three 16-column tiles), timed on the
+    # pair kernel's own launches
+    w24 = wl.config("energy_n24")
+    t24 = [torch.from_numpy(x).to(dev) for x in (w24.phi, w24.Q, w24.bits.view(np.int64), w24.t, w24.L)]
+    B.local_energy(*t24)
+    torch.cuda.synchronize()
+    B.profile_enable(True)
+    B.profile_read(B.PROF_ENERGY)
+    for _ in range(2):
+        S_, N_, E_, st = B.local_energy(*t24)
+    torch.cuda.synchronize()
+    ms24, l24, u24 = B.profile_read(B.PROF_ENERGY)
+    B.profile_enable(False)
+    if int(st.abs().sum()) != 0 or not bool(torch.isfinite(E_.real).all()):
+        raise RuntimeError("local-energy run at 24 modes reported a numerical status")
+    rec["n24"] = {"workload": "energy_n24", "n": w24.n, "eta": w24.eta, "walkers": w24.W, "shadows": w24.S,
+                  "n_gamma": w24.L.shape[1], "nodes_executed": w24.n - w24.eta + 1,
+                  "pair_kernel_ms": ms24 / l24, "pairs_per_s": (u24 / l24) / (ms24 / l24 / 1e3)}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_energy_baseline(w, np)
     return rec

@@ -114,6 +114,7 @@ CONFIGS = {
     "grad_n16": dict(n=16, eta=8, W=1024, S=10000, seed=4, n_gamma=200),
     "precision_n24": dict(n=24, eta=12, W=2048, S=50000, seed=5),
     "energy_n16": dict(n=16, eta=8, W=128, S=1000, seed=7, n_gamma=200, with_t=True),
+    "energy_n24": dict(n=24, eta=12, W=64, S=200, seed=3, n_gamma=200, with_t=True),
 }
 UNEVEN = [dict(n=8, eta=4, W=4096, S=2000, seed=30),
           dict(n=12, eta=6, W=2048, S=5000, seed=31),
