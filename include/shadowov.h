@@ -57,7 +57,14 @@ typedef enum {
 
 /* Interpolation nodes for Pf(A(z)).  UNIT: z_k = exp(2 pi i k / K) (default;
  * a DFT, condition number 1).  CHEBYSHEV: z_k = cos((2k+1) pi / (2K)) as
- * printed in the paper (ill-conditioned for large n). */
+ * printed in the paper (ill-conditioned for large n).  The estimator is one
+ * linear functional of the coefficients of Pf(A(z)), so its value does not
+ * depend on the nodes: so_node_weights gives the named family's nodes and
+ * weights, while the kernels evaluate Pf(B + c J) = z^{-m/2} Pf(A(z)),
+ * c = 1/z, a polynomial of degree n - eta in c, at the n - eta + 1 points
+ * c_j = exp(2 pi i (j + 1/3) / (n - eta + 1)) of the unit circle (as well
+ * conditioned as the roots of unity, and off +-1 and +-i, where the pair
+ * matrices of signed-permutation shadows are often exactly singular). */
 enum { SO_NODES_UNIT = 0, SO_NODES_CHEBYSHEV = 1 };
 
 /* Arithmetic of the pair formation B = X C' X^T (eq. b_mat).  FP64:
@@ -93,9 +100,10 @@ typedef struct {
 #define SO_WSTAT_RANK 1      /* Phi_w is rank-deficient: outputs for w are NaN */
 #define SO_WSTAT_NONFINITE 2 /* a non-finite value reached S_w */
 #define SO_WSTAT_ZERO 4      /* sum_s o_ws == 0: log and gradient undefined (NaN) */
-#define SO_WSTAT_FALLBACK_LOST 8 /* a pair needed the full-size path but its queue
-                                    was full: that pair's estimate may carry the
-                                    rounding of an ill-conditioned elimination */
+#define SO_WSTAT_FALLBACK_LOST 8 /* reserved, never set: every pair that the
+                                    elimination flags reaches the full-size path
+                                    (through its queue, or through a scan of the
+                                    pair values when the queue is full) */
 #define SO_WSTAT_SINGULAR 16 /* shadow_overlap_grad: a node matrix B + c J of some
                                 pair was exactly singular, where the derivative by
                                 inverses is undefined: dlog and green for w are
@@ -304,8 +312,8 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
  *   energy   [n_walkers] complex128 out or NULL: N_w / S_w
  *   status   [n_walkers] int32 out or NULL: SO_WSTAT_RANK (S_w, N_w, E_w
  *            are then NaN) / _NONFINITE, and SO_WSTAT_SINGULAR if a node
- *            matrix of some pair was exactly singular (that node's energy
- *            term is then left out)
+ *            matrix of some pair was exactly singular (the energy of that
+ *            pair is undefined: N_w and E_w are then NaN, S_w is kept)
  * Supported: n <= 24, FP64 (SO_ERR_UNSUPPORTED otherwise); n_walkers <=
  * 65535.  One 256-thread workgroup per pair; deterministic (fixed
  * reduction order); no allocation; enqueued on `stream`. */
@@ -325,6 +333,16 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
  * n <= 32, dt >= 0.  Enqueued on `stream`; the caller owns all memory. */
 so_status so_force_bias(const so_c64 *green, int64_t n_walkers, int n, const double *L, int64_t n_gamma,
                         double dt, so_c64 *xbar, void *stream);
+
+/* Diagnostics: the number of walker x shadow pairs that the last
+ * shadow_overlap call with these arguments and this workspace sent to the
+ * full-size path (the elimination of B_KK met a zero pivot or growth beyond
+ * its bound; such pairs are evaluated as Pf(B + c J) at the full size, which
+ * needs no block of B to be invertible).  Synchronises `stream`, then copies
+ * the counter from the workspace.  Host; SO_ERR_ARG / _UNSUPPORTED /
+ * _WORKSPACE as for so_workspace_size and a too small workspace. */
+so_status so_fallback_count(const so_params *p, int64_t n_walkers, int64_t n_shadows, const void *workspace,
+                            size_t workspace_bytes, int64_t *count, void *stream);
 
 /* Kernel timing for benchmarks (not for the hot path of an application).
  * so_profile_enable(1) makes every later shadow_overlap call bracket each

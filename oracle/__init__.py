@@ -259,7 +259,13 @@ def overlap(phi, Q, bits, K=None, family="unit", nthreads=0) -> np.ndarray:
 
 def grad(phi, Q, bits, K=None, family="unit", nthreads=0):
     """Per walker: S_w, D_w = d log S_w / d Phi_w (holomorphic, n x eta) and
-    the mixed Green's function G_w = D_w Phi_w^T (G_pq = <a_p^dag a_q>)."""
+    the mixed Green's function G_w = D_w Phi_w^T (G_pq = <a_p^dag a_q>).
+
+    Eq. Pfaffian_der needs every node matrix A(z_k) to be invertible.  For a
+    signed-permutation shadow that maps both Majoranas of a mode onto one
+    mode, Pf(A(z)) has exact roots at z = +-1, and the unit-circle nodes
+    include z = 1: use family="chebyshev" (the paper's nodes, never +-1) for
+    that ensemble."""
     phi = _c128(phi)
     Q = _f64(Q)
     bits = np.ascontiguousarray(bits, dtype=np.uint64)

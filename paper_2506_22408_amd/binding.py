@@ -97,6 +97,9 @@ def _load():
     lib.so_local_energy.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, c.c_int, P, P, P, P,
                                     P, c.c_size_t, P]
     lib.so_local_energy.restype = c.c_int
+    lib.so_fallback_count.argtypes = [c.POINTER(SoParams), c.c_int64, c.c_int64, P, c.c_size_t,
+                                      c.POINTER(c.c_int64), P]
+    lib.so_fallback_count.restype = c.c_int
     lib.so_profile_enable.argtypes = [c.c_int]
     lib.so_profile_enable.restype = c.c_int
     lib.so_profile_read.argtypes = [c.c_int, c.POINTER(c.c_double), c.POINTER(c.c_int64), c.POINTER(c.c_int64)]
@@ -220,6 +223,22 @@ def shadow_overlap(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_
     if st != SO_OK:
         raise ShadowOvError(st, "shadow_overlap")
     return out, pairs, status
+
+
+def fallback_count(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_nodes: int = 0,
+                   nodes: str = "unit", precision: str = "fp64", workspace: torch.Tensor | None = None) -> int:
+    """Pairs that the last shadow_overlap call with these shapes (and this
+    workspace: by default the cached one) sent to the full-size path."""
+    W, n, eta, S = _check_inputs(phi, Q, bits)
+    p = make_params(n, eta, n_nodes, nodes, precision)
+    ws = workspace if workspace is not None else _workspace(workspace_size(p, W, S), phi.device)
+    out = ctypes.c_int64(0)
+    stream = torch.cuda.current_stream(phi.device).cuda_stream
+    st = lib.so_fallback_count(ctypes.byref(p), W, S, _dev_ptr(ws), ws.numel(), ctypes.byref(out),
+                               ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "so_fallback_count")
+    return int(out.value)
 
 
 def shadow_overlap_grad(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_nodes: int = 0,

@@ -225,19 +225,20 @@ void compute_weights(const so_params *p, int K, double2 *z, double2 *w) {
     }
 }
 
-// Node table.  Full-size path (rare pairs, so_fallback.h): node matrices
-// s_k B + c_k J in the row order [occupied, empty] of so_prep.h.  Unit-circle
-// nodes use B + conj(z) J = A(z)/z (|z| = 1), so Pf(A(z)) = z^{m/2}
-// Pf(B + conj(z) J); Chebyshev nodes use z B + J.  wf_k weighs Pf(s_k B + c_k J).
-//
-// Reduced path (so_form.h, so_nodes.h): with Q(c) = Pf(B + c J) = sum_x A_x c^x
-// (degree ne = n - eta), Pf(J + z B) = z^{m/2} Q(1/z), so the coefficient of
-// z^y in Pf(A(z)) is A_{m/2-y} and o = pref psign sum_{x=0}^{ne} mu_{m/2-x} A_x
-// whatever the node family.  Q at the roots of unity e_j = exp(2 pi i j/(ne+1))
-// gives A_x = (1/(ne+1)) sum_j Q(e_j) e_j^{-x}, hence o = sum_j v_j Q(e_j) with
-// v_j = (pref psign/(ne+1)) sum_x mu_{m/2-x} e_j^{-x}.  Q(e_j) is
-// pfo Pf(S + e_j J).  psign is the sign of the permutation from the paper's
-// selected order to the stored one.
+// Node table.  With Q(c) = Pf(B + c J) = sum_x A_x c^x (degree ne = n - eta;
+// B and J in the stored row order of so_prep.h), Pf(J + z B) = z^{m/2} Q(1/z),
+// so the coefficient of z^y in Pf(A(z)) is A_{m/2-y} and
+// o = pref psign sum_{x=0}^{ne} mu_{m/2-x} A_x whatever the node family.  Q at
+// the nodes e_j = exp(2 pi i (j + 1/3)/(ne+1)) (the roots of unity turned by a
+// third of a step) gives A_x = (1/(ne+1)) sum_j Q(e_j) e_j^{-x} (for
+// 0 <= x, y <= ne, sum_j e_j^{x-y} vanishes unless x = y), hence
+// o = sum_j v_j Q(e_j) with v_j = (pref psign/(ne+1)) sum_x mu_{m/2-x} e_j^{-x}.
+// The turn keeps the nodes off +-1 and +-i, where Q of a signed-permutation
+// shadow has exact roots (modes whose two Majoranas it maps onto one mode),
+// so the node matrices the derivative inverts stay regular.  The reduced path takes
+// Q(e_j) as Pf(B_KK) Pf(M(e_j)) (so_pair.h) or pfo Pf(S + e_j J) (so_nodes.h),
+// the full-size path as Pf(B + e_j J) itself (so_fallback.h).  psign is the
+// sign of the permutation from the paper's selected order to the stored one.
 // Sign of the permutation from the paper's row order (occupied 0..eta-1,
 // then eta+2u, eta+2u+1 for empty u) to the kernels' order (so_prep.h).
 double row_order_sign(int n, int eta) {
@@ -252,43 +253,28 @@ double row_order_sign(int n, int eta) {
 }
 
 void build_nodetab(const so_params *p, int K, NodeTab *t) {
-    double2 z[SO_KMAX], w[SO_KMAX];
-    compute_weights(p, K, z, w);
     const int n = p->n, eta = p->eta, m = mvalue(n, eta), ne = n - eta;
     const double psign = row_order_sign(n, eta);
     std::memset(t, 0, sizeof(*t));
     t->K = K;
     const long double two_pi = 6.283185307179586476925286766559005768L;
-    for (int k = 0; k < K; ++k) {
-        const double2 wk = make_double2(w[k].x * psign, w[k].y * psign);
-        if (p->nodes == SO_NODES_UNIT) {
-            const long double th = two_pi * (long double)((long long)k * (m / 2) % K) / K;   // z^{m/2}
-            const double cr = (double)cosl(th), ci = (double)sinl(th);
-            t->s[k] = make_double2(1.0, 0.0);
-            t->c[k] = make_double2(z[k].x, -z[k].y);
-            t->wf[k] = make_double2(wk.x * cr - wk.y * ci, wk.x * ci + wk.y * cr);
-        } else {
-            t->s[k] = z[k];
-            t->c[k] = make_double2(1.0, 0.0);
-            t->wf[k] = wk;
-        }
-    }
     long double mu[SO_KMAX];
     cld pref;
     estimator_terms(p, SO_KMAX, mu, &pref);
-    const int Ke = ne + 1;
+    // c_j = exp(2 pi i (3j + 1) / (3 Ke)): angles in units of 2 pi / (3 Ke), exact mod 3 Ke
+    const int Ke = ne + 1, K3 = 3 * Ke;
     t->Ke = Ke;
     for (int j = 0; j < Ke; ++j) {
         long double sr = 0.0L, si = 0.0L;
         for (int x = 0; x <= ne; ++x) {
-            const long double th = -two_pi * (long double)((long long)j * x % Ke) / Ke;
+            const long double th = -two_pi * (long double)((long long)(3 * j + 1) * x % K3) / K3;   // c_j^{-x}
             sr += mu[m / 2 - x] * cosl(th);
             si += mu[m / 2 - x] * sinl(th);
         }
         sr *= psign / (long double)Ke;
         si *= psign / (long double)Ke;
         t->v[j] = make_double2((double)(pref.re * sr - pref.im * si), (double)(pref.re * si + pref.im * sr));
-        const long double te = two_pi * (long double)j / Ke;
+        const long double te = two_pi * (long double)(3 * j + 1) / K3;
         t->e[j] = make_double2((double)cosl(te), (double)sinl(te));
     }
 }
@@ -351,7 +337,7 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false,
     L.off_P = o; o = align_up(o + (size_t)W * Sc * sizeof(double2));
     L.off_pairs = o; o = align_up(o + (size_t)W * S * sizeof(double2));
     L.off_stat = o; o = align_up(o + (size_t)W * sizeof(int32_t));
-    L.off_fbc = o; o = align_up(o + sizeof(uint32_t));
+    L.off_fbc = o; o = align_up(o + sizeof(so_u64));
     L.off_fbl = o; o = align_up(o + (size_t)cap * sizeof(int64_t));
     L.off_fbB = o; o = align_up(o + (size_t)FB_GRID * m * m * sizeof(double2));
     L.Gy = 0;
@@ -379,7 +365,7 @@ struct FormArgs {
     int64_t S_total, s0;
     int Sc, spw;
     double2 *Sb, *Pb;
-    uint32_t *fbc;
+    so_u64 *fbc;
     int64_t *fbl, fb_cap;
     int32_t *wst;
     int64_t W;
@@ -429,7 +415,7 @@ hipError_t launch_form(const FormArgs &a, hipStream_t st) {
 // limited to 65535, so long shadow ranges go in several launches.
 template <int T, int NE, bool MIX>
 hipError_t launch_pair_tn(int n, int eta, const void *Xa, const void *Ca, int64_t W, int64_t S,
-                          const RedTab &rt, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap,
+                          const RedTab &rt, double2 *pairs, so_u64 *fbc, int64_t *fbl, int64_t fb_cap,
                           int32_t *wst, hipStream_t st) {
     constexpr int NB = pair_node_batch(NE);
     const int spw = NB * (NE > 8 ? kRowBatchesPerWave : kPairBatchesPerWave);
@@ -446,7 +432,7 @@ hipError_t launch_pair_tn(int n, int eta, const void *Xa, const void *Ca, int64_
 
 template <int T, bool MIX>
 hipError_t launch_pair_t(int n, int eta, const void *Xa, const void *Ca, int64_t W, int64_t S,
-                         const RedTab &rt, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
+                         const RedTab &rt, double2 *pairs, so_u64 *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
                          hipStream_t st) {
     switch (n - eta) {
         case 2: return launch_pair_tn<T, 2, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
@@ -466,7 +452,7 @@ hipError_t launch_pair_t(int n, int eta, const void *Xa, const void *Ca, int64_t
 }
 
 hipError_t launch_pair(int n, int eta, bool mix, const void *Xa, const void *Ca, int64_t W, int64_t S,
-                       const NodeTab &tab, double2 *pairs, uint32_t *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
+                       const NodeTab &tab, double2 *pairs, so_u64 *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
                        hipStream_t st) {
     RedTab rt;
     std::memset(&rt, 0, sizeof(rt));
@@ -560,7 +546,7 @@ struct ProbPlan {
     float *X32, *C32;
     const void *Xf, *Cf;      // the formation's operands
     int32_t *wst;
-    uint32_t *fbc;
+    so_u64 *fbc;
     int64_t *fbl;
 };
 
@@ -600,7 +586,7 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
     P->Pb = reinterpret_cast<double2 *>(ws + P->L.off_P);
     P->pairs = pair_out ? reinterpret_cast<double2 *>(pair_out) : reinterpret_cast<double2 *>(ws + P->L.off_pairs);
     P->wst = status ? status : reinterpret_cast<int32_t *>(ws + P->L.off_stat);
-    P->fbc = reinterpret_cast<uint32_t *>(ws + P->L.off_fbc);
+    P->fbc = reinterpret_cast<so_u64 *>(ws + P->L.off_fbc);
     P->fbl = reinterpret_cast<int64_t *>(ws + P->L.off_fbl);
     P->fbB = reinterpret_cast<double2 *>(ws + P->L.off_fbB);
     return SO_OK;
@@ -650,8 +636,11 @@ hipError_t enqueue_two_kernel(const ProbPlan &P, hipStream_t st) {
 
 // the full-size path for the flagged pairs, then S_w
 hipError_t enqueue_finish(const ProbPlan &P, hipStream_t st) {
-    hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), 0, st, P.n, P.eta, P.Xw, P.Cw, P.tab, P.fbc, P.fbl,
-                       P.L.fb_cap, P.S, P.fbB, P.pairs);
+    RedTab rt;
+    std::memset(&rt, 0, sizeof(rt));
+    for (int j = 0; j < P.tab.Ke; ++j) { rt.e[j] = P.tab.e[j]; rt.v[j] = P.tab.v[j]; }
+    hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), 0, st, P.n, P.eta, P.Xw, P.Cw, rt, P.tab.Ke, P.fbc,
+                       P.fbl, P.L.fb_cap, P.W, P.S, P.fbB, P.pairs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)P.W), dim3(64), 0, st, P.pairs, P.S, P.overlap, P.wst,
@@ -973,7 +962,7 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
     double *Xa = reinterpret_cast<double *>(ws + L.off_X);
     double *Ca = reinterpret_cast<double *>(ws + L.off_C);
     int32_t *wst = status ? status : reinterpret_cast<int32_t *>(ws + L.off_stat);
-    uint32_t *fbc = reinterpret_cast<uint32_t *>(ws + L.off_fbc);
+    so_u64 *fbc = reinterpret_cast<so_u64 *>(ws + L.off_fbc);
     double2 *Fp = reinterpret_cast<double2 *>(ws + L.off_F);
     double2 *Op = reinterpret_cast<double2 *>(ws + L.off_O);
     NodeTab tab;
@@ -1329,6 +1318,23 @@ so_status so_autotune(so_problem *prob, void *workspace, size_t workspace_bytes,
     (void)hipEventDestroy(e1);
     prob->shadows_per_item = best_spw;
     prob->waves_per_cu = best_wpc;
+    return SO_OK;
+}
+
+so_status so_fallback_count(const so_params *p, int64_t n_walkers, int64_t n_shadows, const void *workspace,
+                            size_t workspace_bytes, int64_t *count, void *stream) {
+    int K;
+    if (!count || !params_ok(p, &K) || n_walkers < 1 || n_shadows < 1) return SO_ERR_ARG;
+    if (!so_supported(p->n, p->eta)) return SO_ERR_UNSUPPORTED;
+    const Layout L = make_layout(p->n, p->eta, n_walkers, n_shadows, false, p->precision == SO_PREC_MIXED);
+    if (!workspace || workspace_bytes < L.total) return SO_ERR_WORKSPACE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    so_u64 v = 0;
+    if (hipMemcpyAsync(&v, static_cast<const char *>(workspace) + L.off_fbc, sizeof(v), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return SO_ERR_HIP;
+    *count = (int64_t)v;
     return SO_OK;
 }
 

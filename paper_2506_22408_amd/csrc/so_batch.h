@@ -18,7 +18,7 @@
 struct PairJob {
     const void *Xa, *Ca;   // formation operands (FP64 or single precision)
     double2 *pairs;
-    uint32_t *fb_count;
+    so_u64 *fb_count;
     int64_t *fb_list;
     int32_t *wstat;
     int64_t fb_cap, S, item0, nitems;

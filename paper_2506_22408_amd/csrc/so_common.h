@@ -122,24 +122,38 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
 __device__ __forceinline__ double2 mirror16c(double2 v) { return c_make(dpp_f64_32<0x140>(v.x), dpp_f64_32<0x140>(v.y)); }
 __device__ __forceinline__ double2 mirror8c(double2 v) { return c_make(dpp_f64_32<0x141>(v.x), dpp_f64_32<0x141>(v.y)); }
 
+// 64-bit counter type of device atomics (the full-size queue)
+typedef unsigned long long so_u64;
+
+// ---- pairs left for the full-size path -----------------------------------------
+// A pair that the elimination flags is queued for the full-size path; when
+// the queue is full its slot in the pair array receives this quiet-NaN bit
+// pattern instead (both halves), and the full-size kernel finds it there by a
+// scan.  No arithmetic result has this payload.
+#define SO_PAIR_MARK 0x7ff85a5e0fa11bacll
+__device__ __forceinline__ double2 so_pair_mark() {
+    const double v = __longlong_as_double(SO_PAIR_MARK);
+    return c_make(v, v);
+}
+__device__ __forceinline__ bool so_is_pair_mark(double2 v) {
+    return __double_as_longlong(v.x) == SO_PAIR_MARK && __double_as_longlong(v.y) == SO_PAIR_MARK;
+}
+
 // ---- node table ---------------------------------------------------------------
-// Node matrices are s B + c J in the row order [occupied, empty] (see
+// Node matrices are B + c J in the row order [occupied, empty] (see
 // so_prep.h).  Q(c) = Pf(B + c J) is a polynomial of degree ne = n - eta in c
 // (J has rank 2 ne), and the estimator is a fixed linear functional of its
-// coefficients.  The reduced path therefore evaluates Q at the ne + 1 roots of
-// unity e_j, as pfo Pf(S + e_j J), with weights v_j; the full-size path
-// evaluates Pf(s_k B + c_k J) at the caller's K nodes with weights wf_k.  Both
-// weight sets carry the interpolation, the inverse-channel factors, the
+// coefficients, whatever nodes the caller names.  The kernels therefore
+// evaluate Q at ne + 1 points e_j of the unit circle (the roots of unity
+// turned by a third of a step) and weigh the values by v_j,
+// which carry the interpolation, the inverse-channel factors, the
 // estimator's prefactor and the sign of the row permutation.
 #define SO_KMAX 49
 struct NodeTab {
-    double2 s[SO_KMAX];    // full-size path
-    double2 c[SO_KMAX];
-    double2 wf[SO_KMAX];
-    double2 e[SO_KMAX];    // reduced path
+    double2 e[SO_KMAX];
     double2 v[SO_KMAX];
-    int K;
-    int Ke;
+    int K;    // the caller's node count (validated; the estimator does not depend on it)
+    int Ke;   // ne + 1
 };
 // the reduced-path part of the table, for kernels that need nothing else
 struct RedTab {

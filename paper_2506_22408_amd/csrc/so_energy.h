@@ -154,8 +154,8 @@ __device__ __forceinline__ void en_sum2(double2 &a, double2 &b, double2 *red) {
     __syncthreads();
 }
 
-// index and value of the largest |x|^2 among the first 64 threads (the
-// candidates of a pivot search never exceed 32; ties: smallest index),
+// index and value of the largest |x|^2 among the first 64 threads (a pivot
+// search has at most m - 1 <= 47 candidates; ties: smallest index),
 // broadcast to the block through one barrier.
 __device__ __forceinline__ int en_argmax(double v, int idx, double *rv, int *ri, double &best) {
     const int t = threadIdx.x;
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
 
 // Per walker, in a fixed order: S_w = (1/S) sum_s o_ws, N_w = (1/S) sum_s e_ws,
 // E_w = N_w / S_w; NaN for a walker flagged rank-deficient, as in the overlap
-// path.  One block of 256 threads per walker.
+// path, and N_w, E_w NaN for a walker with a singular node matrix.  One block of 256 threads per walker.
 __global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, const double2 *__restrict__ opair,
                                                        const double2 *__restrict__ epair, double2 *__restrict__ overlap,
                                                        double2 *__restrict__ numer, double2 *__restrict__ energy,
@@ -528,10 +528,12 @@ __global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, const double2 
         so = c_scale(so, inv);
         se = c_scale(se, inv);
         if (wst && (wst[w] & SO_WSTAT_RANK)) so = se = c_make(NAN, NAN);
+        if (wst && !(isfinite(so.x) && isfinite(so.y) && isfinite(se.x) && isfinite(se.y)))
+            wst[w] |= SO_WSTAT_NONFINITE;
+        // a singular node matrix leaves its energy term undefined: no number
+        if (wst && (wst[w] & SO_WSTAT_SINGULAR)) se = c_make(NAN, NAN);
         if (overlap) overlap[w] = so;
         if (numer) numer[w] = se;
         if (energy) energy[w] = c_mul(se, c_inv(so));
-        if (wst && !(isfinite(so.x) && isfinite(so.y) && isfinite(se.x) && isfinite(se.y)))
-            wst[w] |= SO_WSTAT_NONFINITE;
     }
 }

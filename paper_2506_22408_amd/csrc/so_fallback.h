@@ -1,10 +1,18 @@
-// so_fallback.h -- full-size path for the pairs whose occupied-block
-// elimination met a zero pivot or too much growth (so_form.h).  Rare and
-// simple: recompute B = X C' X^T for the pair, then for every node the
-// Pfaffian of A = s_k B + c_k J (m x m, J materialised) by Householder
-// tridiagonalisation with the matrix in LDS, lane = row.  No shortcut, so
-// it is exact to rounding whatever B_OO is.  The grid is fixed; blocks stride
-// over the queue, whose length is read on the device.
+// so_fallback.h -- full-size path for the pairs whose elimination met a zero
+// pivot or too much growth (so_pair.h, so_form.h).  Rare and simple:
+// recompute B = X C' X^T for the pair, then for every node e_j of the reduced
+// table the Pfaffian of B + e_j J (m x m, J materialised) by Householder
+// tridiagonalisation with the matrix in LDS, lane = row, and the pair value
+// o = sum_j v_j Pf(B + e_j J).  Q(c) = Pf(B + c J) has degree ne = n - eta in
+// c, so its values at the ne + 1 nodes of the table determine the estimator
+// exactly; no block of B has to be invertible, so the value is exact to
+// rounding whatever B_KK is.
+//
+// Work: first the queue of flagged pairs; then, only if the queue overflowed,
+// a scan of the pair array for the pairs marked SO_PAIR_MARK (so_common.h).
+// Every flagged pair therefore reaches this path.  The grid is fixed; blocks
+// stride over the queue, whose length is read on the device, and over the
+// pair array.
 #pragma once
 #include "so_common.h"
 
@@ -51,61 +59,96 @@ __device__ __forceinline__ double2 hh_pf_lds(double2 *A, int lda, int m, double2
     return pf;
 }
 
-// grid FB_GRID, 64 threads; Bscratch holds FB_GRID matrices of m x m.
-__global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double *__restrict__ Xa,
-                                                 const double *__restrict__ Ca, NodeTab tab,
-                                                 const uint32_t *__restrict__ fb_count,
-                                                 const int64_t *__restrict__ fb_list, int64_t fb_cap, int64_t S_total,
-                                                 double2 *__restrict__ Bscratch, double2 *__restrict__ pairs) {
-    __shared__ double2 A[SO_MMAX * (SO_MMAX + 1)];
-    __shared__ double2 trow[2 * SO_NMAX];
-    __shared__ double2 ubuf[SO_MMAX];
-    __shared__ double2 ybuf[SO_MMAX];
-    const int q = threadIdx.x;
+// LDS of one full-size evaluation (one wave)
+struct FbLds {
+    double2 A[SO_MMAX * (SO_MMAX + 1)];
+    double2 trow[2 * SO_NMAX];
+    double2 ubuf[SO_MMAX];
+    double2 ybuf[SO_MMAX];
+};
+
+// o_ws of walker w and shadow s on the full-size path; Bg is m x m complex of
+// this block's global scratch.  Every lane returns the value.
+__device__ __forceinline__ double2 fb_pair(int n, int eta, const double *__restrict__ Xa,
+                                           const double *__restrict__ Ca, const RedTab &tab, int Ke, int64_t w,
+                                           int64_t s, double2 *__restrict__ Bg, FbLds &sh, int q) {
     const int d = 2 * n, m = 2 * n - eta, ne = n - eta, LDA = m + 1;
     const int T = so_tiles(n), DP = 16 * T;
-    const int64_t cnt = min((int64_t)(*fb_count), fb_cap);
+    const double *Xw = Xa + (size_t)w * DP * DP;
+    const double *C = Ca + (size_t)s * DP * DP;
+    for (int i = 0; i < m; ++i) {
+        __syncthreads();
+        if (q < d) {
+            double2 acc = c_make(0, 0);
+            for (int mu = 0; mu < d; ++mu)
+                acc = c_fma(fb_xrow(Xw, i, mu, eta, T), c_make(C[ao_index(mu, q, T)], 0.0), acc);
+            sh.trow[q] = acc;
+        }
+        __syncthreads();
+        if (q < m) {
+            double2 acc = c_make(0, 0);
+            for (int nu = 0; nu < d; ++nu) acc = c_fma(sh.trow[nu], fb_xrow(Xw, q, nu, eta, T), acc);
+            Bg[i * m + q] = acc;
+        }
+    }
+    __syncthreads();
+    double2 o = c_make(0, 0);
+    for (int node = 0; node < Ke; ++node) {
+        const double2 ck = tab.e[node];
+        __syncthreads();
+        if (q < m)
+            for (int j = 0; j < m; ++j) {
+                // exact antisymmetry: the lower triangle is the negated upper one
+                double2 v = (j > q) ? Bg[q * m + j] : ((j < q) ? c_neg(Bg[j * m + q]) : c_make(0, 0));
+                if (q >= eta && j >= eta) {
+                    const int t = q - eta;
+                    if (j - eta == 2 * ne - 1 - t) v = c_add(v, c_scale(ck, t < ne ? 1.0 : -1.0));
+                }
+                sh.A[q * LDA + j] = v;
+            }
+        __syncthreads();
+        const double2 pf = hh_pf_lds(sh.A, LDA, m, sh.ubuf, sh.ybuf, q);
+        o = c_fma(tab.v[node], pf, o);
+    }
+    return o;
+}
+
+// grid FB_GRID, 64 threads; Bscratch holds FB_GRID matrices of m x m.
+// pairs is [W][S_total]; Ke = ne + 1 nodes of the reduced table.
+__global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double *__restrict__ Xa,
+                                                 const double *__restrict__ Ca, RedTab tab, int Ke,
+                                                 const so_u64 *__restrict__ fb_count,
+                                                 const int64_t *__restrict__ fb_list, int64_t fb_cap, int64_t W,
+                                                 int64_t S_total, double2 *__restrict__ Bscratch,
+                                                 double2 *__restrict__ pairs) {
+    __shared__ FbLds sh;
+    const int q = threadIdx.x;
+    const int m = 2 * n - eta;
+    const int64_t queued = (int64_t)(*fb_count);
+    const int64_t cnt = min(queued, fb_cap);
     double2 *Bg = Bscratch + (size_t)blockIdx.x * m * m;
     for (int64_t e = blockIdx.x; e < cnt; e += gridDim.x) {
         const int64_t gs = fb_list[e];
         const int64_t w = gs / S_total, s = gs - w * S_total;
-        const double *Xw = Xa + (size_t)w * DP * DP;
-        const double *C = Ca + (size_t)s * DP * DP;
-        for (int i = 0; i < m; ++i) {
-            __syncthreads();
-            if (q < d) {
-                double2 acc = c_make(0, 0);
-                for (int mu = 0; mu < d; ++mu)
-                    acc = c_fma(fb_xrow(Xw, i, mu, eta, T), c_make(C[ao_index(mu, q, T)], 0.0), acc);
-                trow[q] = acc;
-            }
-            __syncthreads();
-            if (q < m) {
-                double2 acc = c_make(0, 0);
-                for (int nu = 0; nu < d; ++nu) acc = c_fma(trow[nu], fb_xrow(Xw, q, nu, eta, T), acc);
-                Bg[i * m + q] = acc;
-            }
+        const double2 o = fb_pair(n, eta, Xa, Ca, tab, Ke, w, s, Bg, sh, q);
+        if (q == 0) pairs[gs] = o;
+    }
+    if (queued <= fb_cap) return;
+    // the queue overflowed: the pairs it could not hold carry the mark.  Each
+    // block scans its own 64-pair chunks; a found pair is written only by the
+    // block that found it, and no queued pair is ever marked.
+    const int64_t total = W * S_total;
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < total; base += (int64_t)gridDim.x * 64) {
+        const int64_t e = base + q;
+        const bool mk = e < total && so_is_pair_mark(pairs[e]);
+        unsigned long long mask = __ballot(mk);
+        while (mask) {
+            const int b = __ffsll(mask) - 1;
+            mask &= mask - 1;
+            const int64_t gs = base + b;
+            const int64_t w = gs / S_total, s = gs - w * S_total;
+            const double2 o = fb_pair(n, eta, Xa, Ca, tab, Ke, w, s, Bg, sh, q);
+            if (q == 0) pairs[gs] = o;
         }
-        __syncthreads();
-        double2 o = c_make(0, 0);
-        for (int node = 0; node < tab.K; ++node) {
-            const double2 sk = tab.s[node], ck = tab.c[node];
-            __syncthreads();
-            if (q < m)
-                for (int j = 0; j < m; ++j) {
-                    // exact antisymmetry: the lower triangle is the negated upper one
-                    double2 v = (j > q) ? Bg[q * m + j] : ((j < q) ? c_neg(Bg[j * m + q]) : c_make(0, 0));
-                    v = c_mul(v, sk);
-                    if (q >= eta && j >= eta) {
-                        const int t = q - eta;
-                        if (j - eta == 2 * ne - 1 - t) v = c_add(v, c_scale(ck, t < ne ? 1.0 : -1.0));
-                    }
-                    A[q * LDA + j] = v;
-                }
-            __syncthreads();
-            const double2 pf = hh_pf_lds(A, LDA, m, ubuf, ybuf, q);
-            o = c_fma(tab.wf[node], pf, o);
-        }
-        if (q == 0) pairs[w * S_total + s] = o;
     }
 }

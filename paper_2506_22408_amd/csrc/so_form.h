@@ -57,7 +57,7 @@ template <int T, int NS, bool MIX>
 __global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const void *__restrict__ Xa,
                                                   const void *__restrict__ Ca, int64_t S_total, int64_t s0,
                                                   int Sc, int spw, double2 *__restrict__ Sbuf,
-                                                  double2 *__restrict__ Pbuf, uint32_t *__restrict__ fb_count,
+                                                  double2 *__restrict__ Pbuf, so_u64 *__restrict__ fb_count,
                                                   int64_t *__restrict__ fb_list, int64_t fb_cap,
                                                   int32_t *__restrict__ wstat) {
     constexpr int KK = 4 * T, DP = 16 * T, LDP = DP + 1;
@@ -198,12 +198,14 @@ __global__ __launch_bounds__(64) void k_form_mfma(int n, int eta, const void *__
         smax = wave_max(smax);
         const bool flag = zero || !(smax <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * bmax);
         if (l == 0) {
-            Pbuf[pair] = pfo;
+            double2 pv = pfo;
             if (flag) {
-                const uint32_t idx = atomicAdd(fb_count, 1u);
+                // queued for the full-size path, or marked for its scan when the queue is full
+                const so_u64 idx = atomicAdd(fb_count, 1ull);
                 if ((int64_t)idx < fb_cap) fb_list[idx] = (int64_t)w * S_total + s0 + sl;
-                else atomicOr(&wstat[w], SO_WSTAT_FALLBACK_LOST);
+                else pv = so_pair_mark();
             }
+            Pbuf[pair] = pv;
         }
     }
 }

@@ -1,5 +1,5 @@
 // so_nodes.h -- node Pfaffians Pf(S + e_j J) of the Schur complement
-// S (M2 x M2, M2 = 2(n - eta)) at the ne + 1 roots of unity e_j, and the
+// S (M2 x M2, M2 = 2(n - eta)) at the ne + 1 nodes e_j of the node table, and the
 // weighted node sum per pair (so_common.h, node table).
 //
 // In the compact order every row of S belongs to an empty orbital and J
@@ -236,9 +236,9 @@ __global__ __launch_bounds__(64) void k_nodes(const double2 *__restrict__ Sbuf, 
         if (pair < npairs) {
             double2 acc = c_make(0, 0);
             for (int node = 0; node < K; ++node) acc = c_add(acc, vals[lane * K + node]);
-            acc = c_mul(acc, Pbuf[pair]);
+            const double2 pb = Pbuf[pair];
             const int64_t w = pair / Sc, sl = pair - w * Sc;
-            pairs[w * S_total + s0 + sl] = acc;
+            pairs[w * S_total + s0 + sl] = so_is_pair_mark(pb) ? pb : c_mul(acc, pb);
         }
     }
 }
@@ -295,8 +295,8 @@ __global__ __launch_bounds__(64) void k_nodes_wide(int M2, const double2 *__rest
         acc = c_fma(tab.v[node], pf, acc);
     }
     if (q == 0) {
-        acc = c_mul(acc, Pbuf[pair]);
+        const double2 pb = Pbuf[pair];
         const int64_t w = pair / Sc, sl = pair - w * Sc;
-        pairs[w * S_total + s0 + sl] = acc;
+        pairs[w * S_total + s0 + sl] = so_is_pair_mark(pb) ? pb : c_mul(acc, pb);
     }
 }

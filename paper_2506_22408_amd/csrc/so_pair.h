@@ -23,7 +23,8 @@
 // entries or T beyond SO_SCHUR_GROWTH x max(max|B|, 1), queues the pair for
 // the full-size path (so_fallback.h).
 //
-// Nodes: Q(c) = Pf(B + c J) is evaluated at the ne + 1 roots of unity e_j and
+// Nodes: Q(c) = Pf(B + c J) is evaluated at the ne + 1 nodes e_j (roots of
+// unity turned by a third of a step, node table in shadowov.hip) and
 // weighted by v_j (node table, so_common.h).  Each lane forms M(e_j) for its
 // (pair, node) and reduces it by Householder tridiagonalisation entirely in
 // registers (static indices), so a wave runs NB = 64 / (ne + 1) pairs'
@@ -312,7 +313,7 @@ __host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
 template <int T, int NE, bool MIX>
 __device__ __forceinline__ void pair_range(int n, int eta, const void *__restrict__ Xa,
                                            const void *__restrict__ Ca, int64_t S_total, const RedTab &tab,
-                                           double2 *__restrict__ pairs, uint32_t *__restrict__ fb_count,
+                                           double2 *__restrict__ pairs, so_u64 *__restrict__ fb_count,
                                            int64_t *__restrict__ fb_list, int64_t fb_cap,
                                            int32_t *__restrict__ wstat, int w, int64_t sb0, int64_t sb1) {
     constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
@@ -426,10 +427,11 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
             // ---------------- pairwise elimination of K
             double2 pfk;
             const bool flag = elim_bordered<NE, NTQ>(n, WR, Rl, ta, tb, tv, bmax, rbmax, l, pfk);
+            bool queued = true;   // (lane 0) a flagged pair found room in the queue
             if (l == 0 && flag) {
-                const uint32_t idx = atomicAdd(fb_count, 1u);
+                const so_u64 idx = atomicAdd(fb_count, 1ull);
                 if ((int64_t)idx < fb_cap) fb_list[idx] = (int64_t)w * S_total + s;
-                else atomicOr(&wstat[w], SO_WSTAT_FALLBACK_LOST);
+                else queued = false;
             }
             // ---------------- M0, M1, M2 (upper triangles) and Pf(B_KK) into the batch slot
             __syncthreads();   // R reads done
@@ -448,7 +450,9 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
                 slot[NT + e] = c_sub(Tl[tix(x, NE + y)], Tl[tix(y, NE + x)]);         // M1
                 slot[2 * NT + e] = Tl[tix(NE + x, NE + y)];                           // M2
             }
-            if (l == 0) slot[3 * NT] = flag ? c_make(0.0, 0.0) : pfk;
+            // a flagged pair's value comes from the full-size path: zero here,
+            // or the mark when the queue had no room (the full-size kernel scans for it)
+            if (l == 0) slot[3 * NT] = flag ? (queued ? c_make(0.0, 0.0) : so_pair_mark()) : pfk;
         }
         // ---------------- node Pfaffians of the batch
         __syncthreads();
@@ -468,8 +472,8 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
             if (l < nb) {
                 double2 acc = c_make(0.0, 0.0);
                 for (int j = 0; j < KE; ++j) acc = c_add(acc, Vl[l * KE + j]);
-                acc = c_mul(acc, Bt[l * SLOT + 3 * NT]);
-                pairs[(int64_t)w * S_total + bs + l] = acc;
+                const double2 pk = Bt[l * SLOT + 3 * NT];
+                pairs[(int64_t)w * S_total + bs + l] = so_is_pair_mark(pk) ? pk : c_mul(acc, pk);
             }
             continue;
         }
@@ -502,8 +506,8 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
         if (l < nb) {
             double2 acc = c_make(0.0, 0.0);
             for (int j = 0; j < KE; ++j) acc = c_add(acc, Vl[l * KE + j]);
-            acc = c_mul(acc, Bt[l * SLOT + 3 * NT]);
-            pairs[(int64_t)w * S_total + bs + l] = acc;
+            const double2 pk = Bt[l * SLOT + 3 * NT];
+            pairs[(int64_t)w * S_total + bs + l] = so_is_pair_mark(pk) ? pk : c_mul(acc, pk);
         }
     }
 }
@@ -515,7 +519,7 @@ template <int T, int NE, bool MIX>
 __global__ __launch_bounds__(64, 2) void k_pair(int n, int eta, const void *__restrict__ Xa,
                                              const void *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
                                              RedTab tab, double2 *__restrict__ pairs,
-                                             uint32_t *__restrict__ fb_count, int64_t *__restrict__ fb_list,
+                                             so_u64 *__restrict__ fb_count, int64_t *__restrict__ fb_list,
                                              int64_t fb_cap, int32_t *__restrict__ wstat) {
     const int64_t sb0 = (sy0 + blockIdx.y) * (int64_t)spw;
     const int64_t sb1 = min(S_total, sb0 + spw);

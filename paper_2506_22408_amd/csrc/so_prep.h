@@ -27,13 +27,13 @@
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double2 *__restrict__ phi,
                                                     double *__restrict__ Xa, int32_t *__restrict__ wstat,
-                                                    uint32_t *__restrict__ fb_count) {
+                                                    so_u64 *__restrict__ fb_count) {
     __shared__ double2 R[SO_NMAX][SO_NMAX];
     __shared__ double2 V[SO_NMAX][SO_NMAX];
     __shared__ double betas[SO_NMAX];
     const int w = blockIdx.x;
     const int p = threadIdx.x;
-    if (w == 0 && p == 0 && fb_count) *fb_count = 0u;
+    if (w == 0 && p == 0 && fb_count) *fb_count = 0ull;
     const int d = 2 * n;
     const int ne = n - eta;
     const int T = so_tiles(n), DP = 16 * T;

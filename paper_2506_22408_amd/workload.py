@@ -13,6 +13,8 @@ Recipe (numpy ``default_rng(seed)``, PCG64, drawn in this order):
   walkers  Phi = reduced QR of (Z1 + i Z2), Z i.i.d. N(0,1)      [W,n,eta] c128
   shadows  Q   = Haar SO(2n): QR of a Gaussian, column signs fixed by
                  sign(diag R), first column negated if det < 0    [S,2n,2n] f64
+           or (perm workloads) uniform signed permutations with det = +1,
+                 the paper's ensemble                             [S,2n,2n] f64
   bits     b   = n-1 uniform bits, the last bit set to their parity
                  (uniform over even-parity strings); bit j is b_{j+1} [S] u64
   L        Cholesky-like vectors, N(0, 0.1^2), symmetrised per index pair
@@ -52,6 +54,21 @@ def haar_so(rng, S: int, d: int, chunk: int = 4096) -> np.ndarray:
         neg = np.linalg.det(Qm) < 0
         Qm[neg, :, 0] *= -1.0
         out[s0:s1] = Qm
+    return out
+
+
+def signed_permutations(rng, S: int, d: int) -> np.ndarray:
+    """Uniform signed permutations of d Majoranas with det = +1, the paper's
+    shadow ensemble: Q[mu, pi(mu)] = s_mu with a uniform permutation pi and
+    uniform signs, the first sign flipped where the determinant is -1."""
+    perm = np.argsort(rng.random((S, d)), axis=1)
+    signs = rng.choice(np.array([-1.0, 1.0]), size=(S, d))
+    out = np.zeros((S, d, d))
+    rows = np.arange(d)
+    for s in range(S):
+        out[s, rows, perm[s]] = signs[s]
+    neg = np.linalg.det(out) < 0
+    out[neg, 0, :] *= -1.0
     return out
 
 
@@ -97,10 +114,16 @@ def one_body(rng, n: int, scale: float = 0.1) -> np.ndarray:
 
 
 def make(name: str, n: int, eta: int, W: int, S: int, seed: int, n_gamma: int = 0,
-         orthonormal: bool = True, with_t: bool = False) -> Workload:
+         orthonormal: bool = True, with_t: bool = False, shadows: str = "haar") -> Workload:
+    """shadows: "haar" (Haar SO(2n)) or "perm" (signed permutations, the paper's ensemble)."""
     rng = np.random.default_rng(seed)
     phi = walkers(rng, W, n, eta, orthonormal)
-    Q = haar_so(rng, S, 2 * n)
+    if shadows == "haar":
+        Q = haar_so(rng, S, 2 * n)
+    elif shadows == "perm":
+        Q = signed_permutations(rng, S, 2 * n)
+    else:
+        raise ValueError(f"unknown shadow ensemble {shadows!r}")
     bits = even_bits(rng, S, n)
     L = cholesky_like(rng, n, n_gamma) if n_gamma else None
     t = one_body(rng, n) if with_t else None
@@ -115,6 +138,8 @@ CONFIGS = {
     "precision_n24": dict(n=24, eta=12, W=2048, S=50000, seed=5),
     "energy_n16": dict(n=16, eta=8, W=128, S=1000, seed=7, n_gamma=200, with_t=True),
     "energy_n24": dict(n=24, eta=12, W=64, S=200, seed=3, n_gamma=200, with_t=True),
+    # the paper's own shadow ensemble (random signed permutations) at the paper's size
+    "perm_n16": dict(n=16, eta=8, W=1024, S=10000, seed=9, shadows="perm"),
 }
 UNEVEN = [dict(n=8, eta=4, W=4096, S=2000, seed=30),
           dict(n=12, eta=6, W=2048, S=5000, seed=31),

@@ -2,11 +2,15 @@
 the uneven reaction-path workload (N = 8, 12, 16, 20 qubits, eta = N/2, one
 problem per geometry) must give exactly the bits of separate shadow_overlap
 calls (same kernels, same node tables, same fixed-order reduction), whatever
-the tuning knobs, also when captured into a graph and replayed."""
+the tuning knobs, also when captured into a graph and replayed; and the
+values of the oracle, on every pair of the miniature and on sampled pairs of
+the full-size workload (tolerance as for single calls: 1e-10 per pair
+relative to max(|o|, 1e-3 median |o|), 1e-10 per walker)."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2506_22408_amd import workload as wl
 
 pytestmark = pytest.mark.gpu
@@ -126,3 +130,41 @@ def test_graph_capture_and_replay(B):
     assert_same(got[0], ref0)
     for a, b in zip(got[1:], eager[1:]):
         assert_same(a, b)
+
+
+def assert_oracle_pairs(pg, po, what):
+    scale = np.median(np.abs(po))
+    rel = np.abs(pg - po) / np.maximum(np.abs(po), 1e-3 * scale)
+    assert rel.max() <= 1e-10, f"{what}: worst rel {rel.max():.3e}"
+    return rel.max()
+
+
+def test_batched_matches_oracle(B):
+    ws = mini_uneven()
+    bt = B.Batch([dev_problem(w) for w in ws])
+    bt.run()
+    for k, (w, (og, pg, st)) in enumerate(zip(ws, batch_results(bt))):
+        po = oracle.overlap_pairs(w.phi, w.Q, w.bits)
+        worst = assert_oracle_pairs(pg, po, f"problem {k} (n={w.n})")
+        so = po.mean(axis=1)
+        assert np.all(np.abs(og - so) <= 1e-10 * np.abs(so))
+        assert not st.any()
+        print(f"problem {k} (n={w.n}, eta={w.eta}): worst pair rel err {worst:.2e}")
+
+
+def test_uneven_full_size_sampled(B):
+    """The four reaction-path geometries at full size (3.89e7 pairs) in one
+    batched call; 1,000 sampled pairs per geometry against the oracle."""
+    ws = [wl.make(f"uneven{k}", **c) for k, c in enumerate(wl.UNEVEN)]
+    print("uneven: inputs ready", flush=True)
+    bt = B.Batch([dev_problem(w) for w in ws])
+    bt.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(33)
+    for k, w in enumerate(ws):
+        assert not bt.status[k].cpu().numpy().any()
+        sw, ss = rng.integers(0, w.W, 1000), rng.integers(0, w.S, 1000)
+        pg = bt.pairs[k][torch.from_numpy(sw).to(dev()), torch.from_numpy(ss).to(dev())].cpu().numpy()
+        po = oracle.overlap_pairs(w.phi, w.Q, w.bits, pairs=np.stack([sw, ss], 1))
+        worst = assert_oracle_pairs(pg, po, f"geometry n={w.n}")
+        print(f"uneven n={w.n}: {w.W} x {w.S}, worst sampled pair rel err {worst:.2e}")

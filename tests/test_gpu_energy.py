@@ -143,17 +143,40 @@ def test_energy_deterministic(B):
         assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("n,eta,W,S,ng", [(20, 8, 1, 2, 3), (24, 12, 1, 2, 4), (24, 20, 2, 2, 2), (18, 4, 1, 1, 2)])
+@pytest.mark.parametrize("n,eta,W,S,ng", [(20, 8, 1, 2, 3), (24, 12, 1, 2, 4), (24, 20, 2, 2, 2), (18, 4, 1, 1, 2),
+                                          (24, 2, 1, 2, 2), (24, 4, 1, 2, 2), (21, 4, 1, 2, 2), (19, 6, 1, 2, 2)])
 def test_energy_beyond_16_modes(B, n, eta, W, S, ng):
     """n = 17..24: three 16-column tiles and more than 256 (q, r) columns in the
-    V contraction.  n - eta is even here, so the oracle takes the roots of unity
-    (its Chebyshev weights grow too large at these n for a 1e-9 comparison)."""
+    V contraction, up to m = 46 (n = 24, eta = 2: the largest LDS shape, and
+    pivot searches over up to 45 candidates).  The oracle takes roots of unity
+    (its Chebyshev weights grow too large at these n for a 1e-9 comparison):
+    K = n + 1 of them when n - eta is even; when it is odd, z = -1 is a root of
+    every pair's Pfaffian and the oracle takes an odd K = n + 2, whose roots of
+    unity avoid -1."""
     print(f"energy n={n} eta={eta} W={W} S={S} ng={ng}", flush=True)
     w = wl.make("eb", n, eta, W, S, seed=500 + n + eta, n_gamma=ng, with_t=True)
     Sg, Ng, Eg, st = run(B, w, w.t, w.L)
     assert not st.any()
-    o, e = oracle.energy_pairs(w.phi, w.Q, w.bits, w.t, w.L, family="unit")
+    K = None if (n - eta) % 2 == 0 else (n + 2 if n % 2 else n + 1)
+    o, e = oracle.energy_pairs(w.phi, w.Q, w.bits, w.t, w.L, K=K, family="unit")
     check(Sg, Ng, Eg, o, e)
+
+
+def test_energy_singular_node_gives_nan(B):
+    """Single-mode walkers with the identity shadow make every node matrix
+    singular (the pair's Pfaffian polynomial vanishes): the walker is
+    flagged, its numerator and energy are NaN and its overlap is kept."""
+    n, eta, W, S = 8, 4, 2, 3
+    rng = np.random.default_rng(12)
+    phi = np.zeros((W, n, eta), complex)
+    for k in range(W):
+        phi[k, rng.choice(n, eta, replace=False), np.arange(eta)] = 1.0
+    w = wl.make("es", n, eta, W, S, seed=13, n_gamma=3, with_t=True)
+    w = wl.Workload("es", n, eta, phi, np.tile(np.eye(2 * n), (S, 1, 1)), np.zeros(S, np.uint64), w.L, w.t)
+    Sg, Ng, Eg, st = run(B, w, w.t, w.L)
+    assert np.all(st & B.SO_WSTAT_SINGULAR)
+    assert np.all(np.isnan(Ng)) and np.all(np.isnan(Eg))
+    assert np.all(np.abs(Sg) < 1e-13)
 
 
 def test_energy_argument_errors(B):

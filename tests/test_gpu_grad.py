@@ -64,6 +64,96 @@ def test_grad_matches_oracle(B, n, eta, W, S):
     print(f"n={n} eta={eta}: worst D {ed:.2e}, G {eg:.2e} (relative to max per walker)")
 
 
+@pytest.mark.parametrize("n,eta,S", [(8, 4, 16), (8, 4, 40), (8, 4, 136), (16, 8, 16), (16, 8, 40), (16, 8, 136)])
+def test_grad_several_shadows_per_range(B, n, eta, S):
+    """1024 walkers split the shadows into 8 ranges per walker, so one wave
+    accumulates F and the pair sum over spw = 2, 5 and 17 shadows (as the
+    paper-sized workload does over 1,250): 16 walkers against the oracle."""
+    W = 1024
+    w = wl.make("spw", n, eta, W, S, seed=610 + n + S)
+    sg, dg, gg, st = gpu_grad(B, w.phi, w.Q, w.bits)
+    assert not st.any()
+    pick = np.random.default_rng(S).choice(W, 16, replace=False)
+    so, do, go = oracle.grad(w.phi[pick], w.Q, w.bits)
+    assert np.all(np.abs(sg[pick] - so) <= 1e-10 * np.abs(so))
+    ed, eg = close_per_walker(dg[pick], do, 1e-10), close_per_walker(gg[pick], go, 1e-10)
+    print(f"n={n} S={S} (spw {-(-S // 8)}): worst D {ed:.2e}, G {eg:.2e}")
+
+
+@pytest.fixture(scope="module")
+def grad_paper(B):
+    """The paper-sized derivative workload (1024 walkers x 10,000 shadows,
+    8 shadow ranges of 1,250 per walker) through the C ABI once."""
+    w = wl.config("grad_n16")
+    print(f"grad_n16: {w.W} x {w.S} pairs through shadow_overlap_grad", flush=True)
+    return w, gpu_grad(B, w.phi, w.Q, w.bits)
+
+
+def test_grad_paper_workload_sampled(grad_paper):
+    """S_w, D_w and G_w of 16 walkers of the full workload against the
+    oracle over all 10,000 shadows."""
+    w, (sg, dg, gg, st) = grad_paper
+    assert not st.any()
+    pick = np.random.default_rng(4).choice(w.W, 16, replace=False)
+    so, do, go = oracle.grad(w.phi[pick], w.Q, w.bits)
+    assert np.all(np.abs(sg[pick] - so) <= 1e-10 * np.abs(so))
+    ed, eg = close_per_walker(dg[pick], do, 1e-10), close_per_walker(gg[pick], go, 1e-10)
+    print(f"grad_n16, 16 walkers x 10000 shadows: worst D {ed:.2e}, G {eg:.2e}")
+
+
+def test_grad_paper_workload_finite_differences(B, grad_paper):
+    """Central differences (h = 1e-6) of the HIP forward over all 10,000
+    shadows on 8 walkers of the full workload, against D_w S_w from the
+    full-size derivative launch."""
+    w, (sg, dg, _, _) = grad_paper
+    pick = np.arange(8) * 127
+    Qd = torch.from_numpy(w.Q).to(dev())
+    bd = torch.from_numpy(w.bits.view(np.int64)).to(dev())
+    rng = np.random.default_rng(8)
+    h = 1e-6
+    for _ in range(4):
+        p, j = int(rng.integers(w.n)), int(rng.integers(w.eta))
+        for step in (h, 1j * h):
+            ph = w.phi[pick].copy()
+            ph[:, p, j] += step
+            sp, _, _ = B.shadow_overlap(torch.from_numpy(ph).to(dev()), Qd, bd)
+            ph[:, p, j] -= 2 * step
+            sm, _, _ = B.shadow_overlap(torch.from_numpy(ph).to(dev()), Qd, bd)
+            fd = (sp.cpu().numpy() - sm.cpu().numpy()) / (2 * step)
+            an = dg[pick, p, j] * sg[pick]
+            assert np.all(np.abs(fd - an) <= 1e-7 * np.abs(an) + 1e-12), (p, j, step, fd, an)
+            print(f"FD ({p},{j}) step {step}: worst rel {np.max(np.abs(fd - an) / np.abs(an)):.2e}")
+
+
+def test_grad_signed_permutation_shadows(B):
+    """The paper's shadow ensemble (random signed permutations) through the
+    derivative, against the oracle and against central differences of the
+    HIP forward.  A signed permutation that maps both Majoranas of a mode onto
+    one mode gives Pf(A(z)) exact roots at z = +-1, where eq. Pfaffian_der's
+    inverse does not exist; the oracle's unit-circle nodes include z = 1, so
+    it is run on the paper's Chebyshev nodes, which avoid +-1.  Their
+    Vandermonde system amplifies the oracle's own rounding by 1e3 to 1e4 at
+    n = 16 (a few 1e-12 to 1e-10 relative per shadow), so D_w and G_w are held
+    to 1e-9 here; the finite differences check the kernel independently."""
+    w = wl.make("gp", 16, 8, 24, 60, seed=66, shadows="perm")
+    sg, dg, gg, st = gpu_grad(B, w.phi, w.Q, w.bits)
+    so, do, go = oracle.grad(w.phi, w.Q, w.bits, family="chebyshev")
+    assert not st.any()
+    assert np.all(np.abs(sg - so) <= 1e-10 * np.abs(so))
+    ed, eg = close_per_walker(dg, do, 1e-9), close_per_walker(gg, go, 1e-9)
+    print(f"signed permutations: worst D {ed:.2e}, G {eg:.2e}")
+    Qd, bd = torch.from_numpy(w.Q).to(dev()), torch.from_numpy(w.bits.view(np.int64)).to(dev())
+    rng = np.random.default_rng(9)
+    h = 1e-6
+    E = rng.standard_normal((w.n, w.eta)) + 1j * rng.standard_normal((w.n, w.eta))
+    ph = np.stack([w.phi + h * E, w.phi - h * E])
+    sp, _, _ = B.shadow_overlap(torch.from_numpy(ph[0]).to(dev()), Qd, bd)
+    sm, _, _ = B.shadow_overlap(torch.from_numpy(ph[1]).to(dev()), Qd, bd)
+    fd = (sp.cpu().numpy() - sm.cpu().numpy()) / (2 * h)
+    an = np.einsum("wpj,pj->w", dg, E) * sg
+    assert np.all(np.abs(fd - an) <= 1e-7 * np.abs(an)), np.abs(fd - an) / np.abs(an)
+
+
 def test_grad_finite_differences_of_the_gpu_forward(B):
     """Central differences of the HIP forward S_w along Phi_pj (holomorphic
     derivative: a real step h on the complex entry) against D_w S_w."""

@@ -234,24 +234,96 @@ def test_occupied_elimination_growth_and_fallback(B):
     assert np.all(err <= 1e-10 * np.maximum(np.abs(po), 1e-3 * scale)), err / np.maximum(np.abs(po), 1e-3 * scale)
 
 
-@pytest.mark.parametrize("n,eta", [(8, 4), (9, 4)])     # fused pair kernel; two-kernel path
-def test_fallback_queue_overflow_is_reported(B, n, eta):
-    """Walkers whose orbitals are single modes, with the identity shadow and
-    b = 0, make the occupied rows of B exactly zero (every product that could
-    contribute has a zero factor), so every pair meets a zero pivot and needs
-    the full-size path; the queue holds 4096 of the 4800 pairs.  The walkers
-    whose pairs were dropped are flagged; a walker without the flag has every
-    pair exact (the overlap of a pair-preserving shadow is zero)."""
-    W, S = 48, 100
-    rng = np.random.default_rng(5)
+def hf_walkers(rng, W, n, eta):
+    """Walkers whose orbitals are single modes (Hartree-Fock-like)."""
     phi = np.zeros((W, n, eta), complex)
     for w in range(W):
         phi[w, rng.choice(n, eta, replace=False), np.arange(eta)] = 1.0
+    return phi
+
+
+@pytest.mark.parametrize("n,eta", [(8, 4), (9, 4)])     # fused pair kernel; two-kernel path
+def test_fallback_queue_overflow_still_exact(B, n, eta):
+    """Single-mode walkers with the identity shadow and b = 0 make the
+    occupied rows of B exactly zero, so every pair meets a zero pivot and
+    needs the full-size path: 4,800 pairs against a queue of 4,096.  The
+    pairs the queue cannot hold are marked in the pair array and found by
+    the full-size kernel's scan, so every pair is exact (the overlap of a
+    pair-preserving shadow is zero) and no walker is flagged."""
+    W, S = 48, 100
+    phi = hf_walkers(np.random.default_rng(5), W, n, eta)
     Q = np.broadcast_to(np.eye(2 * n), (S, 2 * n, 2 * n)).copy()
     bits = np.zeros(S, np.uint64)
-    sg, pg, st = gpu_overlap(B, phi, Q, bits)
-    lost = (st & B.SO_WSTAT_FALLBACK_LOST) != 0
-    assert lost.any()
-    assert not (st & ~B.SO_WSTAT_FALLBACK_LOST).any()
-    if (~lost).any():
-        assert np.abs(pg[~lost]).max() < 1e-13
+    t = to_dev(phi, Q, bits)
+    out, pairs, st = B.shadow_overlap(*t, return_pairs=True)
+    cnt = B.fallback_count(*t)
+    pg, st = pairs.cpu().numpy(), st.cpu().numpy()
+    print(f"n={n}: {cnt} of {W * S} pairs on the full-size path")
+    assert cnt == W * S
+    assert not st.any()
+    assert np.abs(pg).max() < 1e-13
+
+
+@pytest.mark.parametrize("n,eta", [(8, 4), (9, 4)])
+def test_fallback_overflow_hf_walkers_signed_permutations(B, n, eta):
+    """Single-mode walkers with signed-permutation shadows (the first steps
+    of an AFQMC run on the paper's ensemble): many pairs need the full-size
+    path, more than its queue holds; every pair against the oracle, a few
+    against the closed form."""
+    W, S = 64, 128
+    rng = np.random.default_rng(7 + n)
+    phi = hf_walkers(rng, W, n, eta)
+    Qs, perms, signs = [], [], []
+    for _ in range(S):
+        Q, pm, sg = closed_form.random_signed_permutation(rng, n)
+        Qs.append(Q), perms.append(pm), signs.append(sg)
+    Q = np.array(Qs)
+    bits = wl.even_bits(rng, S, n)
+    t = to_dev(phi, Q, bits)
+    out, pairs, st = B.shadow_overlap(*t, return_pairs=True)
+    cnt = B.fallback_count(*t)
+    sg_, pg, st = out.cpu().numpy(), pairs.cpu().numpy(), st.cpu().numpy()
+    po = oracle.overlap_pairs(phi, Q, bits)
+    print(f"n={n}: {cnt} of {W * S} pairs on the full-size path")
+    assert cnt > 4096
+    assert not st.any()
+    scale = np.abs(po).max()
+    assert np.all(np.abs(pg - po) <= 1e-10 * np.maximum(np.abs(po), 1e-3 * scale))
+    for k in range(6):
+        w_, s_ = int(rng.integers(W)), int(rng.integers(S))
+        ref = closed_form.overlap_pair(phi[w_], perms[s_], signs[s_], int(bits[s_]))
+        assert abs(pg[w_, s_] - ref) <= 1e-10 * max(abs(ref), 1e-3 * scale)
+    so = po.mean(axis=1)
+    assert np.all(np.abs(sg_ - so) <= 1e-10 * np.maximum(np.abs(so), 1e-3 * scale))
+
+
+def test_signed_permutation_paper_workload(B):
+    """The paper's own shadow ensemble at the paper's size: 1024 walkers x
+    10,000 random signed permutations (n = 16, eta = 8).  2,000 sampled pairs
+    against the oracle, 8 against the closed form, and S_w of 8 walkers over
+    all shadows; the count of full-size pairs is reported."""
+    w = wl.config("perm_n16")
+    t = to_dev(w.phi, w.Q, w.bits)
+    print(f"perm_n16: {w.W} x {w.S} pairs", flush=True)
+    out, pairs, st = B.shadow_overlap(*t, return_pairs=True)
+    cnt = B.fallback_count(*t)
+    assert not st.cpu().numpy().any()
+    rng = np.random.default_rng(16)
+    sw, ss = rng.integers(0, w.W, 2000), rng.integers(0, w.S, 2000)
+    pg = pairs[torch.from_numpy(sw).to(dev()), torch.from_numpy(ss).to(dev())].cpu().numpy()
+    sg = out.cpu().numpy()
+    del pairs
+    po = oracle.overlap_pairs(w.phi, w.Q, w.bits, pairs=np.stack([sw, ss], 1))
+    worst = assert_pairs_close(pg, po, what="perm_n16 sampled pairs")
+    for k in range(8):
+        Q = w.Q[ss[k]]
+        perm = np.argmax(np.abs(Q), axis=1)
+        signs = Q[np.arange(Q.shape[0]), perm]
+        ref = closed_form.overlap_pair(w.phi[sw[k]], perm, signs, int(w.bits[ss[k]]))
+        assert abs(pg[k] - ref) <= RTOL * max(abs(ref), 1e-3 * np.median(np.abs(po)))
+    pick = np.arange(8) * 101
+    so = oracle.overlap(w.phi[pick], w.Q, w.bits)
+    assert_walkers_close(sg[pick], so, what="perm_n16 S_w")
+    print(f"perm_n16: worst sampled pair rel err {worst:.2e}; {cnt} of {w.W * w.S} pairs on the full-size path")
+
+

@@ -439,6 +439,33 @@ def test_gradient_finite_differences_and_invariants():
             assert abs(fd - an) <= 1e-7 * abs(an)
 
 
+def test_gradient_signed_permutations_chebyshev_fd():
+    """On the paper's signed-permutation ensemble Pf(A(z)) has exact roots at
+    z = +-1 (modes whose two Majoranas the permutation maps onto one mode), so
+    eq. Pfaffian_der's inverse does not exist at the unit node z = 1.  The
+    gradient on the paper's Chebyshev nodes (never +-1) matches central
+    differences of the overlap; on the unit-circle nodes it fails, either
+    detected (an exactly zero pivot) or silently wrong."""
+    n, eta = 16, 8
+    rng = np.random.default_rng(81)
+    phi = wl.walkers(rng, 2, n, eta)
+    Q = np.array([closed_form.random_signed_permutation(rng, n)[0] for _ in range(12)])
+    bits = wl.even_bits(rng, 12, n)
+    _, Dc, _ = oracle.grad(phi, Q, bits, family="chebyshev")
+    try:
+        _, Du, _ = oracle.grad(phi, Q, bits, family="unit")
+    except np.linalg.LinAlgError:          # an exactly singular node matrix, detected
+        Du = None
+    h = 1e-6
+    E = rng.standard_normal((n, eta)) + 1j * rng.standard_normal((n, eta))
+    pp, pm = phi.copy(), phi.copy()
+    pp[0] += h * E
+    pm[0] -= h * E
+    fd = (np.log(oracle.overlap(pp, Q, bits)[0]) - np.log(oracle.overlap(pm, Q, bits)[0])) / (2 * h)
+    assert abs(fd - np.sum(Dc[0] * E)) <= 1e-7 * abs(fd)
+    assert Du is None or abs(fd - np.sum(Du[0] * E)) > 1e-4 * abs(fd)
+
+
 def test_gradient_brute_force_green():
     """N_pq = 2<0|rho_hat a_p^dag a_q|phi> by dense brute force equals o * G_pq."""
     n, eta = 4, 2
@@ -449,6 +476,36 @@ def test_gradient_brute_force_green():
     N = brute.mixed_one_body(phi[0], Q[0], int(bits[0]))
     Sw, D, G = oracle.grad(phi, Q, bits)
     assert np.abs(N - G[0] * Sw[0]).max() <= 1e-12 * np.abs(N).max()
+
+
+@pytest.mark.parametrize("n,eta", [(4, 2), (5, 2), (6, 4)])
+def test_force_bias_dense_operators(n, eta):
+    """Eq. force_bias, x_bar_gamma = -sqrt(dt) <v_gamma> with
+    v_gamma = i sum_pq L^gamma_pq a_p^dag a_q (eq. cholesky_vec), the mixed
+    expectation <O> = <Psi_T|O|phi>/<Psi_T|phi> taken with dense 2^n
+    operators for a random trial state; force_bias is fed the dense mixed
+    Green's function G_pq = <a_p^dag a_q>.  L is NOT symmetric, so an
+    L_pq / L_qp swap fails, and so do a wrong sign of i or a missing sqrt(dt)."""
+    rng = np.random.default_rng(40 + n)
+    ng, dt = 3, 0.03
+    a = brute.annihilators_dense(n)
+    dim = 1 << n
+    # a random trial state in the eta-particle sector
+    count = np.array([bin(x).count("1") for x in range(dim)])
+    psi = (rng.standard_normal(dim) + 1j * rng.standard_normal(dim)) * (count == eta)
+    phi = wl.walkers(rng, 1, n, eta)[0]
+    v = brute.slater_state(phi)
+    ov = np.vdot(psi, v)
+    G = np.zeros((1, n, n), np.complex128)
+    for p in range(n):
+        for q in range(n):
+            G[0, p, q] = np.vdot(psi, a[p].conj().T @ (a[q] @ v)) / ov
+    L = rng.standard_normal((n * n, ng)) * 0.1          # not symmetrised
+    xb = oracle.force_bias(G, L, dt)
+    for g in range(ng):
+        vg = 1j * sum(L[p * n + q, g] * (a[p].conj().T @ a[q]) for p in range(n) for q in range(n))
+        ref = -np.sqrt(dt) * np.vdot(psi, vg @ v) / ov
+        assert abs(xb[0, g] - ref) <= 1e-12 * abs(ref), (g, xb[0, g], ref)
 
 
 def test_force_bias_definition():
