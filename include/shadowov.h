@@ -147,6 +147,26 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
                          so_c64 *overlap, so_c64 *pair_out, int32_t *status,
                          void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as shadow_overlap (the same kernels, bit for bit),
+ * with the scratch space in a library-owned static device array of
+ * SO_NOALLOC_SCRATCH_BYTES per GPU instead of a caller workspace.  The
+ * caller still passes the inputs and outputs (device pointers, as in
+ * shadow_overlap).  No hipMalloc, hipFree or other allocating call is made;
+ * the first call on a device looks up the array's device address
+ * (hipGetSymbolAddress) and keeps it.  Problems whose workspace
+ * (so_workspace_size with_grad = 0) exceeds the array return
+ * SO_ERR_WORKSPACE before anything is enqueued; e.g. n = 16, eta = 8 fits
+ * about W x S = 256 x 5,000.  Every call on one GPU uses that GPU's one
+ * array, which keeps the last call's contents (the kernels clear what must
+ * start at zero): calls that overlap in time on one GPU, on any streams or
+ * threads, race and must be serialised by the caller. */
+#define SO_NOALLOC_SCRATCH_BYTES (64u << 20)
+so_status shadow_overlap_noalloc(const so_params *p, const so_c64 *phi, int64_t n_walkers,
+                                 const double *Q, const uint64_t *bits, int64_t n_shadows,
+                                 so_c64 *overlap, so_c64 *pair_out, int32_t *status, void *stream);
+
 /* Overlaps and their first derivative (section "Force bias and local
  * energy": d Pf = Pf/2 Tr(A^{-1} dA), eq. Pfaffian_der, applied through
  * A(z) = C_0^(s) + z B and B(Phi)).

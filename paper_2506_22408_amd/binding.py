@@ -67,6 +67,8 @@ def _load():
     lib.so_node_weights.restype = c.c_int
     lib.shadow_overlap.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, P, P, c.c_size_t, P]
     lib.shadow_overlap.restype = c.c_int
+    lib.shadow_overlap_noalloc.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, P, P]
+    lib.shadow_overlap_noalloc.restype = c.c_int
     lib.shadow_overlap_grad.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, P, P, P,
                                         c.c_size_t, P]
     lib.shadow_overlap_grad.restype = c.c_int
@@ -223,6 +225,31 @@ def shadow_overlap(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_
     if st != SO_OK:
         raise ShadowOvError(st, "shadow_overlap")
     return out, pairs, status
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # SO_NOALLOC_SCRATCH_BYTES
+
+
+def shadow_overlap_noalloc(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, overlap: torch.Tensor,
+                           status: torch.Tensor, pairs: torch.Tensor | None = None, *, n_nodes: int = 0,
+                           nodes: str = "unit", precision: str = "fp64", paper_norm: bool = False,
+                           log_output: bool = False) -> None:
+    """shadow_overlap on the library's own scratch array: the caller passes
+    every output (overlap complex128 [W], status int32 [W], optionally pairs
+    [W, S]); nothing is allocated."""
+    W, n, eta, S = _check_inputs(phi, Q, bits)
+    for t, shape, dt in ((overlap, (W,), torch.complex128), (status, (W,), torch.int32)):
+        if t.shape != shape or t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("overlap must be complex128 [W] and status int32 [W], contiguous, on the device")
+    if pairs is not None and (pairs.shape != (W, S) or pairs.dtype != torch.complex128 or not pairs.is_contiguous()):
+        raise ValueError("pairs must be complex128 [W, S], contiguous")
+    p = make_params(n, eta, n_nodes, nodes, precision, paper_norm, log_output)
+    stream = torch.cuda.current_stream(phi.device).cuda_stream
+    st = lib.shadow_overlap_noalloc(ctypes.byref(p), _dev_ptr(phi.contiguous()), W, _dev_ptr(Q.contiguous()),
+                                    _dev_ptr(bits.contiguous()), S, _dev_ptr(overlap), _dev_ptr(pairs),
+                                    _dev_ptr(status), ctypes.c_void_p(stream))
+    if st != SO_OK:
+        raise ShadowOvError(st, "shadow_overlap_noalloc")
 
 
 def fallback_count(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_nodes: int = 0,

@@ -32,6 +32,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "so_common.h"
 #include "so_prep.h"
@@ -887,6 +888,39 @@ size_t vce_extra_bytes(int64_t W, int n, int eta) {
 }  // namespace
 
 // ==========================================================================
+// Library-owned scratch of shadow_overlap_noalloc: one static device array
+// per GPU, held until the process ends.  Host code never uses the array's
+// name as an address (on the host it is only a stand-in for the symbol): the
+// device address comes from hipGetSymbolAddress, once per device with that
+// device current, and is kept per device.
+// ==========================================================================
+__device__ __align__(256) unsigned char scratch[SO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of this device's scratch array (set-up on the first call)
+hipError_t scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+}  // namespace
+
+// ==========================================================================
 // C ABI
 // ==========================================================================
 extern "C" {
@@ -941,6 +975,22 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
     }
     if (enqueue_finish(P, st) != hipSuccess) return SO_ERR_HIP;
     return SO_OK;
+}
+
+so_status shadow_overlap_noalloc(const so_params *p, const so_c64 *phi, int64_t n_walkers, const double *Q,
+                                 const uint64_t *bits, int64_t n_shadows, so_c64 *overlap, so_c64 *pair_out,
+                                 int32_t *status, void *stream) {
+    size_t need = 0;
+    const so_status sv = so_workspace_size(p, n_walkers, n_shadows, 0, &need);
+    if (sv != SO_OK) return sv;
+    if (need > (size_t)SO_NOALLOC_SCRATCH_BYTES) return SO_ERR_WORKSPACE;
+    void *ptr = nullptr;
+    if (scratch_address(&ptr) != hipSuccess) return SO_ERR_HIP;
+    // the same kernels as shadow_overlap, on the scratch array: every region
+    // that must start at zero (the queue counter) or hold statuses is written
+    // by the kernels themselves, so no memset is needed
+    return shadow_overlap(p, phi, n_walkers, Q, bits, n_shadows, overlap, pair_out, status, ptr,
+                          (size_t)SO_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_walkers, const double *Q,
