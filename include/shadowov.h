@@ -187,10 +187,11 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
 
 /* One problem of a batch: the arguments of shadow_overlap, plus two tuning
  * knobs for problems on the fused pair kernel (n - eta even, 2..12):
- *   shadows_per_item  shadows per work item of the persistent kernel
- *                     (rounded up to a multiple of the node batch 64/(ne+1));
- *                     0 = library default
- *   waves_per_cu      persistent waves per compute unit; 0 = default
+ *   shadows_per_item  shadows per work item (one workgroup) of the batch
+ *                     launch (rounded up to a multiple of the node batch
+ *                     64/(ne+1)); 0 = library default
+ *   waves_per_cu      reserved (the hardware dispatcher schedules the items);
+ *                     so_autotune writes 0
  * so_autotune fills both. */
 typedef struct {
     so_params params;
@@ -211,22 +212,24 @@ so_status so_batch_workspace_size(const so_problem *probs, int n_probs, size_t *
 
 /* Several independent problems -- e.g. walker and shadow sets of several
  * geometries with different orbital counts -- in one call: the overlaps of
- * shadow_overlap for each, bit for bit the same values.  Problems on the
- * fused pair kernel share persistent launches per kernel class (same MFMA
- * tile count and n - eta), whose work items (walker, shadow range) are taken
- * from a queue in longest-processing-time order; the other problems use the
- * two-kernel path.  Everything is enqueued on `stream` with no allocation,
- * no memset and no host synchronisation, so the call may be captured into a
- * hipGraph and replayed (the workspace and outputs must then stay fixed). */
+ * shadow_overlap for each, bit for bit the same values.  All problems on the
+ * fused pair kernel with one formation precision share ONE launch, whatever
+ * their (n, eta): its workgroups take work items (walker, shadow range) of
+ * every problem, the costliest problem first, with the items of walkers
+ * w = x (mod 8) on XCD x of the MI355X so that each XCD keeps its walkers'
+ * matrices in its L2.  Problems of other shapes use the two-kernel path
+ * inside the same call.  Everything is enqueued on `stream` with no
+ * allocation, no memset and no host synchronisation, so the call may be
+ * captured into a hipGraph and replayed (the workspace and outputs must then
+ * stay fixed). */
 so_status shadow_overlap_batched(const so_problem *probs, int n_probs, void *workspace, size_t workspace_bytes,
                                  void *stream);
 
-/* Autotuner: times the persistent fused kernel of this problem on a sample
- * of its own inputs (about 2^21 pairs) over shadows_per_item in {1, 2, 4, 8}
- * node batches and waves_per_cu in {4, 8, 16}, and writes the fastest pair
- * into *prob (zeros for problems on the two-kernel path).  Synchronises the
- * stream (not capturable); the caller's outputs are not written.  Workspace:
- * so_batch_workspace_size(prob, 1). */
+/* Autotuner: times the batch launch of this problem alone on a sample of its
+ * own inputs (about 2^21 pairs) over shadows_per_item in {1, 2, 4, 8, 16}
+ * node batches, and writes the fastest into *prob (zeros for problems on the
+ * two-kernel path).  Synchronises the stream (not capturable); the caller's
+ * outputs are not written.  Workspace: so_batch_workspace_size(prob, 1). */
 so_status so_autotune(so_problem *prob, void *workspace, size_t workspace_bytes, void *stream);
 
 /* One-particle reduced density matrix from the shadows (Supp. "Reduced

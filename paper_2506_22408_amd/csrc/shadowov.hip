@@ -20,7 +20,7 @@
 //                   elimination of the occupied indices: S_ws and Pf(B_OO)
 //                   (so_form.h)
 //     k_nodes       node Pfaffians Pf(s_k S + c_k J), weighted sum (so_nodes.h)
-//   (shadow_overlap_batched: k_pair_persistent per kernel class, so_batch.h)
+//   (shadow_overlap_batched: one k_pair_batch launch for all fused problems, so_batch.h)
 //   k_fallback      full-size path for the rare pairs flagged above (so_fallback.h)
 //   k_reduce        S_w = (1/S) sum_s o_ws, fixed order (deterministic)
 // and for the derivative (shadow_overlap_grad), after the two prep kernels:
@@ -649,7 +649,7 @@ hipError_t enqueue_finish(const ProbPlan &P, hipStream_t st) {
     return hipGetLastError();
 }
 
-// ---- batches: persistent fused launches, LPT order, tuning knobs
+// ---- batches: one fused launch, XCD-aware LPT order, tuning knobs
 constexpr int kBatchMax = 16;
 constexpr int kDefaultWavesPerCU = 8;
 
@@ -682,41 +682,54 @@ double pair_cost(int n, int eta) {
     return 16.0 * n * n * m + 8.0 * n * m * m + 8.0 * (n * n * (n + 2 * ne)) + (ne + 1) * 8.0 * ne * ne * ne;
 }
 
-template <int T, int NE, bool MIX>
-hipError_t launch_persistent_tn(const PairJobs &J, int grid, size_t lds, uint32_t *counter, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counter);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pair_persistent<T, NE, MIX>), dim3((unsigned)grid), dim3(64), lds, st, J, counter);
+#ifndef SO_BATCH_ROUNDS
+#define SO_BATCH_ROUNDS 1
+#endif
+constexpr int kBatchRounds = SO_BATCH_ROUNDS;   // rounds of the batch queues (1: LPT order)
+
+// device region of one batch launch: the job table and its header
+struct BatchRegion {
+    BatchJob *jobs;
+    BatchHdr *hdr;
+};
+size_t batch_region_bytes() {
+    return align_up((size_t)SO_BATCH_MAXJOBS * sizeof(BatchJob)) + align_up(sizeof(BatchHdr));
+}
+BatchRegion batch_region(char *base) {
+    BatchRegion r;
+    r.jobs = reinterpret_cast<BatchJob *>(base);
+    r.hdr = reinterpret_cast<BatchHdr *>(base + align_up((size_t)SO_BATCH_MAXJOBS * sizeof(BatchJob)));
+    return r;
+}
+
+template <int LEVEL>
+hipError_t launch_batch_t(bool mix, int64_t grid, size_t lds, const BatchRegion &rg, hipStream_t st) {
+    if (mix)
+        hipLaunchKernelGGL((k_pair_batch<LEVEL, true>), dim3((unsigned)grid), dim3(64), lds, st, rg.jobs, rg.hdr);
+    else
+        hipLaunchKernelGGL((k_pair_batch<LEVEL, false>), dim3((unsigned)grid), dim3(64), lds, st, rg.jobs, rg.hdr);
     return hipGetLastError();
 }
 
-hipError_t launch_persistent(int T, int NE, bool mix, const PairJobs &J, int grid, size_t lds, uint32_t *counter,
-                             hipStream_t st) {
-    switch (T * 32 + NE * 2 + (mix ? 1 : 0)) {
-#define SO_PCASE(TT, NN)                                                                                  \
-    case TT * 32 + NN * 2: return launch_persistent_tn<TT, NN, false>(J, grid, lds, counter, st); \
-    case TT * 32 + NN * 2 + 1: return launch_persistent_tn<TT, NN, true>(J, grid, lds, counter, st);
-        SO_PCASE(1, 2) SO_PCASE(1, 4) SO_PCASE(1, 6) SO_PCASE(1, 8)
-        SO_PCASE(2, 2) SO_PCASE(2, 4) SO_PCASE(2, 6) SO_PCASE(2, 8)
-        SO_PCASE(3, 2) SO_PCASE(3, 4) SO_PCASE(3, 6) SO_PCASE(3, 8)
-        SO_PCASE(2, 10) SO_PCASE(2, 12) SO_PCASE(3, 10) SO_PCASE(3, 12)
-#undef SO_PCASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-// the jobs of one persistent launch: plans ix[0..nj) (one kernel class, in
-// LPT order), shadows [0, S_limit) of each (S_limit <= 0: all)
-PairJobs make_jobs(const ProbPlan *plans, const so_problem *probs, const int *ix, int nj, int64_t S_limit) {
-    PairJobs J;
-    std::memset(&J, 0, sizeof(J));
-    J.njobs = nj;
-    int64_t item = 0;
+// One fused launch over the problems ix[0..nj) (one formation
+// precision; ix in longest-processing-time order), shadows [0, S_limit) of
+// each (S_limit <= 0: all).  The job table and the header are written by
+// kernels, so the sequence can be captured into a graph.
+hipError_t launch_batch(const ProbPlan *plans, const so_problem *probs, const int *ix, int nj, int64_t S_limit,
+                        int waves_per_cu, int rounds, const BatchRegion &rg, hipStream_t st) {
+    BatchHdr hdr;
+    std::memset(&hdr, 0, sizeof(hdr));
+    hdr.njobs = nj;
+    int level = 0;
+    size_t lds = 0;
+    int64_t items = 0, pairs = 0;
+    if (rounds < 1) rounds = 1;
     for (int k = 0; k < nj; ++k) {
         const ProbPlan &P = plans[ix[k]];
-        PairJob &jb = J.job[k];
+        BatchJob jb;
+        std::memset(&jb, 0, sizeof(jb));
         const int64_t S = (S_limit > 0 && S_limit < P.S) ? S_limit : P.S;
+        const int T = so_tiles(P.n), NE = P.n - P.eta;
         jb.Xa = P.Xf;
         jb.Ca = P.Cf;
         jb.pairs = P.pairs;
@@ -728,34 +741,45 @@ PairJobs make_jobs(const ProbPlan *plans, const so_problem *probs, const int *ix
         jb.n = P.n;
         jb.eta = P.eta;
         jb.W = (int)P.W;
-        jb.spw = item_shadows(probs[ix[k]], P.n - P.eta);
-        jb.item0 = item;
-        jb.nitems = P.W * ((S + jb.spw - 1) / jb.spw);
-        item += jb.nitems;
-        for (int j = 0; j < P.tab.Ke; ++j) { J.tab[k].e[j] = P.tab.e[j]; J.tab[k].v[j] = P.tab.v[j]; }
-    }
-    J.total = item;
-    return J;
-}
-
-hipError_t launch_jobs(const ProbPlan *plans, const so_problem *probs, const int *ix, int nj, int64_t S_limit,
-                       int waves_per_cu, uint32_t *counter, hipStream_t st) {
-    const ProbPlan &P0 = plans[ix[0]];
-    const int T = so_tiles(P0.n), NE = P0.n - P0.eta;
-    const PairJobs J = make_jobs(plans, probs, ix, nj, S_limit);
-    size_t lds = 0;
-    for (int k = 0; k < nj; ++k) {
-        const size_t b = pair_lds_bytes(T, plans[ix[k]].n, NE);
+        jb.spw = item_shadows(probs[ix[k]], NE);
+        jb.cls = 16 * T + NE;
+        const int64_t nY = (S + jb.spw - 1) / jb.spw;
+        for (int x = 0; x < SO_BATCH_XCD; ++x) {
+            const int64_t Wx = (P.W - x + SO_BATCH_XCD - 1) / SO_BATCH_XCD;
+            jb.len[x] = Wx > 0 ? Wx * nY : 0;
+            jb.per_round[x] = (jb.len[x] + rounds - 1) / rounds;
+            hdr.round_len[x] += jb.per_round[x];
+            items += jb.len[x];
+        }
+        for (int j = 0; j < P.tab.Ke; ++j) { jb.tab.e[j] = P.tab.e[j]; jb.tab.v[j] = P.tab.v[j]; }
+        hipLaunchKernelGGL(k_batch_setup, dim3(1), dim3(64), 0, st, jb, rg.jobs + k);
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+        const int lv = pair_class_level(T, NE, P.mix);
+        if (lv > level) level = lv;
+        const size_t b = pair_lds_bytes(T, P.n, NE);
         if (b > lds) lds = b;
+        pairs += P.W * S;
     }
-    int64_t grid = (int64_t)device_cus() * (waves_per_cu > 0 ? waves_per_cu : kDefaultWavesPerCU);
-    if (grid > J.total) grid = J.total;
-    if (grid < 1) grid = 1;
-    int64_t pairs = 0;
-    for (int k = 0; k < nj; ++k) pairs += plans[ix[k]].W * plans[ix[k]].S;
+    int64_t qmax = 0;
+    for (int x = 0; x < SO_BATCH_XCD; ++x) {
+        hdr.qlen[x] = (int64_t)rounds * hdr.round_len[x];
+        if (hdr.qlen[x] > qmax) qmax = hdr.qlen[x];
+    }
+    (void)items;
+    (void)waves_per_cu;
+    const int64_t grid = (int64_t)SO_BATCH_XCD * qmax;
+    if (grid < 1 || grid > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_header, dim3(1), dim3(64), 0, st, hdr, rg.hdr);
+    if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     hipEvent_t ea = nullptr;
     hipError_t e = prof_begin(st, &ea);
-    if (e == hipSuccess) e = launch_persistent(T, NE, P0.mix, J, (int)grid, lds, counter, st);
+    if (e != hipSuccess) return e;
+    const bool mix = plans[ix[0]].mix;
+    switch (level) {
+        case 0: e = launch_batch_t<0>(mix, grid, lds, rg, st); break;
+        case 1: e = launch_batch_t<1>(mix, grid, lds, rg, st); break;
+        default: e = launch_batch_t<2>(mix, grid, lds, rg, st); break;
+    }
     if (e == hipSuccess) e = prof_end(st, ea, PROF_PAIR, pairs);
     return e;
 }
@@ -768,8 +792,8 @@ size_t batch_layout(const so_problem *probs, int n_probs, size_t *offs) {
                                      probs[k].n_shadows, false, probs[k].params.precision == SO_PREC_MIXED)
                              .total);
     }
-    offs[n_probs] = o;                                   // launch counters
-    return align_up(o + (size_t)kBatchMax * sizeof(uint32_t));
+    offs[n_probs] = o;                                   // two launch regions (FP64, mixed)
+    return o + 2 * batch_region_bytes();
 }
 
 bool problem_ok(const so_problem &pr) {
@@ -1264,7 +1288,6 @@ so_status shadow_overlap_batched(const so_problem *probs, int n_probs, void *wor
     size_t offs[kBatchMax + 1];
     batch_layout(probs, n_probs, offs);
     char *ws = static_cast<char *>(workspace);
-    uint32_t *counters = reinterpret_cast<uint32_t *>(ws + offs[n_probs]);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     ProbPlan plans[kBatchMax];
     for (int k = 0; k < n_probs; ++k) {
@@ -1275,34 +1298,27 @@ so_status shadow_overlap_batched(const so_problem *probs, int n_probs, void *wor
     }
     for (int k = 0; k < n_probs; ++k)
         if (enqueue_prep(plans[k], st) != hipSuccess) return SO_ERR_HIP;
-    // fused problems in longest-processing-time order, grouped by kernel class
+    // fused problems in longest-processing-time order, one launch
+    // per formation precision
     int order[kBatchMax], nf = 0;
     double cost[kBatchMax];
     for (int k = 0; k < n_probs; ++k)
         if (fused_ok(plans[k].n, plans[k].eta)) {
-            cost[k] = pair_cost(plans[k].n, plans[k].eta) * item_shadows(probs[k], plans[k].n - plans[k].eta);
+            cost[k] = pair_cost(plans[k].n, plans[k].eta) * (double)plans[k].W * (double)plans[k].S;
             order[nf++] = k;
         }
     for (int a = 1; a < nf; ++a)
         for (int b = a; b > 0 && cost[order[b]] > cost[order[b - 1]]; --b) std::swap(order[b], order[b - 1]);
-    bool used[kBatchMax] = {false};
-    int launch = 0;
-    for (int a = 0; a < nf; ++a) {
-        if (used[a]) continue;
-        const int ka = order[a];
-        const int T = so_tiles(plans[ka].n), NE = plans[ka].n - plans[ka].eta;
-        int ix[SO_JOBS_PER_LAUNCH], nj = 0;
-        for (int b = a; b < nf && nj < SO_JOBS_PER_LAUNCH; ++b) {
-            const int kb = order[b];
-            if (used[b] || so_tiles(plans[kb].n) != T || plans[kb].n - plans[kb].eta != NE ||
-                plans[kb].mix != plans[ka].mix)
-                continue;
-            used[b] = true;
-            ix[nj++] = kb;
-        }
-        if (launch_jobs(plans, probs, ix, nj, 0, probs[ix[0]].waves_per_cu, counters + launch, st) != hipSuccess)
-            return SO_ERR_HIP;
-        ++launch;
+    for (int prec = 0; prec < 2; ++prec) {
+        int ix[kBatchMax], nj = 0, wpc = 0;
+        for (int a = 0; a < nf; ++a)
+            if (plans[order[a]].mix == (prec == 1)) {
+                ix[nj++] = order[a];
+                if (probs[order[a]].waves_per_cu > wpc) wpc = probs[order[a]].waves_per_cu;
+            }
+        if (!nj) continue;
+        const BatchRegion rg = batch_region(ws + offs[n_probs] + (size_t)prec * batch_region_bytes());
+        if (launch_batch(plans, probs, ix, nj, 0, wpc, kBatchRounds, rg, st) != hipSuccess) return SO_ERR_HIP;
     }
     for (int k = 0; k < n_probs; ++k)
         if (!fused_ok(plans[k].n, plans[k].eta) && enqueue_two_kernel(plans[k], st) != hipSuccess) return SO_ERR_HIP;
@@ -1320,7 +1336,7 @@ so_status so_autotune(so_problem *prob, void *workspace, size_t workspace_bytes,
     size_t offs[2];
     batch_layout(prob, 1, offs);
     char *ws = static_cast<char *>(workspace);
-    uint32_t *counter = reinterpret_cast<uint32_t *>(ws + offs[1]);
+    const BatchRegion rg = batch_region(ws + offs[1]);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     ProbPlan P;
     // pair values go to the workspace: the caller's outputs are not touched
@@ -1338,36 +1354,33 @@ so_status so_autotune(so_problem *prob, void *workspace, size_t workspace_bytes,
     int64_t Ss = ((int64_t)1 << 21) / P.W;
     if (Ss < 8 * nb) Ss = 8 * nb;
     if (Ss > P.S) Ss = P.S;
-    const int mults[4] = {1, 2, 4, 8};
-    const int wpcs[3] = {4, 8, 16};
+    const int mults[5] = {1, 2, 4, 8, 16};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return SO_ERR_HIP;
     float best = 1e30f;
-    int best_spw = nb * kPairBatchesPerWave, best_wpc = kDefaultWavesPerCU;
+    int best_spw = nb * kPairBatchesPerWave;
     so_problem trial = *prob;
     const int ix[1] = {0};
-    for (int mi = 0; mi < 4; ++mi)
-        for (int wi = 0; wi < 3; ++wi) {
-            trial.shadows_per_item = nb * mults[mi];
-            float tmin = 1e30f;
-            for (int rep = 0; rep < 2; ++rep) {
-                if (hipEventRecord(e0, st) != hipSuccess) return SO_ERR_HIP;
-                if (launch_jobs(&P, &trial, ix, 1, Ss, wpcs[wi], counter, st) != hipSuccess) return SO_ERR_HIP;
-                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return SO_ERR_HIP;
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return SO_ERR_HIP;
-                if (ms < tmin) tmin = ms;
-            }
-            if (tmin < best) {
-                best = tmin;
-                best_spw = trial.shadows_per_item;
-                best_wpc = wpcs[wi];
-            }
+    for (int mi = 0; mi < 5; ++mi) {
+        trial.shadows_per_item = nb * mults[mi];
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) return SO_ERR_HIP;
+            if (launch_batch(&P, &trial, ix, 1, Ss, 0, 1, rg, st) != hipSuccess) return SO_ERR_HIP;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return SO_ERR_HIP;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return SO_ERR_HIP;
+            if (ms < tmin) tmin = ms;
         }
+        if (tmin < best) {
+            best = tmin;
+            best_spw = trial.shadows_per_item;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     prob->shadows_per_item = best_spw;
-    prob->waves_per_cu = best_wpc;
+    prob->waves_per_cu = 0;
     return SO_OK;
 }
 

@@ -231,7 +231,7 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
     const int64_t s1 = min(S_total, s0 + spw);
     for (int64_t s = s0; s < s1; ++s) {
         const double2 *Cs = Ca + (size_t)s * MAT2;
-        pair_formation<T, false>(Xw, Cs, RP, l);
+        pair_formation<T, false>(Xw, Cs, RP, l, LDP);
 
         // ---------------- B (m x m), then R = rows K of Z
         double bmax = 0.0;

@@ -100,21 +100,20 @@ __device__ __forceinline__ double2 pf_lane_from(double2 (&A)[N][N]) {
 }
 
 // ---- formation: P = Xall C'_s Xall^T into LDS -------------------------------
-// Pl is (DP + 1) x LDP doubles, row-major; both triangles of P are written and
-// row and column DP are zeroed (an empty orbital's missing imaginary part
-// points there).  Ends with a barrier.
+// Pl is ld x ld doubles, row-major, for ld - 1 >= d = 2n (the rows and columns
+// of P beyond d are zero, since Xall is zero-padded, and are not stored); both
+// triangles of P are written and row and column ld - 1 are zeroed (an empty
+// orbital's missing imaginary part points there).  Ends with a barrier.
 //
 // MIX = false: FP64 operands (double2 pairs in A order) on
 // v_mfma_f64_16x16x4f64.  MIX = true: single-precision operands (float4
 // quads, C' rows in the order sig16) on v_mfma_f32_16x16x4f32 with
 // single-precision accumulation; P is widened to FP64 when it is stored and
 // everything after the formation runs in FP64.
-// With Ul (FP64 only) U = C' Xall^T is kept as well: Ul[r LDP + c] = U[r][c]
-// for r, c < DP (LDP = DP + 1 columns, column DP left to the caller).
 template <int T, bool MIX>
 __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, const void *__restrict__ Cv,
-                                               double *Pl, int l, double *Ul = nullptr) {
-    constexpr int KK = 4 * T, DP = 16 * T, LDP = DP + 1;
+                                               double *Pl, int l, int ld) {
+    constexpr int KK = 4 * T;
     using Op = typename std::conditional<MIX, float, double>::type;
     using Vec = typename std::conditional<MIX, float4, double2>::type;
     using Acc = typename std::conditional<MIX, so_f4, so_d4>::type;
@@ -126,18 +125,7 @@ __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, cons
     Acc P[T][T], U[T][T];
     form_p<T>(xa, ca, P, U);
     __syncthreads();   // region A is free
-    if constexpr (!MIX) {
-        if (Ul) {
-            // register r of U's tile (I, J) holds U[16 I + 4 r + l/16][16 J + l%16]
-#pragma unroll
-            for (int I = 0; I < T; ++I)
-#pragma unroll
-                for (int J = 0; J < T; ++J)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        Ul[(16 * I + 4 * r + (l >> 4)) * LDP + 16 * J + (l & 15)] = U[I][J][r];
-        }
-    }
+    const int z = ld - 1;   // the zero row and column
 #pragma unroll
     for (int I = 0; I < T; ++I)
 #pragma unroll
@@ -146,13 +134,15 @@ __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, cons
             for (int r = 0; r < 4; ++r) {
                 const int a = p_row(P[I][J], I, r, l), bcol = 16 * J + (l & 15);
                 const double v = (double)P[I][J][r];
-                Pl[a * LDP + bcol] = v;
-                if (J > I) Pl[bcol * LDP + a] = -v;   // P is antisymmetric
+                if (a < z && bcol < z) {
+                    Pl[a * ld + bcol] = v;
+                    if (J > I) Pl[bcol * ld + a] = -v;   // P is antisymmetric
+                }
             }
-    // row and column DP are zero (R overlays them, so they are rewritten per pair)
-    for (int c = l; c <= DP; c += 64) {
-        Pl[DP * LDP + c] = 0.0;
-        Pl[c * LDP + DP] = 0.0;
+    // row and column z are zero (R overlays them, so they are rewritten per pair)
+    for (int c = l; c <= z; c += 64) {
+        Pl[z * ld + c] = 0.0;
+        Pl[c * ld + z] = 0.0;
     }
     __syncthreads();
 }
@@ -288,13 +278,13 @@ __device__ __forceinline__ double2 pencil_pf_row(const double2 *slot, double2 c,
 // of 5, which measured 1.19x faster than a batch of 4 (1.24x at n = 20).
 __host__ __device__ constexpr int pair_node_batch(int ne) { return ne <= 8 ? 64 / (ne + 1) : SO_ROW_NODE_BATCH; }
 
-// LDS per wave: region A = max(P ((DP+1) x (DP+1) f64), R (n x (n + 2 NE) c128),
+// LDS per wave: region A = max(P ((2n+1) x (2n+1) f64), R (n x (n + 2 NE) c128),
 // T (NE (2NE - 1) c128), node values), then the batch: NB slots of
 // 3 NE (NE-1)/2 + 1 complex (M0, M1, M2 upper triangles, Pf(B_KK)).
 __host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
-    const int DP = 16 * T;
+    (void)T;
     const int NB = pair_node_batch(NE);
-    size_t a = (size_t)(DP + 1) * (DP + 1) * sizeof(double);
+    size_t a = (size_t)(2 * n + 1) * (2 * n + 1) * sizeof(double);
     const size_t r = (size_t)n * (n + 2 * NE) * sizeof(double2);
     const size_t t = (size_t)NE * (2 * NE - 1) * sizeof(double2);
     const size_t v = (size_t)64 * sizeof(double2);
@@ -316,7 +306,7 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
                                            double2 *__restrict__ pairs, so_u64 *__restrict__ fb_count,
                                            int64_t *__restrict__ fb_list, int64_t fb_cap,
                                            int32_t *__restrict__ wstat, int w, int64_t sb0, int64_t sb1) {
-    constexpr int KK = 4 * T, KH = 2 * T, DP = 16 * T, LDP = DP + 1;
+    constexpr int DP = 16 * T;
     constexpr size_t MATB = (size_t)DP * DP * (MIX ? sizeof(float) : sizeof(double));   // bytes per matrix
     constexpr int KE = NE + 1;
     constexpr int NB = pair_node_batch(NE);
@@ -329,7 +319,8 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
     double2 *Rl = reinterpret_cast<double2 *>(lds);
     double2 *Tl = reinterpret_cast<double2 *>(lds);
     double2 *Vl = reinterpret_cast<double2 *>(lds);
-    size_t abytes = (size_t)(DP + 1) * LDP * sizeof(double);
+    const int LDP = 2 * n + 1;   // P is (2n + 1) x (2n + 1); row and column 2n are zero
+    size_t abytes = (size_t)LDP * LDP * sizeof(double);
     {
         const size_t r = (size_t)n * (n + 2 * NE) * sizeof(double2);
         const size_t t = (size_t)NT2 * sizeof(double2);
@@ -340,7 +331,11 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
     }
     double2 *Bt = reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) + abytes);   // batch slots
 
-    const int l = threadIdx.x;
+    // the lane index through an opaque move: nothing derived from it can be
+    // hoisted out of a caller's loop over work items (where it would stay live
+    // beside the other kernel classes' state in the batch kernel)
+    int l = threadIdx.x;
+    asm volatile("" : "+v"(l));
     const int WR = n + 2 * NE;              // columns of R: K (n), L (NE), E (NE)
 
     // this lane's trailing entries (a < b) of the 2NE x 2NE block
@@ -357,9 +352,9 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
     const char *Xw = static_cast<const char *>(Xa) + (size_t)w * MATB;
     auto Pget = [&](int a, int b) -> double { return Pl[a * LDP + b]; };
     // Xall rows of the real and imaginary parts of stored row i; an empty
-    // orbital's row is real, and its imaginary part points at the zero row DP
+    // orbital's row is real, and its imaginary part points at the zero row 2n
     auto rre = [&](int i) -> int { return i < eta ? i : eta + i; };
-    auto rim = [&](int i) -> int { return i < eta ? eta + i : DP; };
+    auto rim = [&](int i) -> int { return i < eta ? eta + i : LDP - 1; };
     auto Bget = [&](int i, int j) -> double2 {
         const int ir = rre(i) * LDP, ii = rim(i) * LDP, jr = rre(j), ji = rim(j);
         return c_make(Pl[ir + jr] - Pl[ii + ji], Pl[ir + ji] + Pl[ii + jr]);
@@ -370,7 +365,7 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
         for (int b = 0; b < nb; ++b) {
             const int64_t s = bs + b;
             // ---------------- formation: P = Xall C' Xall^T
-            pair_formation<T, MIX>(Xw, static_cast<const char *>(Ca) + (size_t)s * MATB, Pl, l);
+            pair_formation<T, MIX>(Xw, static_cast<const char *>(Ca) + (size_t)s * MATB, Pl, l, LDP);
 
             // ---------------- R = rows K of Z, trailing T = [[B_LL, 0], [0, 0]]
             constexpr int RPL = (8 * T * (8 * T + NE) + 63) / 64;   // B entries of R per lane (n <= 8 T)
@@ -512,11 +507,32 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
     }
 }
 
+// Register levels of the kernel classes (T, NE, formation precision), from
+// the VGPRs each class's kernel needs in the compiler's resource report:
+// level 0 fits 168 (three waves per SIMD), level 1 fits 256 without spills
+// when alone (two waves per SIMD), level 2 is the rest.  The kernels of level
+// 0 are built for three waves per SIMD; the batch kernel of level L holds
+// the classes of level <= L.
+__host__ __device__ constexpr int pair_class_level(int T, int NE, bool mix) {
+    if (T == 1) return NE <= 6 ? 0 : 1;
+    if (T == 2) {
+        if (NE <= 6) return 0;
+        if (NE == 10) return mix ? 0 : 1;
+        return 1;
+    }
+    // T == 3: the FP64 classes other than ne = 10 are kept out of level 1,
+    // whose batch kernel then holds the uneven reaction-path set without more
+    // spills
+    if (mix) return NE <= 4 ? 0 : 1;
+    return NE == 10 ? 1 : 2;
+}
+
 // grid (W, ceil(S_total / spw)) from shadow group sy0, one wave per block;
-// spw is a multiple of pair_node_batch(NE).  At least two waves per SIMD: the
-// three-tile instances would otherwise take more than 256 registers.
+// spw is a multiple of pair_node_batch(NE).  Three waves per SIMD for the
+// classes of level 0, two otherwise (the three-tile instances would take
+// more than 256 registers).
 template <int T, int NE, bool MIX>
-__global__ __launch_bounds__(64, 2) void k_pair(int n, int eta, const void *__restrict__ Xa,
+__global__ __launch_bounds__(64, pair_class_level(T, NE, MIX) == 0 ? 3 : 2) void k_pair(int n, int eta, const void *__restrict__ Xa,
                                              const void *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
                                              RedTab tab, double2 *__restrict__ pairs,
                                              so_u64 *__restrict__ fb_count, int64_t *__restrict__ fb_list,
