@@ -333,6 +333,8 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
  *   numerator [n_walkers] complex128 out or NULL: the shadow estimate of
  *            <Psi_T|H|phi_w>, N_w = (1/S) sum_s e_ws
  *   energy   [n_walkers] complex128 out or NULL: N_w / S_w
+ *   pair_overlap, pair_numerator  [n_walkers][n_shadows] complex128 out or
+ *            NULL: the single-shadow terms o_ws and e_ws of those averages
  *   status   [n_walkers] int32 out or NULL: SO_WSTAT_RANK (S_w, N_w, E_w
  *            are then NaN) / _NONFINITE, and SO_WSTAT_SINGULAR if a node
  *            matrix of some pair was exactly singular (the energy of that
@@ -344,8 +346,9 @@ so_status so_local_energy_workspace_size(const so_params *p, int64_t n_walkers, 
                                          size_t *bytes);
 so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walkers, const double *Q,
                           const uint64_t *bits, int64_t n_shadows, const so_c64 *t, const double *L, int n_gamma,
-                          so_c64 *overlap, so_c64 *numerator, so_c64 *energy, int32_t *status, void *workspace,
-                          size_t workspace_bytes, void *stream);
+                          so_c64 *overlap, so_c64 *numerator, so_c64 *energy, so_c64 *pair_overlap,
+                          so_c64 *pair_numerator, int32_t *status, void *workspace, size_t workspace_bytes,
+                          void *stream);
 
 /* Force bias of every walker ("Force bias and local energy", eq. force_bias,
  * with the Cholesky vectors L^gamma of eq. cholesky_vec):

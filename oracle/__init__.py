@@ -34,17 +34,23 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "shadow_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 selects a build with AddressSanitizer and UBSan (run the
+# process with the gcc ASan runtime preloaded; tests/test_sanitizers.py does)
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_asan.so" if _SANITIZE else "liboracle.so")
 _lib = None
 
 NODE_FAMILIES = ("unit", "chebyshev")
 
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with gcc (plain -O2, no fast-math)."""
+    """Compile ``liboracle.so`` with gcc (plain -O2, no fast-math), or the
+    sanitized ``liboracle_asan.so`` when ORACLE_SANITIZE=1."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-std=c99", "-O2", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+        opt = (["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                "-fno-omit-frame-pointer"] if _SANITIZE else ["-O2"])
+        cmd = ["gcc", "-std=c99", *opt, "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
                _SRC, "-o", tmp, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)

@@ -97,7 +97,7 @@ def _load():
                                                    c.POINTER(c.c_size_t)]
     lib.so_local_energy_workspace_size.restype = c.c_int
     lib.so_local_energy.argtypes = [c.POINTER(SoParams), P, c.c_int64, P, P, c.c_int64, P, P, c.c_int, P, P, P, P,
-                                    P, c.c_size_t, P]
+                                    P, P, P, c.c_size_t, P]
     lib.so_local_energy.restype = c.c_int
     lib.so_fallback_count.argtypes = [c.POINTER(SoParams), c.c_int64, c.c_int64, P, c.c_size_t,
                                       c.POINTER(c.c_int64), P]
@@ -342,11 +342,12 @@ def rdm1(Q: torch.Tensor, bits: torch.Tensor, *, trial: bool = True, with_majora
 
 
 def local_energy(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, t: torch.Tensor, L: torch.Tensor, *,
-                 paper_norm: bool = False, workspace: torch.Tensor | None = None):
+                 paper_norm: bool = False, return_pairs: bool = False, workspace: torch.Tensor | None = None):
     """Local energies E_L = N_w / S_w (so_local_energy) for H = sum t_pq a_p^dag a_q
     + 1/2 sum_g Lhat_g^2, with t [n, n] complex128 and L [n*n, n_gamma] float64
     (each L^g real symmetric).  Returns (overlap [W], numerator [W],
-    energy [W], status int32 [W])."""
+    energy [W], status int32 [W]), and with ``return_pairs`` also the
+    single-shadow terms (o [W, S], e [W, S])."""
     W, n, eta, S = _check_inputs(phi, Q, bits)
     if not (t.is_cuda and L.is_cuda) or t.dtype != torch.complex128 or L.dtype != torch.float64:
         raise TypeError("t must be complex128 and L float64, on the device")
@@ -361,13 +362,18 @@ def local_energy(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, t: torc
         raise ShadowOvError(st, "so_local_energy_workspace_size")
     ws = workspace if workspace is not None else _workspace(int(nbytes.value), phi.device)
     out = [torch.empty(W, dtype=torch.complex128, device=phi.device) for _ in range(3)]
+    pairs = ([torch.empty((W, S), dtype=torch.complex128, device=phi.device) for _ in range(2)]
+             if return_pairs else [None, None])
     status = torch.zeros(W, dtype=torch.int32, device=phi.device)
     stream = torch.cuda.current_stream(phi.device).cuda_stream
     st = lib.so_local_energy(ctypes.byref(p), _dev_ptr(phi), W, _dev_ptr(Q), _dev_ptr(bits), S, _dev_ptr(t),
                              _dev_ptr(L) if ng else None, ng, _dev_ptr(out[0]), _dev_ptr(out[1]), _dev_ptr(out[2]),
-                             _dev_ptr(status), _dev_ptr(ws), ws.numel(), ctypes.c_void_p(stream))
+                             _dev_ptr(pairs[0]), _dev_ptr(pairs[1]), _dev_ptr(status), _dev_ptr(ws), ws.numel(),
+                             ctypes.c_void_p(stream))
     if st != SO_OK:
         raise ShadowOvError(st, "so_local_energy")
+    if return_pairs:
+        return out[0], out[1], out[2], status, pairs[0], pairs[1]
     return out[0], out[1], out[2], status
 
 

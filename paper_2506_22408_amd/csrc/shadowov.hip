@@ -1004,6 +1004,11 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
 so_status shadow_overlap_noalloc(const so_params *p, const so_c64 *phi, int64_t n_walkers, const double *Q,
                                  const uint64_t *bits, int64_t n_shadows, so_c64 *overlap, so_c64 *pair_out,
                                  int32_t *status, void *stream) {
+    // every argument check of shadow_overlap comes before the first HIP call
+    int K;
+    if (!params_ok(p, &K) || !phi || !Q || !bits || !overlap || n_walkers < 1 || n_shadows < 1 ||
+        n_walkers > (int64_t)INT32_MAX || n_shadows > (int64_t)INT32_MAX)
+        return SO_ERR_ARG;
     size_t need = 0;
     const so_status sv = so_workspace_size(p, n_walkers, n_shadows, 0, &need);
     if (sv != SO_OK) return sv;
@@ -1190,12 +1195,13 @@ so_status so_local_energy_workspace_size(const so_params *p, int64_t n_walkers, 
 
 so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walkers, const double *Q,
                           const uint64_t *bits, int64_t n_shadows, const so_c64 *t, const double *L, int n_gamma,
-                          so_c64 *overlap, so_c64 *numerator, so_c64 *energy, int32_t *status, void *workspace,
-                          size_t workspace_bytes, void *stream) {
+                          so_c64 *overlap, so_c64 *numerator, so_c64 *energy, so_c64 *pair_overlap,
+                          so_c64 *pair_numerator, int32_t *status, void *workspace, size_t workspace_bytes,
+                          void *stream) {
     int K;
     if (!phi || !Q || !bits || !t || (n_gamma > 0 && !L) || !energy_args_ok(p, n_walkers, n_shadows, n_gamma, &K))
         return SO_ERR_ARG;
-    if (!overlap && !numerator && !energy) return SO_ERR_ARG;
+    if (!overlap && !numerator && !energy && !pair_overlap && !pair_numerator) return SO_ERR_ARG;
     if (p->flags & SO_FLAG_LOG_OUTPUT) return SO_ERR_UNSUPPORTED;
     if (!so_supported(p->n, p->eta) || p->n > SO_EN_NMAX || p->precision != SO_PREC_FP64) return SO_ERR_UNSUPPORTED;
     const int n = p->n, eta = p->eta, d = 2 * n, T = so_tiles(n);
@@ -1209,8 +1215,9 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     double *K2 = reinterpret_cast<double *>(ws + Lo.off_K2);
     double2 *Kt = reinterpret_cast<double2 *>(ws + Lo.off_Kt);
     double *Ms = reinterpret_cast<double *>(ws + Lo.off_M);
-    double2 *op = reinterpret_cast<double2 *>(ws + Lo.off_o);
-    double2 *ep = reinterpret_cast<double2 *>(ws + Lo.off_e);
+    double2 *op = pair_overlap ? reinterpret_cast<double2 *>(pair_overlap) : reinterpret_cast<double2 *>(ws + Lo.off_o);
+    double2 *ep = pair_numerator ? reinterpret_cast<double2 *>(pair_numerator)
+                                 : reinterpret_cast<double2 *>(ws + Lo.off_e);
     int32_t *wst = status ? status : reinterpret_cast<int32_t *>(ws + Lo.off_stat);
     double2 *Xr = reinterpret_cast<double2 *>(ws + Lo.off_Xr);
     double *Cr = reinterpret_cast<double *>(ws + Lo.off_Cr);

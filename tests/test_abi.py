@@ -82,3 +82,41 @@ def test_null_pointers_and_small_workspace_rejected():
     assert B.lib.shadow_overlap(ctypes.byref(bad), d, 4, d, d, 4, d, None, None, d, 1 << 30, None) == B.SO_ERR_ARG
     bad = B.SoParams(8, 4, 0, 0, 0, 1 << 5)  # unknown flag
     assert B.lib.shadow_overlap(ctypes.byref(bad), d, 4, d, d, 4, d, None, None, d, 1 << 30, None) == B.SO_ERR_ARG
+
+
+def test_host_queries_every_shape():
+    """Every host-side query over every (n, eta) the library names: workspace
+    sizes of each entry point, node weights of both families, batch layouts,
+    and the argument checks of the entry points that need a device (they
+    must fail before any HIP call).  Run against the host-sanitized build
+    this sweeps the layout and table code for memory errors."""
+    d = ctypes.c_void_p(0x1000)
+    nb = ctypes.c_size_t(0)
+    for n in range(2, 25):
+        for eta in range(2, n + 1, 2):
+            for fam in ("unit", "chebyshev"):
+                for prec in ("fp64", "mixed"):
+                    p = B.make_params(n, eta, 0, fam, prec)
+                    for grad in (0, 1):
+                        assert B.lib.so_workspace_size(ctypes.byref(p), 7, 13, grad, ctypes.byref(nb)) == B.SO_OK
+                    z, w = B.node_weights(p)
+                    assert len(z) == n + 1 and np.all(np.isfinite(w))
+            p = B.make_params(n, eta)
+            st = B.lib.so_local_energy_workspace_size(ctypes.byref(p), 5, 9, 3, ctypes.byref(nb))
+            assert st == B.SO_OK
+            probs = (B.SoProblem * 2)()
+            for k in range(2):
+                probs[k].params = p
+                probs[k].phi, probs[k].Q, probs[k].bits, probs[k].overlap = 0x1000, 0x1000, 0x1000, 0x1000
+                probs[k].n_walkers, probs[k].n_shadows = 3 + k, 11 + k
+            assert B.lib.so_batch_workspace_size(probs, 2, ctypes.byref(nb)) == B.SO_OK
+            # entry points that would launch: refused before any HIP call
+            assert B.lib.shadow_overlap(ctypes.byref(p), d, 4, d, d, 4, d, None, None, None, 0, None) == \
+                B.SO_ERR_WORKSPACE
+            cnt = ctypes.c_int64(0)
+            assert B.lib.so_fallback_count(ctypes.byref(p), 4, 4, None, 0, ctypes.byref(cnt), None) == \
+                B.SO_ERR_WORKSPACE
+    big = B.make_params(16, 8)
+    assert B.lib.shadow_overlap_noalloc(ctypes.byref(big), d, 1024, d, d, 10000, d, None, None, None) == \
+        B.SO_ERR_WORKSPACE
+    assert B.lib.shadow_overlap_noalloc(ctypes.byref(big), None, 4, d, d, 4, d, None, None, None) == B.SO_ERR_ARG

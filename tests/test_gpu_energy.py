@@ -36,13 +36,23 @@ def td(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
 
 
+LAST_PAIRS = {}
+
+
 def run(B, w, t, L):
-    S_, N_, E_, st = B.local_energy(td(w.phi), td(w.Q), td(w.bits.view(np.int64)), td(t), td(L))
+    S_, N_, E_, st, op, ep = B.local_energy(td(w.phi), td(w.Q), td(w.bits.view(np.int64)), td(t), td(L),
+                                            return_pairs=True)
     torch.cuda.synchronize()
+    LAST_PAIRS["o"], LAST_PAIRS["e"] = op.cpu().numpy(), ep.cpu().numpy()
     return S_.cpu().numpy(), N_.cpu().numpy(), E_.cpu().numpy(), st.cpu().numpy()
 
 
 def check(Sg, Ng, Eg, o, e):
+    """Walker sums and, element by element, the pair terms of the last run."""
+    for name, r in (("o", o), ("e", e)):
+        g = LAST_PAIRS[name]
+        scale = np.maximum(np.abs(r), np.abs(r).mean(axis=1, keepdims=True))
+        assert np.all(np.abs(g - r) <= 1e-9 * scale), f"pair {name}: {(np.abs(g - r) / scale).max():.2e}"
     So, No = o.mean(axis=1), e.mean(axis=1)
     so, se = np.abs(o).mean(axis=1), np.abs(e).mean(axis=1)
     assert np.all(np.abs(Sg - So) <= 1e-9 * so), np.abs(Sg - So) / so
@@ -92,9 +102,11 @@ def test_energy_flagged_walkers(B):
     phi = w.phi.copy()
     phi[1][:, 3] = phi[1][:, 0]
     phi[2][0, 0] = np.nan
-    S_, N_, E_, st = B.local_energy(td(phi), td(w.Q), td(w.bits.view(np.int64)), td(w.t), td(w.L))
+    S_, N_, E_, st, op, ep = B.local_energy(td(phi), td(w.Q), td(w.bits.view(np.int64)), td(w.t), td(w.L),
+                                            return_pairs=True)
     torch.cuda.synchronize()
     Sg, Ng, Eg, st = (x.cpu().numpy() for x in (S_, N_, E_, st))
+    LAST_PAIRS["o"], LAST_PAIRS["e"] = op.cpu().numpy()[[0, 3]], ep.cpu().numpy()[[0, 3]]
     assert st[1] & B.SO_WSTAT_RANK
     assert np.isnan(Sg[1]) and np.isnan(Ng[1]) and np.isnan(Eg[1])
     assert st[2] & B.SO_WSTAT_NONFINITE and not np.isfinite(Sg[2])
@@ -133,6 +145,26 @@ def test_energy_paper_sized_sampled(B):
     Sg3, Ng3, Eg3, st3 = run(B, sub, w.t, w.L)
     o, e = oracle.energy_pairs(sub.phi, sub.Q, sub.bits, w.t, w.L)
     check(Sg3, Ng3, Eg3, o, e)
+
+
+def test_energy_pair_terms_paper_sized(B):
+    """The single-shadow terms e_ws and o_ws of energy_n16 (n = 16, eta = 8,
+    200 Cholesky-like vectors) element by element against the oracle, on the
+    first 4 walkers x 60 shadows (240 pairs).  The oracle's Chebyshev weights
+    amplify its own rounding (sum |w_k| ~ 3e5 at n = 16), so pairs are held to
+    1e-9 of max(|x|, mean |x|)."""
+    w = wl.config("energy_n16")
+    sub = wl.Workload("sub", w.n, w.eta, w.phi[:4], w.Q[:60], w.bits[:60], w.L, w.t)
+    out = B.local_energy(td(sub.phi), td(sub.Q), td(sub.bits.view(np.int64)), td(w.t), td(w.L), return_pairs=True)
+    torch.cuda.synchronize()
+    og, eg = out[4].cpu().numpy(), out[5].cpu().numpy()
+    assert not out[3].cpu().numpy().any()
+    o, e = oracle.energy_pairs(sub.phi, sub.Q, sub.bits, w.t, w.L)
+    for name, g, r in (("o", og, o), ("e", eg, e)):
+        scale = np.maximum(np.abs(r), np.abs(r).mean())
+        rel = np.abs(g - r) / scale
+        assert rel.max() <= 1e-9, f"{name}: worst {rel.max():.2e}"
+        print(f"energy_n16 pair terms {name}: worst {rel.max():.2e}, median {np.median(np.abs(g - r) / np.abs(r)):.2e}")
 
 
 def test_energy_deterministic(B):
@@ -197,8 +229,8 @@ def test_energy_argument_errors(B):
     # L missing with n_gamma > 0
     st = B.lib.so_local_energy(ctypes.byref(p), ctypes.c_void_p(phi.data_ptr()), 2, ctypes.c_void_p(Q.data_ptr()),
                                ctypes.c_void_p(bits.data_ptr()), 3, ctypes.c_void_p(t.data_ptr()), None, 2,
-                               ctypes.c_void_p(out.data_ptr()), None, None, None, ctypes.c_void_p(ws.data_ptr()),
-                               ws.numel(), None)
+                               ctypes.c_void_p(out.data_ptr()), None, None, None, None, None,
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
     assert st == B.SO_ERR_ARG
     torch.cuda.synchronize()
     assert torch.count_nonzero(out) == 0
