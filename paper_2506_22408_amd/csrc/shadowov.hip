@@ -1064,7 +1064,7 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
     const double2 *Xc = reinterpret_cast<const double2 *>(Xa);
     const double2 *Cc = reinterpret_cast<const double2 *>(Ca);
 #define SO_GRAD_LAUNCH(TT, NN)                                                                              \
-    hipLaunchKernelGGL((k_grad_pair<TT, NN>), grid, dim3(64), lds, st, n, eta, Xc, Cc, S, spw, rt, Fp, Op, wst)
+    hipLaunchKernelGGL((k_grad_pair<TT, NN>), grid, dim3(128), lds, st, n, eta, Xc, Cc, S, spw, rt, Fp, Op, wst)
     switch (T * 16 + NE) {
         case 16 + 2: SO_GRAD_LAUNCH(1, 2); break;
         case 16 + 4: SO_GRAD_LAUNCH(1, 4); break;

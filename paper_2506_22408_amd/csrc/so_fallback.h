@@ -26,12 +26,16 @@ __device__ __forceinline__ double2 fb_xrow(const double *Xw, int i, int col, int
 // Pfaffian of the m x m complex skew matrix in LDS (row stride lda; the
 // upper and lower triangles both present) by Householder tridiagonalisation,
 // lane q = row; destroys the matrix.  ubuf, ybuf: m complex of LDS scratch.
-// Returns the same value in every lane.  Starts and ends with a barrier.
-__device__ __forceinline__ double2 hh_pf_lds(double2 *A, int lda, int m, double2 *ubuf, double2 *ybuf, int q) {
+// Returns the same value in every lane.  Starts and ends with a barrier.  With
+// act = false the wave neither reads nor writes and only keeps the barriers
+// (the second wave of a two-wave workgroup); its return value is then
+// meaningless.
+__device__ __forceinline__ double2 hh_pf_lds(double2 *A, int lda, int m, double2 *ubuf, double2 *ybuf, int q,
+                                             bool act = true) {
     __syncthreads();
     double2 pf = c_make(1, 0);
     for (int k = 0; k < m; k += 2) {
-        const double2 x = (q > k && q < m) ? A[q * lda + k] : c_make(0, 0);
+        const double2 x = (act && q > k && q < m) ? A[q * lda + k] : c_make(0, 0);
         const double nx2 = grp_sum<64>(c_abs2(x));
         const double2 xf = grp_bcast<64>(x, k + 1);
         const double nx = sqrt(nx2);
@@ -42,15 +46,15 @@ __device__ __forceinline__ double2 hh_pf_lds(double2 *A, int lda, int m, double2
         if (k + 2 >= m) break;
         const double beta = nx > 0.0 ? 1.0 / (nx2 + nx * ax) : 0.0;
         const double2 u = (q == k + 1) ? c_sub(xf, alpha) : x;
-        if (q >= k + 1 && q < m) ubuf[q] = c_conj(u);
+        if (act && q >= k + 1 && q < m) ubuf[q] = c_conj(u);
         __syncthreads();
         double2 y = c_make(0, 0);
-        if (q >= k + 2 && q < m)
+        if (act && q >= k + 2 && q < m)
             for (int j = k + 1; j < m; ++j) y = c_fma(A[q * lda + j], ubuf[j], y);
         y = c_scale(y, beta);
-        if (q >= k + 2 && q < m) ybuf[q] = y;
+        if (act && q >= k + 2 && q < m) ybuf[q] = y;
         __syncthreads();
-        if (q >= k + 2 && q < m)
+        if (act && q >= k + 2 && q < m)
             for (int j = k + 2; j < m; ++j)
                 A[q * lda + j] = c_fma(u, ybuf[j], c_fma(c_neg(y), c_conj(ubuf[j]), A[q * lda + j]));
         __syncthreads();

@@ -37,35 +37,43 @@
 // ---- Gauss-Jordan with partial pivoting on the first nr columns of the
 // nr x nc system G (row-major, LDS), one column per lane (nc <= 64), nr <=
 // NRM.  Leaves [I | G^{-1} rhs].  Returns false on an exactly zero pivot
-// column.  The pivot key is the high word of |G[r][k]|^2 with its low 6 bits
-// replaced by 63 - lane (the high word of a non-negative double orders like
-// the value).  The row loop of the update is unrolled to NRM so that a
-// step's LDS accesses are issued together.
+// column (the rest of the elimination is then skipped).  The pivot key is the
+// high word of |G[r][k]|^2 with its low 6 bits replaced by 63 - lane (the high
+// word of a non-negative double orders like the value).  The row loop of the
+// update is unrolled to NRM so that a step's LDS accesses are issued
+// together.  The barriers do not depend on the data: every step executes the
+// same three.  With act = false the wave neither reads nor writes G and
+// returns true (the second wave of a two-wave workgroup calls it that way to
+// keep the barriers: its pivot search would race with the active wave's row
+// swap, which no barrier separates from it).
 template <int NRM>
-__device__ __forceinline__ bool gj_wave(double2 *G, int nr, int nc, int l) {
+__device__ __forceinline__ bool gj_wave(double2 *G, int nr, int nc, int l, bool act = true) {
+    bool ok = true;
     for (int k = 0; k < nr; ++k) {
-        const int r = k + l;
-        unsigned key = 0u;
-        if (r < nr) {
-            const unsigned hw = (unsigned)(__double_as_longlong(c_abs2(G[r * nc + k])) >> 32);
-            key = (hw & ~63u) | (unsigned)(63 - l);
-        }
-        const unsigned kmax = wave_max_u32(key);
-        if (kmax < 64u) return false;
-        const int p = k + (63 - (int)(kmax & 63u));
-        if (p != k) {
-            if (l < nc) {
-                const double2 t0 = G[k * nc + l], t1 = G[p * nc + l];
-                G[k * nc + l] = t1;
-                G[p * nc + l] = t0;
+        int p = k;
+        if (act && ok) {
+            const int r = k + l;
+            unsigned key = 0u;
+            if (r < nr) {
+                const unsigned hw = (unsigned)(__double_as_longlong(c_abs2(G[r * nc + k])) >> 32);
+                key = (hw & ~63u) | (unsigned)(63 - l);
             }
-            __syncthreads();
+            const unsigned kmax = wave_max_u32(key);
+            if (kmax < 64u) ok = false;
+            else p = k + (63 - (int)(kmax & 63u));
         }
-        const double2 ip = c_inv_nr(G[k * nc + k]);
+        const bool work = act && ok && l < nc;
+        if (work && p != k) {
+            const double2 t0 = G[k * nc + l], t1 = G[p * nc + l];
+            G[k * nc + l] = t1;
+            G[p * nc + l] = t0;
+        }
         __syncthreads();
-        if (l < nc) G[k * nc + l] = c_mul(G[k * nc + l], ip);
+        const double2 ip = work ? c_inv_nr(G[k * nc + k]) : c_make(0.0, 0.0);
         __syncthreads();
-        if (l < nc) {
+        if (work) G[k * nc + l] = c_mul(G[k * nc + l], ip);
+        __syncthreads();
+        if (work) {
             const double2 gk = G[k * nc + l];
 #pragma unroll
             for (int rr = 0; rr < NRM; ++rr) {
@@ -77,24 +85,35 @@ __device__ __forceinline__ bool gj_wave(double2 *G, int nr, int nc, int l) {
         }
         __syncthreads();
     }
-    return true;
+    return ok;
 }
 
-// Gauss-Jordan with partial pivoting for four independent NE x 2NE systems
-// (NE <= 8), one per 16-lane row (system g at G0 + g * stride, row-major):
-// lane c of row g loads column c, the steps run on registers with DPP
-// broadcasts inside the row (no LDS traffic or barrier inside a step), and
-// the column is stored back, leaving [I | M^{-1} rhs].  The pivot is the
-// largest |G[r][k]|, the first one on ties; a system whose pivot column is
-// zero sets *sing (and is left partly reduced).
+// Inverse of one node matrix M(c) = M0 + c M1 + c^2 M2 (NE x NE skew, NE <= 8,
+// upper triangles at Mup, Mup + NT, Mup + 2 NT) by Gauss-Jordan with partial
+// pivoting on one 16-lane row, entirely in registers: lane c < NE holds
+// column c of M(c) and lane NE + y column y of the identity; the steps use DPP
+// broadcasts inside the row.  On return lane NE + y holds column y of
+// M(c)^{-1} in col[0..NE).  The pivot is the largest |M[r][k]|, the first one
+// on ties; a zero pivot column sets sing.
 template <int NE>
-__device__ __forceinline__ void gj_rows16(double2 *G0, int stride, int l, bool *sing) {
-    constexpr int NC = 2 * NE;
-    const int g = l >> 4, c = l & 15;
-    double2 *G = G0 + g * stride;
-    double2 col[NE];
+__device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int c, bool &sing, double2 (&col)[NE]) {
+    constexpr int NT = NE * (NE - 1) / 2;
+    const double2 cj2 = c_mul(cj, cj);
 #pragma unroll
-    for (int r = 0; r < NE; ++r) col[r] = c < NC ? G[r * NC + c] : c_make(0.0, 0.0);
+    for (int r = 0; r < NE; ++r) {
+        double2 v = c_make(0.0, 0.0);
+        if (c < NE) {
+            if (r != c) {
+                const int a = r < c ? r : c, b = r < c ? c : r;
+                const int ei = a * (2 * NE - 1 - a) / 2 + (b - a - 1);
+                v = c_fma(cj2, Mup[2 * NT + ei], c_fma(cj, Mup[NT + ei], Mup[ei]));
+                if (r > c) v = c_neg(v);
+            }
+        } else if (c - NE == r) {
+            v = c_make(1.0, 0.0);
+        }
+        col[r] = v;
+    }
     bool zero = false;
     [&]<int... K>(std::integer_sequence<int, K...>) {
         (([&] {
@@ -112,9 +131,9 @@ __device__ __forceinline__ void gj_rows16(double2 *G0, int stride, int l, bool *
 #pragma unroll
              for (int r = k + 1; r < NE; ++r)
                  if (r == p) {
-                     const double2 t = col[k];
+                     const double2 tmp = col[k];
                      col[k] = col[r];
-                     col[r] = t;
+                     col[r] = tmp;
                  }
              const double2 piv = bc16c<k>(col[k]);
              col[k] = c_mul(col[k], c_inv_nr(bk > 0.0 ? piv : c_make(1.0, 0.0)));
@@ -126,79 +145,86 @@ __device__ __forceinline__ void gj_rows16(double2 *G0, int stride, int l, bool *
                  }
          }()), ...);
     }(std::make_integer_sequence<int, NE>{});
-    if (zero) *sing = true;
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < NE; ++r)
-        if (c < NC) G[r * NC + c] = col[r];
-    __syncthreads();
+    if (zero) sing = true;
 }
 
-// LDS regions of k_grad_pair (bytes), in order RP, RB, RR, RG, RS.  RP holds
-// P until B is built and Abar after that; RB holds B and, once the full-size
-// route is ruled out, the node sums A_0, A_1, A_2; the full-size route's
-// [B + cJ | I] (m x 2m) and its Householder vectors span RR and RG.
+// LDS regions of k_grad_pair (bytes), in order RP, RB, RR, RG, RS.
+//   RP: P, then the node inverses N_j (they may run on into RB), then Abar;
+//   RB: B, then the back substitution's solution rows;
+//   RR: the rows K of Z, then the trailing block, then A_0, A_1, A_2 and Z, Z';
+//   RG: Y0, Y1 and B_KK^{-1};
+//   RS: M0, M1, M2, Pf(M_j), the pivot permutation and cross-wave scratch.
+// The full-size route's [B + cJ | I] (m x 2m) and its Householder vectors span
+// RR and RG.
 struct GradLds {
     size_t rp, rb, rr, rg, rs, total;
 };
 __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
-    const int DP = 16 * T, LDP = DP + 1, m = n + NE, d = 2 * n;
+    const int DP = 16 * T, LDP = DP + 1, m = n + NE;
     GradLds g;
     auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
-    g.rp = al((size_t)(DP + 1) * LDP * sizeof(double));
+    g.rp = al((size_t)LDP * LDP * sizeof(double));
     g.rb = al((size_t)m * m * sizeof(double2));
     if (g.rb > g.rp) g.rp = g.rb;
     size_t rr = (size_t)n * (n + 2 * NE);
-    if ((size_t)4 * NE * 2 * NE > rr) rr = (size_t)4 * NE * 2 * NE;
     if ((size_t)NE * (2 * NE - 1) > rr) rr = (size_t)NE * (2 * NE - 1);
-    if ((size_t)2 * n * NE > rr) rr = (size_t)2 * n * NE;
+    if ((size_t)3 * NE * NE + 2 * n * NE > rr) rr = (size_t)3 * NE * NE + 2 * n * NE;
     g.rr = al(rr * sizeof(double2));
     size_t rg = (size_t)n * (2 * n + 2 * NE);
     const size_t full = ((size_t)2 * m * m + 2 * m) * sizeof(double2);
     if (full > g.rr + rg * sizeof(double2)) rg = (full - g.rr + sizeof(double2) - 1) / sizeof(double2);
     g.rg = al(rg * sizeof(double2));
-    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1) + 8) * sizeof(double2));   // + the permutation
+    // M0, M1, M2, Pf(M_j), the permutation (n ints) and 4 doubles of scratch
+    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1)) * sizeof(double2) + SO_GRAD_NMAX * sizeof(int) +
+              4 * sizeof(double));
     g.total = g.rp + g.rb + g.rr + g.rg + g.rs;
     return g;
 }
 
-// grid (W, Gy), one wave per block: walker blockIdx.x, shadows
-// [blockIdx.y spw, ...).  Writes its partial sums of F (2n x m, row-major)
-// and of o to Fpart[(w Gy + gy) 2nm ...] and Opart[w Gy + gy].
+// grid (W, Gy), two waves (128 threads) per block working on one pair at a
+// time: walker blockIdx.x, shadows [blockIdx.y spw, ...).  Writes its partial
+// sums of F (2n x m, row-major) and of o to Fpart[(w Gy + gy) 2nm ...] and
+// Opart[w Gy + gy].  Both waves execute every barrier; steps that one wave
+// does alone contain none.
 template <int T, int NE>
-__global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 *__restrict__ Xa,
-                                                  const double2 *__restrict__ Ca, int64_t S_total, int spw,
-                                                  RedTab tab, double2 *__restrict__ Fpart,
-                                                  double2 *__restrict__ Opart, int32_t *__restrict__ wstat) {
+__global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const double2 *__restrict__ Xa,
+                                                      const double2 *__restrict__ Ca, int64_t S_total, int spw,
+                                                      RedTab tab, double2 *__restrict__ Fpart,
+                                                      double2 *__restrict__ Opart, int32_t *__restrict__ wstat) {
+    constexpr int NTH = 128;
     constexpr int DP = 16 * T, LDP = DP + 1, MAT2 = DP * DP / 2;
     constexpr int KE = NE + 1;
     constexpr int NT = NE * (NE - 1) / 2;
     constexpr int NT2 = NE * (2 * NE - 1);
-    constexpr int NTQ = (NT2 + 63) / 64;
+    constexpr int NTQ = (NT2 + NTH - 1) / NTH;
     constexpr int KK = 4 * T;
     constexpr int TM = (8 * T + NE + 15) / 16;              // 16-row tiles of F^T (m = n + NE <= 8T + NE)
     const int m = n + NE, d = 2 * n, WR = n + 2 * NE, GW = 2 * n + 2 * NE;
-    const int l = threadIdx.x, w = blockIdx.x;
+    const int t0 = threadIdx.x, wv = t0 >> 6, w = blockIdx.x;
     extern __shared__ double lds[];
     const GradLds L = grad_lds(T, n, NE);
     char *base = reinterpret_cast<char *>(lds);
     double *RP = reinterpret_cast<double *>(base);
     double2 *RA = reinterpret_cast<double2 *>(base);   // over P once B is built
+    double2 *NJ = RA;                                  // node inverses, before Abar
     double2 *RB = reinterpret_cast<double2 *>(base + L.rp);
     double2 *RR = reinterpret_cast<double2 *>(base + L.rp + L.rb);
     double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr);
     double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr + L.rg);
     double2 *Mup = RS;                       // M0, M1, M2 upper triangles
     double2 *pfm = RS + 3 * NT;              // Pf(M_j)
-    double2 *Ahat = RB;                      // A_0, A_1, A_2 (NE x NE each), over B
+    int *pis = reinterpret_cast<int *>(pfm + KE);
+    double *xred = reinterpret_cast<double *>(pis + SO_GRAD_NMAX);
+    double2 *Ahat = RR;                      // A_0, A_1, A_2 (NE x NE each)
+    double2 *Zr = RR + 3 * NE * NE;          // Z, Z' (n x NE each)
     double2 *ubuf = RR + 2 * m * m;          // Householder vectors of the full-size route
     double2 *ybuf = ubuf + m;
 
-    // trailing entries (a < b) of the 2NE x 2NE block handled by this lane
+    // trailing entries (a < b) of the 2NE x 2NE block handled by this thread
     int ta[NTQ], tb[NTQ];
 #pragma unroll
     for (int q = 0; q < NTQ; ++q) {
-        int e = l + 64 * q, a = 0;
+        int e = t0 + NTH * q, a = 0;
         if (e >= NT2) e = 0;
         while (e >= 2 * NE - 1 - a) { e -= 2 * NE - 1 - a; ++a; }
         ta[q] = a;
@@ -213,39 +239,51 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
         const int u = i - eta, v = j - eta;
         return (u + v == 2 * NE - 1) ? (u < NE ? 1.0 : -1.0) : 0.0;
     };
+    // block-wide maximum of a value that each wave has reduced
+    auto block_max = [&](double v) -> double {
+        if ((t0 & 63) == 0) xred[wv] = v;
+        __syncthreads();
+        const double r = fmax(xred[0], xred[1]);
+        __syncthreads();
+        return r;
+    };
 
     // F^T = sum over the range of Abar''^T (Xall C'^T), real and imaginary
-    // parts, in the matrix-core accumulators (tile (I, J), register r, lane
-    // l: F^T[16 I + 4 r + l/16][16 J + l%16])
-    so_d4 FT[2][TM][T];
+    // parts, in the matrix-core accumulators: wave wv holds the column tile
+    // J = wv (tile (I, J), register r, lane l: F^T[16 I + 4 r + l/16][16 J + l%16])
+    so_d4 FT[2][TM];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
 #pragma unroll
-        for (int I = 0; I < TM; ++I)
-#pragma unroll
-            for (int J = 0; J < T; ++J) FT[p][I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+        for (int I = 0; I < TM; ++I) FT[p][I] = so_d4{0.0, 0.0, 0.0, 0.0};
     double2 oacc = c_make(0.0, 0.0);
     int32_t wflags = 0;
 
     const int64_t s0 = (int64_t)blockIdx.y * spw;
     const int64_t s1 = min(S_total, s0 + spw);
     for (int64_t s = s0; s < s1; ++s) {
+        // the thread index through an opaque move: indices derived from it are
+        // recomputed per pair instead of being hoisted out of the shadow loop,
+        // where they would stay live (and spill) through every stage
+        int t = t0;
+        asm volatile("" : "+v"(t));
+        const int l = t & 63;
         const double2 *Cs = Ca + (size_t)s * MAT2;
+        // both waves form P (the same values; the formation is a few percent of a pair)
         pair_formation<T, false>(Xw, Cs, RP, l, LDP);
 
         // ---------------- B (m x m), then R = rows K of Z
         double bmax = 0.0;
-        for (int e = l; e < m * m; e += 64) {
+        for (int e = t; e < m * m; e += NTH) {
             const int i = e / m, j = e - i * m;
             const int ir = rre(i) * LDP, ii = rim(i) * LDP, jr = rre(j), ji = rim(j);
             const double2 v = c_make(RP[ir + jr] - RP[ii + ji], RP[ir + ji] + RP[ii + jr]);
             RB[e] = v;
             bmax = fmax(bmax, c_abs2(v));
         }
-        bmax = wave_max(bmax);
+        bmax = block_max(wave_max(bmax));   // its barriers also publish B
         const double rbmax = rcp_nr(fmax(bmax, 1e-300));
-        __syncthreads();
-        for (int e = l; e < n * WR; e += 64) {
+        for (int e = t; e < n * WR; e += NTH) {
             const int i = e / WR, j = e - i * WR;
             RR[e] = (j < m) ? RB[i * m + j] : c_make(Jel(i, n + (j - m)), 0.0);
         }
@@ -253,57 +291,59 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
 #pragma unroll
         for (int q = 0; q < NTQ; ++q) {
             tv[q] = c_make(0.0, 0.0);
-            if (l + 64 * q < NT2 && tb[q] < NE) tv[q] = RB[(n + ta[q]) * m + n + tb[q]];
+            if (t + NTH * q < NT2 && tb[q] < NE) tv[q] = RB[(n + ta[q]) * m + n + tb[q]];
         }
         __syncthreads();
 
         // ---------------- elimination of K, pencil, node Pfaffians
         double2 pfk;
         int perm = l;
-        bool flag = elim_bordered<NE, NTQ>(n, WR, RR, ta, tb, tv, bmax, rbmax, l, pfk, &perm);
+        const bool flag = elim_bordered<NE, NTQ, NTH>(n, WR, RR, ta, tb, tv, bmax, rbmax, t, pfk, &perm, xred);
         double2 o = c_make(0.0, 0.0);
         if (!flag) {
             // ---------------- Y0, Y1, B_KK^{-1} by back substitution with the pivot rows
             // U [Y' | W] = [R_LE | I] in the pivoted order (U = the rows of R, block
             // upper triangular with pivots [[0, a], [-a, 0]]); then, with pi the
             // permutation, Y[pi(i)] = Y'[i] and B_KK^{-1}[pi(i)][pi(j)] = (-W D W^T)[i][j]
-            // (P B_KK P^T = L D L^T = -U^T D^{-1} U).  Lane c < 2NE + n holds
-            // column c of the right-hand side; the solution goes to RB (free: the
-            // full-size route is ruled out) and then, reordered, to RG.
+            // (P B_KK P^T = L D L^T = -U^T D^{-1} U).  Lane c < 2NE + n of wave 0
+            // holds column c of the right-hand side; the solution goes to RB (free:
+            // the full-size route is ruled out) and then, reordered, to RG.
             {
                 constexpr int NRM = 8 * T;
                 const int SW = 2 * NE + n;
-                double2 rhs[NRM];
+                if (wv == 0) {
+                    double2 rhs[NRM];
 #pragma unroll
-                for (int i = 0; i < NRM; ++i) {
-                    rhs[i] = c_make(0.0, 0.0);
-                    if (i < n && l < SW) rhs[i] = l < 2 * NE ? RR[i * WR + n + l] : c_make(i == l - 2 * NE ? 1.0 : 0.0, 0.0);
-                }
-#pragma unroll
-                for (int bb = 0; bb < NRM / 2; ++bb) {
-                    const int k = NRM - 2 - 2 * bb;
-                    if (k < n) {
-                        const double2 ia = c_inv_nr(RR[k * WR + k + 1]);
-                        const double2 yk1 = c_mul(rhs[k], ia), yk = c_neg(c_mul(rhs[k + 1], ia));
-                        rhs[k] = yk;
-                        rhs[k + 1] = yk1;
-#pragma unroll
-                        for (int i = 0; i < k; ++i)
-                            rhs[i] = c_fma(c_neg(RR[i * WR + k]), yk, c_fma(c_neg(RR[i * WR + k + 1]), yk1, rhs[i]));
+                    for (int i = 0; i < NRM; ++i) {
+                        rhs[i] = c_make(0.0, 0.0);
+                        if (i < n && l < SW)
+                            rhs[i] = l < 2 * NE ? RR[i * WR + n + l] : c_make(i == l - 2 * NE ? 1.0 : 0.0, 0.0);
                     }
-                }
-                int *pis = reinterpret_cast<int *>(pfm + KE);
-                if (l < n) pis[l] = perm;
 #pragma unroll
-                for (int i = 0; i < NRM; ++i)
-                    if (i < n && l < SW) RB[i * SW + l] = rhs[i];
+                    for (int bb = 0; bb < NRM / 2; ++bb) {
+                        const int k = NRM - 2 - 2 * bb;
+                        if (k < n) {
+                            const double2 ia = c_inv_nr(RR[k * WR + k + 1]);
+                            const double2 yk1 = c_mul(rhs[k], ia), yk = c_neg(c_mul(rhs[k + 1], ia));
+                            rhs[k] = yk;
+                            rhs[k + 1] = yk1;
+#pragma unroll
+                            for (int i = 0; i < k; ++i)
+                                rhs[i] = c_fma(c_neg(RR[i * WR + k]), yk, c_fma(c_neg(RR[i * WR + k + 1]), yk1, rhs[i]));
+                        }
+                    }
+                    if (l < n) pis[l] = perm;
+#pragma unroll
+                    for (int i = 0; i < NRM; ++i)
+                        if (i < n && l < SW) RB[i * SW + l] = rhs[i];
+                }
                 __syncthreads();
-                for (int e = l; e < n * 2 * NE; e += 64) {
+                for (int e = t; e < n * 2 * NE; e += NTH) {
                     const int i = e / (2 * NE), c = e - i * (2 * NE);
                     const double2 v = RB[i * SW + c];
                     RG[pis[i] * GW + (c < NE ? n + c : m + (c - NE))] = v;
                 }
-                for (int e = l; e < n * n; e += 64) {
+                for (int e = t; e < n * n; e += NTH) {
                     const int i = e / n, j = e - i * n;
                     const double2 *wi = RB + i * SW + 2 * NE, *wj = RB + j * SW + 2 * NE;
                     double2 acc = c_make(0.0, 0.0);
@@ -315,10 +355,10 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
             }
 #pragma unroll
             for (int q = 0; q < NTQ; ++q)
-                if (l + 64 * q < NT2) RR[l + 64 * q] = tv[q];
+                if (t + NTH * q < NT2) RR[t + NTH * q] = tv[q];
             __syncthreads();
             auto tix = [&](int a, int bb) -> int { return a * (2 * NE - 1) - a * (a - 1) / 2 + (bb - a - 1); };
-            for (int e = l; e < NT; e += 64) {
+            for (int e = t; e < NT; e += NTH) {
                 int x = 0, r = e;
                 while (r >= NE - 1 - x) { r -= NE - 1 - x; ++x; }
                 const int y = x + 1 + r;
@@ -327,68 +367,46 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
                 Mup[2 * NT + e] = RR[tix(NE + x, NE + y)];
             }
             __syncthreads();
-            // Pf(M_j), four nodes per pass, one per 16-lane row
-            for (int j0 = 0; j0 < KE; j0 += 4) {
-                const int j = j0 + (l >> 4);
-                const double2 pf = pencil_pf_row<NE>(Mup, tab.e[j < KE ? j : KE - 1], l & 15);
-                if ((l & 15) == 0 && j < KE) pfm[j] = pf;
+            // Pf(M_j) and N_j = M_j^{-1}: eight nodes per pass, one per 16-lane row
+            const int g8 = t >> 4, q16 = t & 15;
+            bool sing = false;
+            for (int j0 = 0; j0 < KE; j0 += 8) {
+                const int j = j0 + g8;
+                const double2 cj = tab.e[j < KE ? j : KE - 1];
+                const double2 pf = pencil_pf_row<NE>(Mup, cj, q16);
+                if (q16 == 0 && j < KE) pfm[j] = pf;
+                double2 col[NE];
+                bool sg = false;
+                gj_node_row<NE>(Mup, cj, q16, sg, col);
+                if (j < KE) {
+                    sing = sing || sg;
+                    if (q16 >= NE && q16 < 2 * NE) {
+                        const int y = q16 - NE;
+#pragma unroll
+                        for (int x = 0; x < NE; ++x) NJ[(j * NE + x) * NE + y] = col[x];
+                    }
+                }
             }
+            if (sing) wflags |= SO_WSTAT_SINGULAR;
             __syncthreads();
             for (int j = 0; j < KE; ++j) o = c_fma(tab.v[j], pfm[j], o);
             o = c_mul(o, pfk);
-        }
-        if (!flag) {
-            // ---------------- A_p from the node inverses, four nodes at a time
-            double2 ah0 = c_make(0, 0), ah1 = c_make(0, 0), ah2 = c_make(0, 0);
-            bool sing = false;
-            for (int g0 = 0; g0 < KE; g0 += 4) {
-                for (int e = l; e < 4 * NE * 2 * NE; e += 64) {
-                    const int g = e / (NE * 2 * NE), rc = e - g * (NE * 2 * NE);
-                    const int x = rc / (2 * NE), c = rc - x * (2 * NE);
-                    const int j = min(g0 + g, KE - 1);
-                    double2 v;
-                    if (c < NE) {
-                        if (x == c) {
-                            v = c_make(0.0, 0.0);
-                        } else {
-                            const int a = min(x, c), b = max(x, c);
-                            const int ei = a * (2 * NE - 1 - a) / 2 + (b - a - 1);
-                            const double2 cj = tab.e[j];
-                            v = c_fma(c_mul(cj, cj), Mup[2 * NT + ei], c_fma(cj, Mup[NT + ei], Mup[ei]));
-                            if (x > c) v = c_neg(v);
-                        }
-                    } else {
-                        v = c_make((c - NE == x) ? 1.0 : 0.0, 0.0);
-                    }
-                    RR[e] = v;
+            // ---------------- A_p = sum_j v_j Pf(M_j) e_j^p N_j (p = 0, 1, 2)
+            for (int e = t; e < 3 * NE * NE; e += NTH) {
+                const int pw = e / (NE * NE), xy = e - pw * NE * NE;
+                double2 acc = c_make(0.0, 0.0);
+                for (int j = 0; j < KE; ++j) {
+                    double2 cf = c_mul(tab.v[j], pfm[j]);
+                    if (pw >= 1) cf = c_mul(cf, tab.e[j]);
+                    if (pw == 2) cf = c_mul(cf, tab.e[j]);
+                    acc = c_fma(cf, NJ[j * NE * NE + xy], acc);
                 }
-                __syncthreads();
-                gj_rows16<NE>(RR, NE * 2 * NE, l, &sing);
-                if (l < NE * NE) {
-                    const int x = l / NE, y = l - x * NE;
-                    for (int g = 0; g < 4 && g0 + g < KE; ++g) {
-                        const int j = g0 + g;
-                        const double2 nv = RR[g * NE * 2 * NE + x * 2 * NE + NE + y];
-                        const double2 c0 = c_mul(tab.v[j], pfm[j]);
-                        const double2 c1 = c_mul(c0, tab.e[j]);
-                        const double2 c2 = c_mul(c1, tab.e[j]);
-                        ah0 = c_fma(c0, nv, ah0);
-                        ah1 = c_fma(c1, nv, ah1);
-                        ah2 = c_fma(c2, nv, ah2);
-                    }
-                }
-                __syncthreads();
-            }
-            if (__any(sing)) wflags |= SO_WSTAT_SINGULAR;
-            if (l < NE * NE) {
-                Ahat[l] = ah0;
-                Ahat[NE * NE + l] = ah1;
-                Ahat[2 * NE * NE + l] = ah2;
+                Ahat[e] = acc;
             }
             __syncthreads();
-            // ---------------- Z, Z' (n x NE) into RR
+            // ---------------- Z, Z' (n x NE)
             // Y0 = RG[:, n:m], Y1 = RG[:, m:m+NE], B_KK^{-1} = RG[:, m+NE:m+NE+n]
-            for (int e = l; e < n * NE; e += 64) {
+            for (int e = t; e < n * NE; e += NTH) {
                 const int i = e / NE, x = e - i * NE;
                 double2 z = c_make(0, 0), zp = c_make(0, 0);
                 for (int y = 0; y < NE; ++y) {
@@ -396,24 +414,24 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
                     z = c_fma(y0, Ahat[y * NE + x], c_fma(y1, Ahat[NE * NE + y * NE + x], z));
                     zp = c_fma(y0, Ahat[NE * NE + y * NE + x], c_fma(y1, Ahat[2 * NE * NE + y * NE + x], zp));
                 }
-                RR[e] = z;
-                RR[n * NE + e] = zp;
+                Zr[e] = z;
+                Zr[n * NE + e] = zp;
             }
             __syncthreads();
             // ---------------- Abar (m x m) into RA
-            for (int e = l; e < m * m; e += 64) {
+            for (int e = t; e < m * m; e += NTH) {
                 const int i = e / m, j = e - i * m;
                 double2 v;
                 if (i < n && j < n) {
                     double2 acc = c_make(0, 0);
                     for (int x = 0; x < NE; ++x)
-                        acc = c_fma(RR[i * NE + x], RG[j * GW + n + x],
-                                    c_fma(RR[n * NE + i * NE + x], RG[j * GW + m + x], acc));
+                        acc = c_fma(Zr[i * NE + x], RG[j * GW + n + x],
+                                    c_fma(Zr[n * NE + i * NE + x], RG[j * GW + m + x], acc));
                     v = c_fma(o, RG[i * GW + m + NE + j], c_mul(pfk, acc));
                 } else if (i < n) {
-                    v = c_neg(c_mul(pfk, RR[i * NE + (j - n)]));
+                    v = c_neg(c_mul(pfk, Zr[i * NE + (j - n)]));
                 } else if (j < n) {
-                    v = c_mul(pfk, RR[j * NE + (i - n)]);
+                    v = c_mul(pfk, Zr[j * NE + (i - n)]);
                 } else {
                     v = c_mul(pfk, Ahat[(i - n) * NE + (j - n)]);
                 }
@@ -421,29 +439,34 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
             }
             __syncthreads();
         } else {
-            // ---------------- full-size route: Pf and inverse of every B + e_j J
+            // ---------------- full-size route: Pf and inverse of every B + e_j J;
+            // wave 0 reduces, wave 1 takes the same decisions and barriers
             o = c_make(0.0, 0.0);
-            for (int e = l; e < m * m; e += 64) RA[e] = c_make(0.0, 0.0);
+            for (int e = t; e < m * m; e += NTH) RA[e] = c_make(0.0, 0.0);
             double2 *Aug = RR;   // m x 2m over RR and RG
             const int AW = 2 * m;
             for (int j = 0; j < KE; ++j) {
                 const double2 cj = tab.e[j];
                 __syncthreads();
-                for (int e = l; e < m * m; e += 64) {
+                for (int e = t; e < m * m; e += NTH) {
                     const int i = e / m, c = e - i * m;
                     Aug[i * AW + c] = c_add(RB[e], c_scale(cj, Jel(i, c)));
                 }
-                const double2 qj = hh_pf_lds(Aug, AW, m, ubuf, ybuf, l);
-                for (int e = l; e < m * AW; e += 64) {
+                const double2 qw = hh_pf_lds(Aug, AW, m, ubuf, ybuf, l, wv == 0);
+                if (t == 0) { xred[0] = qw.x; xred[1] = qw.y; }
+                __syncthreads();
+                const double2 qj = c_make(xred[0], xred[1]);
+                for (int e = t; e < m * AW; e += NTH) {
                     const int i = e / AW, c = e - i * AW;
                     Aug[e] = (c < m) ? c_add(RB[i * m + c], c_scale(cj, Jel(i, c)))
                                      : c_make((c - m == i) ? 1.0 : 0.0, 0.0);
                 }
                 __syncthreads();
-                if (!gj_wave<8 * T + NE>(Aug, m, AW, l)) wflags |= SO_WSTAT_SINGULAR;
+                const bool gok = gj_wave<8 * T + NE>(Aug, m, AW, l, wv == 0);
+                if (!gok) wflags |= SO_WSTAT_SINGULAR;   // wave 0 only (wave 1 gets true)
                 const double2 f = c_mul(tab.v[j], qj);
                 o = c_fma(tab.v[j], qj, o);
-                for (int e = l; e < m * m; e += 64) {
+                for (int e = t; e < m * m; e += NTH) {
                     const int i = e / m, c = e - i * m;
                     RA[e] = c_fma(f, Aug[i * AW + m + c], RA[e]);
                 }
@@ -456,23 +479,28 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
         // and Abar'' (DP x m) the rows of Abar placed on the rows of Xall:
         // Abar''[rre(i)] = Abar[i], Abar''[rim(i)] = i Abar[i].  On the matrix
         // cores as F^T += Abar''^T U^T: U^T = Xall C'^T from the operands, its
-        // tile (I, J) register r being the B operand at k-step 4 I + r.
-        {
-            double xa[T][KK], ca[T][KK];
+        // tile (I, J) register r being the B operand at k-step 4 I + r.  Wave wv
+        // takes the column tile J = wv.
+#pragma unroll
+        for (int J = 0; J < T; ++J) {
+            if (J != wv) continue;   // wave J takes column tile J (a compile-time index)
+            // operands: all of Xall, and tile J of C' only
+            double xa[T][KK], cj[KK];
             load_ops<T>(Xw, xa, l);
-            load_ops<T>(Cs, ca, l);
-            so_d4 Ut[T][T];
 #pragma unroll
-            for (int I = 0; I < T; ++I)
+            for (int h = 0; h < 2 * T; ++h) {
+                const double2 v = Cs[(J * 2 * T + h) * 64 + l];
+                cj[2 * h] = v.x;
+                cj[2 * h + 1] = v.y;
+            }
+            so_d4 Ut[T];
 #pragma unroll
-                for (int J = 0; J < T; ++J) Ut[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+            for (int I = 0; I < T; ++I) Ut[I] = so_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk)
 #pragma unroll
                 for (int I = 0; I < T; ++I)
-#pragma unroll
-                    for (int J = 0; J < T; ++J)
-                        Ut[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], ca[J][kk], Ut[I][J], 0, 0, 0);
+                    Ut[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], cj[kk], Ut[I], 0, 0, 0);
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
                 // A operand: Abar''[k][c], k = 4 kk + l/16 a row of Xall, c = 16 I + l%16
@@ -485,30 +513,27 @@ __global__ __launch_bounds__(64) void k_grad_pair(int n, int eta, const double2 
                     double2 a = c_make(0.0, 0.0);
                     if (k < d && c < m) a = RA[i * m + c];
                     if (imag) a = c_make(-a.y, a.x);
-#pragma unroll
-                    for (int J = 0; J < T; ++J) {
-                        FT[0][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, Ut[kk >> 2][J][kk & 3], FT[0][I][J], 0, 0, 0);
-                        FT[1][I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, Ut[kk >> 2][J][kk & 3], FT[1][I][J], 0, 0, 0);
-                    }
+                    FT[0][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, Ut[kk >> 2][kk & 3], FT[0][I], 0, 0, 0);
+                    FT[1][I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, Ut[kk >> 2][kk & 3], FT[1][I], 0, 0, 0);
                 }
             }
         }
         __syncthreads();   // Abar reads done before the next formation
     }
     const int64_t part = (int64_t)w * gridDim.y + blockIdx.y;
+    const int l = t0 & 63;
+    if (wv < T) {
+        const int J = wv;
 #pragma unroll
-    for (int I = 0; I < TM; ++I)
-#pragma unroll
-        for (int J = 0; J < T; ++J)
+        for (int I = 0; I < TM; ++I)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int c = 16 * I + 4 * r + (l >> 4), mu = 16 * J + (l & 15);
-                if (c < m && mu < d) Fpart[part * (int64_t)(d * m) + mu * m + c] = c_make(FT[0][I][J][r], FT[1][I][J][r]);
+                if (c < m && mu < d) Fpart[part * (int64_t)(d * m) + mu * m + c] = c_make(FT[0][I][r], FT[1][I][r]);
             }
-    if (l == 0) {
-        Opart[part] = oacc;
-        if (wflags) atomicOr(&wstat[w], wflags);
     }
+    if (t0 == 0) Opart[part] = oacc;
+    if (l == 0 && wflags) atomicOr(&wstat[w], wflags);
 }
 
 // One workgroup of 64 per walker: F = sum over the walker's partials (fixed

@@ -148,20 +148,25 @@ __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, cons
 }
 
 // ---- pairwise elimination of K in the bordered rows ---------------------------
-// Rl: the rows K of Z (n x WR complex, LDS); tv: this lane's trailing entries
+// Rl: the rows K of Z (n x WR complex, LDS); tv: this thread's trailing entries
 // (ta < tb) of the 2NE x 2NE block, updated in place; rbmax = 1 / max|B|^2.
 // Returns true when the pair needs the full-size path (zero pivot or growth);
-// pfk = Pf(B_KK).  Ends with a barrier.  The rows of R are left as they were
-// when each served as a pivot row, with the K columns in the final pivoted
-// order: rows k, k+1 of pair k/2 are then rows k, k+1 of U in
-// P B_KK P^T = L D L^T, U = D L^T (D: the 2 x 2 pivots [[0, a], [-a, 0]]).
-// With a non-null perm, lane i < n gets perm = the original index of pivoted
-// position i.
-template <int NE, int NTQ>
+// pfk = Pf(B_KK).  The rows of R are left as they were when each served as a
+// pivot row, with the K columns in the final pivoted order: rows k, k+1 of
+// pair k/2 are then rows k, k+1 of U in P B_KK P^T = L D L^T, U = D L^T (D:
+// the 2 x 2 pivots [[0, a], [-a, 0]]).  With a non-null perm, lane i < n of
+// every wave gets perm = the original index of pivoted position i.
+// NTH threads (one or two waves) share the work; t = threadIdx.x.  Every wave
+// takes the pivot decisions itself from the same data, so they agree and the
+// barriers stay uniform; with two waves the final growth maximum is combined
+// through xred (two doubles of LDS).
+template <int NE, int NTQ, int NTH = 64>
 __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const int (&ta)[NTQ], const int (&tb)[NTQ],
-                                              double2 (&tv)[NTQ], double bmax, double rbmax, int l, double2 &pfk,
-                                              int *perm = nullptr) {
+                                              double2 (&tv)[NTQ], double bmax, double rbmax, int t, double2 &pfk,
+                                              int *perm = nullptr, double *xred = nullptr) {
+    static_assert(NTH == 64 || NTH == 128, "one or two waves");
     constexpr int NT2 = NE * (2 * NE - 1);
+    const int l = t & 63;
     pfk = c_make(1.0, 0.0);
     int pi = l;
     bool zero = false;
@@ -183,16 +188,16 @@ __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const 
         if (kmax < 64u) { zero = true; break; }
         const int p = k + 1 + (63 - (int)(kmax & 63u));
         if (p != k + 1) {
-            if (l < WR) {
-                const double2 t0 = Rl[(k + 1) * WR + l], t1 = Rl[p * WR + l];
-                Rl[(k + 1) * WR + l] = t1;
-                Rl[p * WR + l] = t0;
+            if (t < WR) {
+                const double2 t0 = Rl[(k + 1) * WR + t], t1 = Rl[p * WR + t];
+                Rl[(k + 1) * WR + t] = t1;
+                Rl[p * WR + t] = t0;
             }
             __syncthreads();
-            if (l < n) {
-                const double2 t0 = Rl[l * WR + k + 1], t1 = Rl[l * WR + p];
-                Rl[l * WR + k + 1] = t1;
-                Rl[l * WR + p] = t0;
+            if (t < n) {
+                const double2 t0 = Rl[t * WR + k + 1], t1 = Rl[t * WR + p];
+                Rl[t * WR + k + 1] = t1;
+                Rl[t * WR + p] = t0;
             }
             __syncthreads();
             pfk = c_neg(pfk);
@@ -205,19 +210,19 @@ __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const 
         const double2 *r1 = Rl + (k + 1) * WR;
 #pragma unroll
         for (int q = 0; q < NTQ; ++q) {
-            if (l + 64 * q < NT2) {
+            if (t + NTH * q < NT2) {
                 const int ca_ = n + ta[q], cb_ = n + tb[q];
-                const double2 t = c_sub(c_mul(r1[ca_], r0[cb_]), c_mul(r0[ca_], r1[cb_]));
-                tv[q] = c_fma(t, ia, tv[q]);
+                const double2 tt = c_sub(c_mul(r1[ca_], r0[cb_]), c_mul(r0[ca_], r1[cb_]));
+                tv[q] = c_fma(tt, ia, tv[q]);
             }
         }
-        // rows i in [k+2, n), columns j in [k+2, WR); lane halves take alternate
-        // rows: R[i][j] += R[k+1][i] tau_j - R[k][i] sigma_j with the scaled
-        // pivot rows tau = R[k] / a, sigma = R[k+1] / a
-        const int h = l >> 5;
-        for (int j = k + 2 + (l & 31); j < WR; j += 32) {
+        // rows i in [k+2, n), columns j in [k+2, WR); groups of 32 threads take
+        // alternate rows: R[i][j] += R[k+1][i] tau_j - R[k][i] sigma_j with the
+        // scaled pivot rows tau = R[k] / a, sigma = R[k+1] / a
+        const int h = t >> 5;
+        for (int j = k + 2 + (t & 31); j < WR; j += 32) {
             const double2 tau = c_mul(r0[j], ia), nsig = c_neg(c_mul(r1[j], ia));
-            for (int i = k + 2 + h; i < n; i += 2) {
+            for (int i = k + 2 + h; i < n; i += NTH / 32) {
                 double2 *rij = Rl + i * WR + j;
                 *rij = c_fma(r1[i], tau, c_fma(r0[i], nsig, *rij));
             }
@@ -227,7 +232,7 @@ __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const 
     // growth of the unpivoted columns: at the end every row of R is the pivot
     // row it was when it was used, so its L and E entries are all there is to watch
     double gmax = 0.0;
-    for (int e = l; e < n * 2 * NE; e += 64) {
+    for (int e = t; e < n * 2 * NE; e += NTH) {
         const int i = e / (2 * NE), c = e - i * (2 * NE);
         gmax = fmax(gmax, c_abs2(Rl[i * WR + n + c]));
     }
@@ -235,6 +240,12 @@ __device__ __forceinline__ bool elim_bordered(int n, int WR, double2 *Rl, const 
 #pragma unroll
     for (int q = 0; q < NTQ; ++q) tmax = fmax(tmax, c_abs2(tv[q]));
     tmax = wave_max(fmax(tmax, gmax));
+    if constexpr (NTH == 128) {
+        if (l == 0) xred[t >> 6] = tmax;
+        __syncthreads();
+        tmax = fmax(xred[0], xred[1]);
+        __syncthreads();
+    }
     const bool flag = zero || !(tmax <= SO_SCHUR_GROWTH * SO_SCHUR_GROWTH * fmax(bmax, 1.0));
     if (perm) *perm = pi;
     return flag;

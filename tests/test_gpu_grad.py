@@ -198,6 +198,36 @@ def test_grad_full_size_route(B):
     print(f"full-size route: worst D {ed:.2e}, G {eg:.2e} (relative to max per walker)")
 
 
+@pytest.mark.parametrize("n,eta", [(8, 4), (16, 8)])
+def test_grad_full_size_route_then_ordinary_pairs(B, n, eta):
+    """A pair on the full-size route followed, in the same shadow range, by
+    ordinary pairs (the two waves of a workgroup must leave the route in step):
+    1,024 copies of one walker over 8 ranges of 100 shadows, the first of each
+    range near a pair-preserving rotation, must all give the same bits, and
+    those must match the oracle."""
+    import scipy.linalg as sla
+    W, Gy, spw = 1024, 8, 100
+    base = wl.make("fr", n, eta, 1, Gy * spw, seed=4100 + n)
+    rng = np.random.default_rng(4200 + n)
+    Q = base.Q.copy()
+    for r in range(Gy):
+        hm = rng.standard_normal((2 * n, 2 * n))
+        Q[r * spw] = sla.expm(1e-6 * (hm - hm.T))
+    ph1, Qd, bd = to_dev(base.phi, Q, base.bits)
+    B.shadow_overlap(ph1, Qd, bd)
+    routed = B.fallback_count(ph1, Qd, bd)
+    assert routed >= Gy // 2                       # the route opens most ranges
+    phi = np.repeat(base.phi, W, axis=0)
+    sg, dg, gg, st = gpu_grad(B, phi, Q, base.bits)
+    assert not (st & ~B.SO_WSTAT_SINGULAR).any()
+    for x in (sg, dg, gg, st):
+        assert (x == x[:1]).all(), "copies of one walker differ"
+    so, do, go = oracle.grad(base.phi, Q, base.bits)
+    assert np.all(np.abs(sg[:1] - so) <= 1e-9 * np.abs(so))
+    ed, eg = close_per_walker(dg[:1], do, 1e-10), close_per_walker(gg[:1], go, 1e-10)
+    print(f"n={n}: full-size route first in {routed} of {Gy} ranges, 1024 copies equal; D {ed:.2e}, G {eg:.2e}")
+
+
 def test_grad_zero_overlap_is_flagged(B):
     """Walkers whose orbitals are single modes, with the identity shadow and
     b = 0, give pair values that are exactly zero, so S_w = 0: the walker is
