@@ -15,8 +15,13 @@
 //   Abar_KL = -pfk Z,        Z  = Y0 A_0 + Y1 A_1,
 //   Abar_LK =  pfk Z^T,
 //   Abar_KK = o B_KK^{-1} + pfk (Z Y0^T + Z' Y1^T),   Z' = Y0 A_1 + Y1 A_2.
-// Y0, Y1 and B_KK^{-1} come from one Gauss-Jordan pass over
-// [B_KK | B_KL | J_KL | I]; the N_j from Gauss-Jordan passes over [M_j | I].
+// Y0, Y1 and B_KK^{-1} come from the pivoted elimination of K and a back
+// substitution; the N_j from Gauss-Jordan passes over [M_j | I].  Each node's
+// Pf(M_j) weights both its N_j and its share of o, so the large parts of
+// o B_KK^{-1} and Y N Y^T cancel node by node when B_KK is ill conditioned
+// (interpolating Pf(M) N from ne - 1 other nodes, a polynomial of degree
+// ne - 2, saves a node pass but loses that pairing: measured up to 1e-10
+// relative error in Abar where the per-node sums stay near 1e-13).
 // A pair whose elimination is flagged (so_pair.h) takes the full-size route:
 // Pf and inverse of every B + e_j J.
 //
@@ -150,10 +155,10 @@ __device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int 
 
 // LDS regions of k_grad_pair (bytes), in order RP, RB, RR, RG, RS.
 //   RP: P, then the node inverses N_j (they may run on into RB), then Abar;
-//   RB: B, then the back substitution's solution rows;
+//   RB: B, then the back substitution's solution rows (n x (n + 2NE + 1));
 //   RR: the rows K of Z, then the trailing block, then A_0, A_1, A_2 and Z, Z';
-//   RG: Y0, Y1 and B_KK^{-1};
-//   RS: M0, M1, M2, Pf(M_j), the pivot permutation and cross-wave scratch.
+//   RG: [Y0 | Y1 | B_KK^{-1}] (n x (n + 2NE + 1));
+//   RS: M0, M1, M2, Pf(M(e_j)), the pivot permutation and cross-wave scratch.
 // The full-size route's [B + cJ | I] (m x 2m) and its Householder vectors span
 // RR and RG.
 struct GradLds {
@@ -164,17 +169,18 @@ __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
     GradLds g;
     auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
     g.rp = al((size_t)LDP * LDP * sizeof(double));
-    g.rb = al((size_t)m * m * sizeof(double2));
-    if (g.rb > g.rp) g.rp = g.rb;
+    const size_t wrows = (size_t)n * (n + 2 * NE + 1);   // solution rows (padded stride)
+    g.rb = al(((size_t)m * m > wrows ? (size_t)m * m : wrows) * sizeof(double2));
+    if (al((size_t)m * m * sizeof(double2)) > g.rp) g.rp = al((size_t)m * m * sizeof(double2));
     size_t rr = (size_t)n * (n + 2 * NE);
     if ((size_t)NE * (2 * NE - 1) > rr) rr = (size_t)NE * (2 * NE - 1);
     if ((size_t)3 * NE * NE + 2 * n * NE > rr) rr = (size_t)3 * NE * NE + 2 * n * NE;
     g.rr = al(rr * sizeof(double2));
-    size_t rg = (size_t)n * (2 * n + 2 * NE);
+    size_t rg = (size_t)n * (n + 2 * NE + 1);
     const size_t full = ((size_t)2 * m * m + 2 * m) * sizeof(double2);
     if (full > g.rr + rg * sizeof(double2)) rg = (full - g.rr + sizeof(double2) - 1) / sizeof(double2);
     g.rg = al(rg * sizeof(double2));
-    // M0, M1, M2, Pf(M_j), the permutation (n ints) and 4 doubles of scratch
+    // M0, M1, M2, Pf(M(e_j)), the permutation (n ints) and 4 doubles of scratch
     g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1)) * sizeof(double2) + SO_GRAD_NMAX * sizeof(int) +
               4 * sizeof(double));
     g.total = g.rp + g.rb + g.rr + g.rg + g.rs;
@@ -199,7 +205,9 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
     constexpr int NTQ = (NT2 + NTH - 1) / NTH;
     constexpr int KK = 4 * T;
     constexpr int TM = (8 * T + NE + 15) / 16;              // 16-row tiles of F^T (m = n + NE <= 8T + NE)
-    const int m = n + NE, d = 2 * n, WR = n + 2 * NE, GW = 2 * n + 2 * NE;
+    // GW, SWP: row strides of RG and of the solution rows, odd in complex
+    // entries so that a column read by consecutive rows spreads over the banks
+    const int m = n + NE, d = 2 * n, WR = n + 2 * NE, GW = n + 2 * NE + 1, SWP = n + 2 * NE + 1;
     const int t0 = threadIdx.x, wv = t0 >> 6, w = blockIdx.x;
     extern __shared__ double lds[];
     const GradLds L = grad_lds(T, n, NE);
@@ -212,7 +220,7 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
     double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr);
     double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr + L.rg);
     double2 *Mup = RS;                       // M0, M1, M2 upper triangles
-    double2 *pfm = RS + 3 * NT;              // Pf(M_j)
+    double2 *pfm = RS + 3 * NT;              // Pf(M(e_j))
     int *pis = reinterpret_cast<int *>(pfm + KE);
     double *xred = reinterpret_cast<double *>(pis + SO_GRAD_NMAX);
     double2 *Ahat = RR;                      // A_0, A_1, A_2 (NE x NE each)
@@ -335,21 +343,20 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
                     if (l < n) pis[l] = perm;
 #pragma unroll
                     for (int i = 0; i < NRM; ++i)
-                        if (i < n && l < SW) RB[i * SW + l] = rhs[i];
+                        if (i < n && l < SW) RB[i * SWP + l] = rhs[i];
                 }
                 __syncthreads();
                 for (int e = t; e < n * 2 * NE; e += NTH) {
                     const int i = e / (2 * NE), c = e - i * (2 * NE);
-                    const double2 v = RB[i * SW + c];
-                    RG[pis[i] * GW + (c < NE ? n + c : m + (c - NE))] = v;
+                    RG[pis[i] * GW + c] = RB[i * SWP + c];
                 }
                 for (int e = t; e < n * n; e += NTH) {
                     const int i = e / n, j = e - i * n;
-                    const double2 *wi = RB + i * SW + 2 * NE, *wj = RB + j * SW + 2 * NE;
+                    const double2 *wi = RB + i * SWP + 2 * NE, *wj = RB + j * SWP + 2 * NE;
                     double2 acc = c_make(0.0, 0.0);
                     for (int k = 0; k < n; k += 2)
                         acc = c_fma(RR[k * WR + k + 1], c_sub(c_mul(wi[k], wj[k + 1]), c_mul(wi[k + 1], wj[k])), acc);
-                    RG[pis[i] * GW + m + NE + pis[j]] = c_neg(acc);
+                    RG[pis[i] * GW + 2 * NE + pis[j]] = c_neg(acc);
                 }
                 __syncthreads();
             }
@@ -405,12 +412,12 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
             }
             __syncthreads();
             // ---------------- Z, Z' (n x NE)
-            // Y0 = RG[:, n:m], Y1 = RG[:, m:m+NE], B_KK^{-1} = RG[:, m+NE:m+NE+n]
+            // Y0 = RG[:, 0:NE], Y1 = RG[:, NE:2NE], B_KK^{-1} = RG[:, 2NE:2NE+n]
             for (int e = t; e < n * NE; e += NTH) {
                 const int i = e / NE, x = e - i * NE;
                 double2 z = c_make(0, 0), zp = c_make(0, 0);
                 for (int y = 0; y < NE; ++y) {
-                    const double2 y0 = RG[i * GW + n + y], y1 = RG[i * GW + m + y];
+                    const double2 y0 = RG[i * GW + y], y1 = RG[i * GW + NE + y];
                     z = c_fma(y0, Ahat[y * NE + x], c_fma(y1, Ahat[NE * NE + y * NE + x], z));
                     zp = c_fma(y0, Ahat[NE * NE + y * NE + x], c_fma(y1, Ahat[2 * NE * NE + y * NE + x], zp));
                 }
@@ -425,9 +432,9 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
                 if (i < n && j < n) {
                     double2 acc = c_make(0, 0);
                     for (int x = 0; x < NE; ++x)
-                        acc = c_fma(Zr[i * NE + x], RG[j * GW + n + x],
-                                    c_fma(Zr[n * NE + i * NE + x], RG[j * GW + m + x], acc));
-                    v = c_fma(o, RG[i * GW + m + NE + j], c_mul(pfk, acc));
+                        acc = c_fma(Zr[i * NE + x], RG[j * GW + x],
+                                    c_fma(Zr[n * NE + i * NE + x], RG[j * GW + NE + x], acc));
+                    v = c_fma(o, RG[i * GW + 2 * NE + j], c_mul(pfk, acc));
                 } else if (i < n) {
                     v = c_neg(c_mul(pfk, Zr[i * NE + (j - n)]));
                 } else if (j < n) {
