@@ -23,7 +23,9 @@ workload with sampled pair errors against the oracle), ``grad`` (derivative
 and force bias, with its own oracle baseline), ``rdm1`` (density matrix from
 the shadows, HBM-bound), ``vce`` (full-space overlaps through the
 virtual-correlation-energy prologue), ``energy`` (local energies from the
-second Pfaffian derivatives, with its own oracle baseline) and ``uneven``
+second Pfaffian derivatives, with its own oracle baseline), ``perm`` (the
+main workload's size on random signed-permutation shadows, with the number
+of pairs that took the full-size path) and ``uneven``
 (four geometries in one batched call, graph-replayed, FP64 and mixed,
 beside separate calls).
 """
@@ -96,6 +98,35 @@ def cpu_baseline(w, target_s=24.0):
             "sample": f"all {w.W} walkers x first {s} of {w.S} shadows ({w.W * s} pairs, {dt:.1f} s)"}
 
 
+def grad_executed_flops_per_pair(n, eta):
+    """FP64 flops per pair that k_grad_pair executes in its own formulation
+    (each operation counted once, although both waves form P): complex
+    multiply-add = 8 flops, FP64 MFMA 16x16x4 = 2048.
+      formation  (T^2 + T(T+1)/2) 4T MFMAs (U = C' Xall^T, then the upper tiles of P)
+      elimination of K  rank-2 updates of the n x (n + 2ne) rows and the
+                 2ne x 2ne trailing block, 2 and 3 complex products per entry
+      back substitution  2ne + n right-hand sides through the n/2 pivot steps
+      B_KK^{-1}  -W D W^T, n/2 terms of 2.5 complex products per entry
+      nodes      ne + 1 pencil Pfaffians (ne^3/3 complex MACs) and
+                 Gauss-Jordan inverses of [M_j | I] (2 ne^3 complex MACs)
+      A_p, Z, Z', Abar  3 ne^2 (ne+1), 4 n ne^2 and 2 n^2 ne complex MACs
+      F          T^2 4T + 2T 4T ceil(m/16) MFMAs."""
+    T = -(-2 * n // 16)
+    ne, KK = n - eta, 4 * T
+    m, WR, KE = n + ne, n + 2 * ne, ne + 1
+    nt2 = ne * (2 * ne - 1)
+    TM = -(-m // 16)
+    mfma = 2048.0
+    form = (T * T + T * (T + 1) // 2) * KK * mfma
+    elim = sum(max(0, n - k - 2) * max(0, WR - k - 2) * 16.0 + nt2 * 24.0 for k in range(0, n, 2))
+    back = (2 * ne + n) * sum(16.0 * k for k in range(0, n, 2))
+    binv = n * n * (n // 2) * 20.0
+    nodes = KE * (8.0 * ne ** 3 / 3 + 16.0 * ne ** 3)
+    asm = 8.0 * (3 * ne * ne * KE + 4 * n * ne * ne + 2 * n * n * ne)
+    fmat = (T * T * KK + 2 * T * KK * TM) * mfma
+    return form + elim + back + binv + nodes + asm + fmat
+
+
 def grad_leg(args, B, wl, torch, np):
     """The derivative workload (N = 16, eta = 8, 1,024 walkers x 10,000
     shadows, 200 Cholesky-like vectors): one step = shadow_overlap_grad
@@ -129,6 +160,8 @@ def grad_leg(args, B, wl, torch, np):
           + 16.0 * g.n * m * m)
     kern_s = gms / 1e3 / glaunch
     achieved = fl * (gpairs / glaunch) / kern_s / 1e12
+    flx = grad_executed_flops_per_pair(g.n, g.eta)
+    executed = flx * (gpairs / glaunch) / kern_s / 1e12
     return {"metric": "grad evals/s", "value": g.W * g.S / per, "unit": "walker x shadow adjoint contributions/s",
             "walkers_per_s": g.W / per, "ms_per_step": per * 1e3, "steps": args.grad_steps,
             "config": {"workload": "grad_n16", "n": g.n, "eta": g.eta, "walkers": g.W, "shadows": g.S,
@@ -136,7 +169,36 @@ def grad_leg(args, B, wl, torch, np):
             "kernels": {"k_grad_pair": {"ms_per_step": gms / args.grad_steps}},
             "roofline": {"bound": "alu", "kernel": "k_grad_pair", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "flops_per_pair": fl,
+                         "executed_flops_per_pair": flx, "executed_tflops": executed,
+                         "executed_frac": executed / PEAK_FP64_TFLOPS,
                          "avg_launch_ms": kern_s * 1e3, "pairs_per_launch": gpairs / glaunch}}
+
+
+def perm_leg(args, B, wl, torch, np):
+    """The paper's shadow ensemble at the main workload's size: N = 16,
+    eta = 8, 1,024 walkers x 10,000 random signed-permutation shadows.  The
+    pairs whose elimination is flagged go through the full-size path in the
+    same call; their number is reported."""
+    w = wl.config("perm_n16")
+    dev = torch.device("cuda:0")
+    phi = torch.from_numpy(w.phi).to(dev)
+    Q = torch.from_numpy(w.Q).to(dev)
+    bits = torch.from_numpy(w.bits.view(np.int64)).to(dev)
+    B.shadow_overlap(phi, Q, bits)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.perm_steps):
+        out, _, status = B.shadow_overlap(phi, Q, bits)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / args.perm_steps
+    flagged = B.fallback_count(phi, Q, bits)
+    if int(status.abs().sum()) != 0 or not bool(torch.isfinite(out.real).all()):
+        raise RuntimeError("signed-permutation run reported a numerical status")
+    return {"metric": "walker x shadow overlaps/s, signed-permutation shadows", "value": w.W * w.S / per,
+            "unit": "overlaps/s", "ms_per_step": per * 1e3, "steps": args.perm_steps,
+            "full_size_path_pairs": flagged, "full_size_path_frac": flagged / (w.W * w.S),
+            "config": {"workload": "perm_n16", "n": w.n, "eta": w.eta, "walkers": w.W, "shadows": w.S,
+                       "shadow_family": "random signed permutations"}}
 
 
 def uneven_leg(args, B, wl, torch, np):
@@ -488,6 +550,8 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the derivative leg")
     ap.add_argument("--grad-steps", type=int, default=2)
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--no-perm", action="store_true", help="skip the signed-permutation leg")
+    ap.add_argument("--perm-steps", type=int, default=3)
     ap.add_argument("--uneven-steps", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
     ap.add_argument("--no-rdm", action="store_true", help="skip the density-matrix leg")
@@ -599,23 +663,33 @@ def main():
         "path": {"flops_per_pair": pf_flops + fm_flops, "tflops": (pf_flops + fm_flops) * value / 1e12,
                  "frac": (pf_flops + fm_flops) * value / 1e12 / PEAK_FP64_TFLOPS},
     }
+    t_start = time.perf_counter()
+
+    def leg(key, fn, *a):
+        rec[key] = fn(*a)
+        print(f"bench: {key} leg done ({time.perf_counter() - t_start:.0f} s)", file=sys.stderr, flush=True)
+
+    print(f"bench: main leg done, {rec['ms_per_step']:.1f} ms per step", file=sys.stderr, flush=True)
     if not args.no_mixed:
-        rec["mixed"] = mixed_n16_leg(args, B, torch, phi, Q, bits, pairs_per_step, out)
-        rec["precision_n24"] = precision_leg(args, B, wl, torch, np)
+        leg("mixed", mixed_n16_leg, args, B, torch, phi, Q, bits, pairs_per_step, out)
+        leg("precision_n24", precision_leg, args, B, wl, torch, np)
     if not args.no_grad:
-        rec["grad"] = grad_leg(args, B, wl, torch, np)
+        leg("grad", grad_leg, args, B, wl, torch, np)
     if not args.no_rdm:
-        rec["rdm1"] = rdm_leg(args, B, wl, torch, np, Q, bits)
+        leg("rdm1", rdm_leg, args, B, wl, torch, np, Q, bits)
     if not args.no_vce:
-        rec["vce"] = vce_leg(args, B, wl, torch, np)
+        leg("vce", vce_leg, args, B, wl, torch, np)
     if not args.no_energy:
-        rec["energy"] = energy_leg(args, B, wl, torch, np)
+        leg("energy", energy_leg, args, B, wl, torch, np)
+    if not args.no_perm:
+        leg("perm", perm_leg, args, B, wl, torch, np)
     if not args.no_uneven:
-        rec["uneven"] = uneven_leg(args, B, wl, torch, np)
+        leg("uneven", uneven_leg, args, B, wl, torch, np)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(w)
+        leg("cpu_baseline", cpu_baseline, w)
         if "grad" in rec:
             rec["grad"]["cpu_baseline"] = cpu_grad_baseline(wl)
+            print("bench: grad cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(rec), flush=True)
 
 
