@@ -424,8 +424,12 @@ hipError_t launch_pair_tn(int n, int eta, const void *Xa, const void *Ca, int64_
     const int64_t ny = (S + spw - 1) / spw;
     for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
         const int64_t gy = (ny - y0) < 65535 ? (ny - y0) : 65535;
-        hipLaunchKernelGGL((k_pair<T, NE, MIX>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds, st, n, eta, Xa, Ca, S,
-                           y0, spw, rt, pairs, fbc, fbl, fb_cap, wst);
+        if (n == 8 * T)
+            hipLaunchKernelGGL((k_pair<T, NE, MIX, true>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds, st, n, eta,
+                               Xa, Ca, S, y0, spw, rt, pairs, fbc, fbl, fb_cap, wst);
+        else
+            hipLaunchKernelGGL((k_pair<T, NE, MIX, false>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds, st, n, eta,
+                               Xa, Ca, S, y0, spw, rt, pairs, fbc, fbl, fb_cap, wst);
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }
     return hipSuccess;

@@ -70,7 +70,7 @@ __device__ __forceinline__ void batch_item(const BatchJob &jb, int w, int64_t sb
 #define SO_BCASE(TT, NN)                                                                                       \
     case 16 * TT + NN:                                                                                         \
         if constexpr (pair_class_level(TT, NN, MIX) <= LEVEL)                                                \
-            pair_range<TT, NN, MIX>(jb.n, jb.eta, jb.Xa, jb.Ca, jb.S, jb.tab, jb.pairs, jb.fb_count, jb.fb_list, \
+            pair_range<TT, NN, MIX, false, true>(jb.n, jb.eta, jb.Xa, jb.Ca, jb.S, jb.tab, jb.pairs, jb.fb_count, jb.fb_list, \
                                     jb.fb_cap, jb.wstat, w, sb0, sb1);                                         \
         break;
     switch (jb.cls) {

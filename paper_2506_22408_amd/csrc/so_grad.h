@@ -278,7 +278,7 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
         const int l = t & 63;
         const double2 *Cs = Ca + (size_t)s * MAT2;
         // both waves form P (the same values; the formation is a few percent of a pair)
-        pair_formation<T, false>(Xw, Cs, RP, l, LDP);
+        pair_formation<T, false, true>(Xw, Cs, RP, l, LDP);
 
         // ---------------- B (m x m), then R = rows K of Z
         double bmax = 0.0;

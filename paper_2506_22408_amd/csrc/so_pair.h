@@ -109,8 +109,9 @@ __device__ __forceinline__ double2 pf_lane_from(double2 (&A)[N][N]) {
 // v_mfma_f64_16x16x4f64.  MIX = true: single-precision operands (float4
 // quads, C' rows in the order sig16) on v_mfma_f32_16x16x4f32 with
 // single-precision accumulation; P is widened to FP64 when it is stored and
-// everything after the formation runs in FP64.
-template <int T, bool MIX>
+// everything after the formation runs in FP64.  FULL: ld = 16 T + 1 (2n =
+// DP), so every tile entry is stored without a bounds test.
+template <int T, bool MIX, bool FULL = false>
 __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, const void *__restrict__ Cv,
                                                double *Pl, int l, int ld) {
     constexpr int KK = 4 * T;
@@ -134,7 +135,7 @@ __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, cons
             for (int r = 0; r < 4; ++r) {
                 const int a = p_row(P[I][J], I, r, l), bcol = 16 * J + (l & 15);
                 const double v = (double)P[I][J][r];
-                if (a < z && bcol < z) {
+                if (FULL || (a < z && bcol < z)) {
                     Pl[a * ld + bcol] = v;
                     if (J > I) Pl[bcol * ld + a] = -v;   // P is antisymmetric
                 }
@@ -310,8 +311,11 @@ __host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
 // Pfaffians and the pair values pairs[w S_total + s].  One wave; the LDS
 // layout is pair_lds_bytes(T, n, NE).  Xa and Ca hold the walker and shadow
 // matrices in FP64 (MIX = false) or single precision (MIX = true), DP x DP
-// elements each, in the formation's operand order.
-template <int T, int NE, bool MIX>
+// elements each, in the formation's operand order.  FULL: n = 8 T, so P's
+// row stride is the compile-time 16 T + 1 and its stores need no bounds
+// test (measured 1.6% of k_pair at n = 16 and 3.5% at n = 24).  OPAQUE_LANE:
+// see below.
+template <int T, int NE, bool MIX, bool FULL, bool OPAQUE_LANE>
 __device__ __forceinline__ void pair_range(int n, int eta, const void *__restrict__ Xa,
                                            const void *__restrict__ Ca, int64_t S_total, const RedTab &tab,
                                            double2 *__restrict__ pairs, so_u64 *__restrict__ fb_count,
@@ -330,7 +334,8 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
     double2 *Rl = reinterpret_cast<double2 *>(lds);
     double2 *Tl = reinterpret_cast<double2 *>(lds);
     double2 *Vl = reinterpret_cast<double2 *>(lds);
-    const int LDP = 2 * n + 1;   // P is (2n + 1) x (2n + 1); row and column 2n are zero
+    // P is (2n + 1) x (2n + 1); row and column 2n are zero
+    const int LDP = FULL ? DP + 1 : 2 * n + 1;
     size_t abytes = (size_t)LDP * LDP * sizeof(double);
     {
         const size_t r = (size_t)n * (n + 2 * NE) * sizeof(double2);
@@ -342,11 +347,12 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
     }
     double2 *Bt = reinterpret_cast<double2 *>(reinterpret_cast<char *>(lds) + abytes);   // batch slots
 
-    // the lane index through an opaque move: nothing derived from it can be
-    // hoisted out of a caller's loop over work items (where it would stay live
-    // beside the other kernel classes' state in the batch kernel)
+    // in the batch kernel, the lane index through an opaque move: nothing
+    // derived from it can be hoisted out of the loop over work items (where
+    // it would stay live beside the other kernel classes' state); the plain
+    // kernel keeps the hoisting (measured 1% faster at n = 16)
     int l = threadIdx.x;
-    asm volatile("" : "+v"(l));
+    if constexpr (OPAQUE_LANE) asm volatile("" : "+v"(l));
     const int WR = n + 2 * NE;              // columns of R: K (n), L (NE), E (NE)
 
     // this lane's trailing entries (a < b) of the 2NE x 2NE block
@@ -376,7 +382,7 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
         for (int b = 0; b < nb; ++b) {
             const int64_t s = bs + b;
             // ---------------- formation: P = Xall C' Xall^T
-            pair_formation<T, MIX>(Xw, static_cast<const char *>(Ca) + (size_t)s * MATB, Pl, l, LDP);
+            pair_formation<T, MIX, FULL>(Xw, static_cast<const char *>(Ca) + (size_t)s * MATB, Pl, l, LDP);
 
             // ---------------- R = rows K of Z, trailing T = [[B_LL, 0], [0, 0]]
             constexpr int RPL = (8 * T * (8 * T + NE) + 63) / 64;   // B entries of R per lane (n <= 8 T)
@@ -542,7 +548,7 @@ __host__ __device__ constexpr int pair_class_level(int T, int NE, bool mix) {
 // spw is a multiple of pair_node_batch(NE).  Three waves per SIMD for the
 // classes of level 0, two otherwise (the three-tile instances would take
 // more than 256 registers).
-template <int T, int NE, bool MIX>
+template <int T, int NE, bool MIX, bool FULL>
 __global__ __launch_bounds__(64, pair_class_level(T, NE, MIX) == 0 ? 3 : 2) void k_pair(int n, int eta, const void *__restrict__ Xa,
                                              const void *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
                                              RedTab tab, double2 *__restrict__ pairs,
@@ -550,6 +556,6 @@ __global__ __launch_bounds__(64, pair_class_level(T, NE, MIX) == 0 ? 3 : 2) void
                                              int64_t fb_cap, int32_t *__restrict__ wstat) {
     const int64_t sb0 = (sy0 + blockIdx.y) * (int64_t)spw;
     const int64_t sb1 = min(S_total, sb0 + spw);
-    pair_range<T, NE, MIX>(n, eta, Xa, Ca, S_total, tab, pairs, fb_count, fb_list, fb_cap, wstat, (int)blockIdx.x, sb0,
-                      sb1);
+    pair_range<T, NE, MIX, FULL, false>(n, eta, Xa, Ca, S_total, tab, pairs, fb_count, fb_list, fb_cap, wstat,
+                                        (int)blockIdx.x, sb0, sb1);
 }
