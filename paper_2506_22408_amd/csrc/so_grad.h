@@ -378,6 +378,7 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
             const int g8 = t >> 4, q16 = t & 15;
             bool sing = false;
             for (int j0 = 0; j0 < KE; j0 += 8) {
+                if (j0 + 4 * wv >= KE) break;   // no node for this wave's rows (no barrier in the pass)
                 const int j = j0 + g8;
                 const double2 cj = tab.e[j < KE ? j : KE - 1];
                 const double2 pf = pencil_pf_row<NE>(Mup, cj, q16);
