@@ -154,11 +154,13 @@ __device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int 
 }
 
 // LDS regions of k_grad_pair (bytes), in order RP, RB, RR, RG, RS.
-//   RP: P, then the node inverses N_j (they may run on into RB), then Abar;
+//   RP: P, then the trailing block (the pencil's source), then the node
+//       inverses N_j, then Abar;
 //   RB: B, then the back substitution's solution rows (n x (n + 2NE + 1));
-//   RR: the rows K of Z, then the trailing block, then A_0, A_1, A_2 and Z, Z';
+//   RR: the rows K of Z, then A_0, A_1, A_2 and Z, Z';
 //   RG: [Y0 | Y1 | B_KK^{-1}] (n x (n + 2NE + 1));
-//   RS: M0, M1, M2, Pf(M(e_j)), the pivot permutation and cross-wave scratch.
+//   RS: M0, M1, M2, Pf(M(e_j)), the pivots of B_KK, the pivot permutation and
+//       cross-wave scratch.
 // The full-size route's [B + cJ | I] (m x 2m) and its Householder vectors span
 // RR and RG.
 struct GradLds {
@@ -172,17 +174,19 @@ __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
     const size_t wrows = (size_t)n * (n + 2 * NE + 1);   // solution rows (padded stride)
     g.rb = al(((size_t)m * m > wrows ? (size_t)m * m : wrows) * sizeof(double2));
     if (al((size_t)m * m * sizeof(double2)) > g.rp) g.rp = al((size_t)m * m * sizeof(double2));
+    if (al((size_t)NE * (2 * NE - 1) * sizeof(double2)) > g.rp) g.rp = al((size_t)NE * (2 * NE - 1) * sizeof(double2));
+    // the node inverses are written while the first wave fills RB: RP holds them all
+    if (al((size_t)(NE + 1) * NE * NE * sizeof(double2)) > g.rp) g.rp = al((size_t)(NE + 1) * NE * NE * sizeof(double2));
     size_t rr = (size_t)n * (n + 2 * NE);
-    if ((size_t)NE * (2 * NE - 1) > rr) rr = (size_t)NE * (2 * NE - 1);
     if ((size_t)3 * NE * NE + 2 * n * NE > rr) rr = (size_t)3 * NE * NE + 2 * n * NE;
     g.rr = al(rr * sizeof(double2));
     size_t rg = (size_t)n * (n + 2 * NE + 1);
     const size_t full = ((size_t)2 * m * m + 2 * m) * sizeof(double2);
     if (full > g.rr + rg * sizeof(double2)) rg = (full - g.rr + sizeof(double2) - 1) / sizeof(double2);
     g.rg = al(rg * sizeof(double2));
-    // M0, M1, M2, Pf(M(e_j)), the permutation (n ints) and 4 doubles of scratch
-    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1)) * sizeof(double2) + SO_GRAD_NMAX * sizeof(int) +
-              4 * sizeof(double));
+    // M0, M1, M2, Pf(M(e_j)), the pivots, the permutation (n ints) and 4 doubles of scratch
+    g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1) + SO_GRAD_NMAX / 2) * sizeof(double2) +
+              SO_GRAD_NMAX * sizeof(int) + 4 * sizeof(double));
     g.total = g.rp + g.rb + g.rr + g.rg + g.rs;
     return g;
 }
@@ -221,7 +225,8 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
     double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr + L.rg);
     double2 *Mup = RS;                       // M0, M1, M2 upper triangles
     double2 *pfm = RS + 3 * NT;              // Pf(M(e_j))
-    int *pis = reinterpret_cast<int *>(pfm + KE);
+    double2 *piv = pfm + KE;                 // the pivots a of B_KK's 2 x 2 blocks
+    int *pis = reinterpret_cast<int *>(piv + SO_GRAD_NMAX / 2);
     double *xred = reinterpret_cast<double *>(pis + SO_GRAD_NMAX);
     double2 *Ahat = RR;                      // A_0, A_1, A_2 (NE x NE each)
     double2 *Zr = RR + 3 * NE * NE;          // Z, Z' (n x NE each)
@@ -309,77 +314,31 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
         const bool flag = elim_bordered<NE, NTQ, NTH>(n, WR, RR, ta, tb, tv, bmax, rbmax, t, pfk, &perm, xred);
         double2 o = c_make(0.0, 0.0);
         if (!flag) {
-            // ---------------- Y0, Y1, B_KK^{-1} by back substitution with the pivot rows
-            // U [Y' | W] = [R_LE | I] in the pivoted order (U = the rows of R, block
-            // upper triangular with pivots [[0, a], [-a, 0]]); then, with pi the
-            // permutation, Y[pi(i)] = Y'[i] and B_KK^{-1}[pi(i)][pi(j)] = (-W D W^T)[i][j]
-            // (P B_KK P^T = L D L^T = -U^T D^{-1} U).  Lane c < 2NE + n of wave 0
-            // holds column c of the right-hand side; the solution goes to RB (free:
-            // the full-size route is ruled out) and then, reordered, to RG.
-            {
-                constexpr int NRM = 8 * T;
-                const int SW = 2 * NE + n;
-                if (wv == 0) {
-                    double2 rhs[NRM];
-#pragma unroll
-                    for (int i = 0; i < NRM; ++i) {
-                        rhs[i] = c_make(0.0, 0.0);
-                        if (i < n && l < SW)
-                            rhs[i] = l < 2 * NE ? RR[i * WR + n + l] : c_make(i == l - 2 * NE ? 1.0 : 0.0, 0.0);
-                    }
-#pragma unroll
-                    for (int bb = 0; bb < NRM / 2; ++bb) {
-                        const int k = NRM - 2 - 2 * bb;
-                        if (k < n) {
-                            const double2 ia = c_inv_nr(RR[k * WR + k + 1]);
-                            const double2 yk1 = c_mul(rhs[k], ia), yk = c_neg(c_mul(rhs[k + 1], ia));
-                            rhs[k] = yk;
-                            rhs[k + 1] = yk1;
-#pragma unroll
-                            for (int i = 0; i < k; ++i)
-                                rhs[i] = c_fma(c_neg(RR[i * WR + k]), yk, c_fma(c_neg(RR[i * WR + k + 1]), yk1, rhs[i]));
-                        }
-                    }
-                    if (l < n) pis[l] = perm;
-#pragma unroll
-                    for (int i = 0; i < NRM; ++i)
-                        if (i < n && l < SW) RB[i * SWP + l] = rhs[i];
-                }
-                __syncthreads();
-                for (int e = t; e < n * 2 * NE; e += NTH) {
-                    const int i = e / (2 * NE), c = e - i * (2 * NE);
-                    RG[pis[i] * GW + c] = RB[i * SWP + c];
-                }
-                for (int e = t; e < n * n; e += NTH) {
-                    const int i = e / n, j = e - i * n;
-                    const double2 *wi = RB + i * SWP + 2 * NE, *wj = RB + j * SWP + 2 * NE;
-                    double2 acc = c_make(0.0, 0.0);
-                    for (int k = 0; k < n; k += 2)
-                        acc = c_fma(RR[k * WR + k + 1], c_sub(c_mul(wi[k], wj[k + 1]), c_mul(wi[k + 1], wj[k])), acc);
-                    RG[pis[i] * GW + 2 * NE + pis[j]] = c_neg(acc);
-                }
-                __syncthreads();
-            }
+            // ---------------- the pencil M0, M1, M2 from the trailing block, staged
+            // through RP (P is no longer needed)
+            double2 *TT = reinterpret_cast<double2 *>(RP);
 #pragma unroll
             for (int q = 0; q < NTQ; ++q)
-                if (t + NTH * q < NT2) RR[t + NTH * q] = tv[q];
+                if (t + NTH * q < NT2) TT[t + NTH * q] = tv[q];
             __syncthreads();
             auto tix = [&](int a, int bb) -> int { return a * (2 * NE - 1) - a * (a - 1) / 2 + (bb - a - 1); };
             for (int e = t; e < NT; e += NTH) {
                 int x = 0, r = e;
                 while (r >= NE - 1 - x) { r -= NE - 1 - x; ++x; }
                 const int y = x + 1 + r;
-                Mup[e] = RR[tix(x, y)];
-                Mup[NT + e] = c_sub(RR[tix(x, NE + y)], RR[tix(y, NE + x)]);
-                Mup[2 * NT + e] = RR[tix(NE + x, NE + y)];
+                Mup[e] = TT[tix(x, y)];
+                Mup[NT + e] = c_sub(TT[tix(x, NE + y)], TT[tix(y, NE + x)]);
+                Mup[2 * NT + e] = TT[tix(NE + x, NE + y)];
             }
             __syncthreads();
-            // Pf(M_j) and N_j = M_j^{-1}: eight nodes per pass, one per 16-lane row
-            const int g8 = t >> 4, q16 = t & 15;
+            // ---------------- two things at once, with no barrier in either:
+            // wave 0 solves for Y0, Y1 and B_KK^{-1} (back substitution with the
+            // pivot rows) and then takes the estimator nodes from 8 on; wave 1 takes
+            // Pf(M_j) and N_j = M_j^{-1} of nodes 0..7, four per pass (one per
+            // 16-lane row).  The nodes do not depend on the solve.
+            const int g4 = (t >> 4) & 3, q16 = t & 15;
             bool sing = false;
-            for (int j0 = 0; j0 < KE; j0 += 8) {
-                if (j0 + 4 * wv >= KE) break;   // no node for this wave's rows (no barrier in the pass)
-                const int j = j0 + g8;
+            auto node_pass = [&](int j) {
                 const double2 cj = tab.e[j < KE ? j : KE - 1];
                 const double2 pf = pencil_pf_row<NE>(Mup, cj, q16);
                 if (q16 == 0 && j < KE) pfm[j] = pf;
@@ -394,12 +353,64 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
                         for (int x = 0; x < NE; ++x) NJ[(j * NE + x) * NE + y] = col[x];
                     }
                 }
+            };
+            // U [Y' | W] = [R_LE | I] in the pivoted order (U = the rows of R, block
+            // upper triangular with pivots [[0, a], [-a, 0]]); then, with pi the
+            // permutation, Y[pi(i)] = Y'[i] and B_KK^{-1}[pi(i)][pi(j)] = (-W D W^T)[i][j]
+            // (P B_KK P^T = L D L^T = -U^T D^{-1} U).  Lane c < 2NE + n of wave 0
+            // holds column c of the right-hand side; the solution goes to RB (free:
+            // the full-size route is ruled out) and then, reordered, to RG.
+            constexpr int NRM = 8 * T;
+            const int SW = 2 * NE + n;
+            if (wv == 0) {
+                double2 rhs[NRM];
+#pragma unroll
+                for (int i = 0; i < NRM; ++i) {
+                    rhs[i] = c_make(0.0, 0.0);
+                    if (i < n && l < SW)
+                        rhs[i] = l < 2 * NE ? RR[i * WR + n + l] : c_make(i == l - 2 * NE ? 1.0 : 0.0, 0.0);
+                }
+#pragma unroll
+                for (int bb = 0; bb < NRM / 2; ++bb) {
+                    const int k = NRM - 2 - 2 * bb;
+                    if (k < n) {
+                        const double2 a = RR[k * WR + k + 1];
+                        if (l == 0) piv[k / 2] = a;
+                        const double2 ia = c_inv_nr(a);
+                        const double2 yk1 = c_mul(rhs[k], ia), yk = c_neg(c_mul(rhs[k + 1], ia));
+                        rhs[k] = yk;
+                        rhs[k + 1] = yk1;
+#pragma unroll
+                        for (int i = 0; i < k; ++i)
+                            rhs[i] = c_fma(c_neg(RR[i * WR + k]), yk, c_fma(c_neg(RR[i * WR + k + 1]), yk1, rhs[i]));
+                    }
+                }
+                if (l < n) pis[l] = perm;
+#pragma unroll
+                for (int i = 0; i < NRM; ++i)
+                    if (i < n && l < SW) RB[i * SWP + l] = rhs[i];
+                for (int j0 = 8; j0 < KE; j0 += 4) node_pass(j0 + g4);
+            } else {
+                for (int j0 = 0; j0 < (KE < 8 ? KE : 8); j0 += 4) node_pass(j0 + g4);
             }
             if (sing) wflags |= SO_WSTAT_SINGULAR;
             __syncthreads();
+            for (int e = t; e < n * 2 * NE; e += NTH) {
+                const int i = e / (2 * NE), c = e - i * (2 * NE);
+                RG[pis[i] * GW + c] = RB[i * SWP + c];
+            }
+            for (int e = t; e < n * n; e += NTH) {
+                const int i = e / n, j = e - i * n;
+                const double2 *wi = RB + i * SWP + 2 * NE, *wj = RB + j * SWP + 2 * NE;
+                double2 acc = c_make(0.0, 0.0);
+                for (int k = 0; k < n; k += 2)
+                    acc = c_fma(piv[k / 2], c_sub(c_mul(wi[k], wj[k + 1]), c_mul(wi[k + 1], wj[k])), acc);
+                RG[pis[i] * GW + 2 * NE + pis[j]] = c_neg(acc);
+            }
             for (int j = 0; j < KE; ++j) o = c_fma(tab.v[j], pfm[j], o);
             o = c_mul(o, pfk);
-            // ---------------- A_p = sum_j v_j Pf(M_j) e_j^p N_j (p = 0, 1, 2)
+            // ---------------- A_p = sum_j v_j Pf(M_j) e_j^p N_j (p = 0, 1, 2), in the
+            // same phase (the node results were complete at the last barrier)
             for (int e = t; e < 3 * NE * NE; e += NTH) {
                 const int pw = e / (NE * NE), xy = e - pw * NE * NE;
                 double2 acc = c_make(0.0, 0.0);
