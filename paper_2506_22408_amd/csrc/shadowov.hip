@@ -281,7 +281,7 @@ void build_nodetab(const so_params *p, int K, NodeTab *t) {
 }
 
 constexpr size_t kSChunkBytes = (size_t)512 << 20;   // budget for one chunk of S matrices
-constexpr int FB_GRID = 256;                           // blocks of the fallback kernel
+constexpr int FB_GRID = 2048;                          // blocks of the fallback kernel
 constexpr int kFormShadowsPerWave = 8;                 // shadows per formation wave
 constexpr int kPairBatchesPerWave = 2;                 // node batches per fused wave
 #ifndef SO_ROW_BATCHES_PER_WAVE
@@ -291,7 +291,7 @@ constexpr int kRowBatchesPerWave = SO_ROW_BATCHES_PER_WAVE;   // the same for ne
 constexpr int64_t kRdmBlocks = 2048;                    // blocks of the density-matrix reduction
 
 struct Layout {
-    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_fbB, off_F, off_O;
+    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_F, off_O;
     size_t off_X32, off_C32;   // single-precision formation operands (mixed precision)
     size_t total;
     int Sc;
@@ -340,7 +340,6 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false,
     L.off_stat = o; o = align_up(o + (size_t)W * sizeof(int32_t));
     L.off_fbc = o; o = align_up(o + sizeof(so_u64));
     L.off_fbl = o; o = align_up(o + (size_t)cap * sizeof(int64_t));
-    L.off_fbB = o; o = align_up(o + (size_t)FB_GRID * m * m * sizeof(double2));
     L.Gy = 0;
     L.off_F = L.off_O = o;
     if (with_grad) {
@@ -543,7 +542,7 @@ struct ProbPlan {
     const double2 *phi;
     const double *Q;
     const uint64_t *bits;
-    double2 *overlap, *pairs, *Sb, *Pb, *fbB;
+    double2 *overlap, *pairs, *Sb, *Pb;
     const double2 *Xa, *Ca;   // FP64 operands (full-size path; formation unless mixed)
     double *Xw, *Cw;
     bool mix;                 // mixed precision: single-precision formation operands
@@ -593,7 +592,6 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
     P->wst = status ? status : reinterpret_cast<int32_t *>(ws + P->L.off_stat);
     P->fbc = reinterpret_cast<so_u64 *>(ws + P->L.off_fbc);
     P->fbl = reinterpret_cast<int64_t *>(ws + P->L.off_fbl);
-    P->fbB = reinterpret_cast<double2 *>(ws + P->L.off_fbB);
     return SO_OK;
 }
 
@@ -644,8 +642,16 @@ hipError_t enqueue_finish(const ProbPlan &P, hipStream_t st) {
     RedTab rt;
     std::memset(&rt, 0, sizeof(rt));
     for (int j = 0; j < P.tab.Ke; ++j) { rt.e[j] = P.tab.e[j]; rt.v[j] = P.tab.v[j]; }
-    hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), 0, st, P.n, P.eta, P.Xw, P.Cw, rt, P.tab.Ke, P.fbc,
-                       P.fbl, P.L.fb_cap, P.W, P.S, P.fbB, P.pairs);
+    // the largest shapes (n = 24, small eta) need more than the default 64 KiB
+    static const bool fb_attr = [] {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_fallback),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)fb_lds_bytes(SO_NMAX_SUPPORTED, 0));
+        return true;
+    }();
+    (void)fb_attr;
+    hipLaunchKernelGGL(k_fallback, dim3(FB_GRID), dim3(64), fb_lds_bytes(P.n, P.eta), st, P.n, P.eta, P.Xw, P.Cw,
+                       rt, P.tab.Ke, P.fbc, P.fbl, P.L.fb_cap, P.W, P.S, P.pairs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)P.W), dim3(64), 0, st, P.pairs, P.S, P.overlap, P.wst,

@@ -1,7 +1,9 @@
 // so_fallback.h -- full-size path for the pairs whose elimination met a zero
-// pivot or too much growth (so_pair.h, so_form.h).  Rare and simple:
-// recompute B = X C' X^T for the pair, then for every node e_j of the reduced
-// table the Pfaffian of B + e_j J (m x m, J materialised) by Householder
+// pivot or too much growth (so_pair.h, so_form.h).  Rare on Haar shadows;
+// on signed-permutation shadows with single-mode walkers (the first steps of
+// a run on the paper's ensemble) most pairs land here, so the operands are
+// staged in LDS once per pair.  For every node e_j of the reduced table it
+// takes the Pfaffian of B + e_j J (m x m, J materialised) by Householder
 // tridiagonalisation with the matrix in LDS, lane = row, and the pair value
 // o = sum_j v_j Pf(B + e_j J).  Q(c) = Pf(B + c J) has degree ne = n - eta in
 // c, so its values at the ne + 1 nodes of the table determine the estimator
@@ -63,36 +65,66 @@ __device__ __forceinline__ double2 hh_pf_lds(double2 *A, int lda, int m, double2
     return pf;
 }
 
-// LDS of one full-size evaluation (one wave)
-struct FbLds {
-    double2 A[SO_MMAX * (SO_MMAX + 1)];
-    double2 trow[2 * SO_NMAX];
-    double2 ubuf[SO_MMAX];
-    double2 ybuf[SO_MMAX];
-};
+// Dynamic LDS of k_fallback (bytes), m = 2n - eta, d = 2n: the staged
+// operands C' (d x d) and Xall (d x (d + 1), rows padded to an odd stride),
+// which the node matrix (m x (m + 1) complex) overlays once B is built; then
+// B (m x m complex), kept across the nodes; then 2m complex for the
+// formation's row buffer and the Householder vectors.
+__host__ __device__ inline size_t fb_stage_bytes(int n, int eta) {
+    const size_t m = (size_t)(2 * n - eta), d = (size_t)(2 * n);
+    size_t stage = (d * d + d * (d + 1)) * sizeof(double);
+    const size_t a = m * (m + 1) * sizeof(double2);
+    if (a > stage) stage = a;
+    return (stage + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t fb_lds_bytes(int n, int eta) {
+    const size_t m = (size_t)(2 * n - eta);
+    return fb_stage_bytes(n, eta) + (m * m + 2 * m) * sizeof(double2);
+}
 
-// o_ws of walker w and shadow s on the full-size path; Bg is m x m complex of
-// this block's global scratch.  Every lane returns the value.
+// o_ws of walker w and shadow s on the full-size path (one wave); lds is the
+// block's dynamic LDS (fb_lds_bytes).  Every lane returns the value.
 __device__ __forceinline__ double2 fb_pair(int n, int eta, const double *__restrict__ Xa,
                                            const double *__restrict__ Ca, const RedTab &tab, int Ke, int64_t w,
-                                           int64_t s, double2 *__restrict__ Bg, FbLds &sh, int q) {
-    const int d = 2 * n, m = 2 * n - eta, ne = n - eta, LDA = m + 1;
+                                           int64_t s, char *lds, int q) {
+    const int d = 2 * n, m = 2 * n - eta, ne = n - eta, LDA = m + 1, LX = d + 1;
     const int T = so_tiles(n), DP = 16 * T;
     const double *Xw = Xa + (size_t)w * DP * DP;
     const double *C = Ca + (size_t)s * DP * DP;
-    for (int i = 0; i < m; ++i) {
-        __syncthreads();
-        if (q < d) {
-            double2 acc = c_make(0, 0);
-            for (int mu = 0; mu < d; ++mu)
-                acc = c_fma(fb_xrow(Xw, i, mu, eta, T), c_make(C[ao_index(mu, q, T)], 0.0), acc);
-            sh.trow[q] = acc;
+    double *Cs = reinterpret_cast<double *>(lds);
+    double *Xr = Cs + d * d;
+    double2 *A = reinterpret_cast<double2 *>(lds);
+    double2 *Bl = reinterpret_cast<double2 *>(lds + fb_stage_bytes(n, eta));
+    double2 *ubuf = Bl + m * m;
+    double2 *ybuf = ubuf + m;
+    double2 *trow = ubuf;   // d <= 2m complex
+    __syncthreads();        // the previous pair's reads are done
+    // both operands in storage order (coalesced), to row-major LDS
+    for (int f = q; f < DP * DP; f += 64) {
+        int row, col;
+        ao_rowcol(f, T, row, col);
+        if (row < d && col < d) {
+            Cs[row * d + col] = C[f];
+            Xr[row * LX + col] = Xw[f];
         }
+    }
+    __syncthreads();
+    // X[i] = Xall[i] + i Xall[eta + i] for an occupied row, Xall[eta + i] (real) otherwise
+    auto xel = [&](int i, int mu) -> double2 {
+        return i < eta ? c_make(Xr[i * LX + mu], Xr[(eta + i) * LX + mu]) : c_make(Xr[(eta + i) * LX + mu], 0.0);
+    };
+    // B = X C' X^T, one row per step: trow = X[i] C', then B[i][q] = trow . X[q]
+    for (int i = 0; i < m; ++i) {
+        double2 acc = c_make(0, 0);
+        if (q < d)
+            for (int mu = 0; mu < d; ++mu) acc = c_fma(xel(i, mu), c_make(Cs[mu * d + q], 0.0), acc);
+        __syncthreads();   // the previous row's reads of trow are done
+        if (q < d) trow[q] = acc;
         __syncthreads();
         if (q < m) {
-            double2 acc = c_make(0, 0);
-            for (int nu = 0; nu < d; ++nu) acc = c_fma(sh.trow[nu], fb_xrow(Xw, q, nu, eta, T), acc);
-            Bg[i * m + q] = acc;
+            double2 b = c_make(0, 0);
+            for (int nu = 0; nu < d; ++nu) b = c_fma(trow[nu], xel(q, nu), b);
+            Bl[i * m + q] = b;
         }
     }
     __syncthreads();
@@ -103,38 +135,35 @@ __device__ __forceinline__ double2 fb_pair(int n, int eta, const double *__restr
         if (q < m)
             for (int j = 0; j < m; ++j) {
                 // exact antisymmetry: the lower triangle is the negated upper one
-                double2 v = (j > q) ? Bg[q * m + j] : ((j < q) ? c_neg(Bg[j * m + q]) : c_make(0, 0));
+                double2 v = (j > q) ? Bl[q * m + j] : ((j < q) ? c_neg(Bl[j * m + q]) : c_make(0, 0));
                 if (q >= eta && j >= eta) {
                     const int t = q - eta;
                     if (j - eta == 2 * ne - 1 - t) v = c_add(v, c_scale(ck, t < ne ? 1.0 : -1.0));
                 }
-                sh.A[q * LDA + j] = v;
+                A[q * LDA + j] = v;
             }
         __syncthreads();
-        const double2 pf = hh_pf_lds(sh.A, LDA, m, sh.ubuf, sh.ybuf, q);
+        const double2 pf = hh_pf_lds(A, LDA, m, ubuf, ybuf, q);
         o = c_fma(tab.v[node], pf, o);
     }
     return o;
 }
 
-// grid FB_GRID, 64 threads; Bscratch holds FB_GRID matrices of m x m.
-// pairs is [W][S_total]; Ke = ne + 1 nodes of the reduced table.
+// any grid, 64 threads, fb_lds_bytes(n, eta) of dynamic LDS.  pairs is
+// [W][S_total]; Ke = ne + 1 nodes of the reduced table.
 __global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double *__restrict__ Xa,
                                                  const double *__restrict__ Ca, RedTab tab, int Ke,
                                                  const so_u64 *__restrict__ fb_count,
                                                  const int64_t *__restrict__ fb_list, int64_t fb_cap, int64_t W,
-                                                 int64_t S_total, double2 *__restrict__ Bscratch,
-                                                 double2 *__restrict__ pairs) {
-    __shared__ FbLds sh;
+                                                 int64_t S_total, double2 *__restrict__ pairs) {
+    extern __shared__ __align__(16) char fb_lds[];
     const int q = threadIdx.x;
-    const int m = 2 * n - eta;
     const int64_t queued = (int64_t)(*fb_count);
     const int64_t cnt = min(queued, fb_cap);
-    double2 *Bg = Bscratch + (size_t)blockIdx.x * m * m;
     for (int64_t e = blockIdx.x; e < cnt; e += gridDim.x) {
         const int64_t gs = fb_list[e];
         const int64_t w = gs / S_total, s = gs - w * S_total;
-        const double2 o = fb_pair(n, eta, Xa, Ca, tab, Ke, w, s, Bg, sh, q);
+        const double2 o = fb_pair(n, eta, Xa, Ca, tab, Ke, w, s, fb_lds, q);
         if (q == 0) pairs[gs] = o;
     }
     if (queued <= fb_cap) return;
@@ -151,7 +180,7 @@ __global__ __launch_bounds__(64) void k_fallback(int n, int eta, const double *_
             mask &= mask - 1;
             const int64_t gs = base + b;
             const int64_t w = gs / S_total, s = gs - w * S_total;
-            const double2 o = fb_pair(n, eta, Xa, Ca, tab, Ke, w, s, Bg, sh, q);
+            const double2 o = fb_pair(n, eta, Xa, Ca, tab, Ke, w, s, fb_lds, q);
             if (q == 0) pairs[gs] = o;
         }
     }

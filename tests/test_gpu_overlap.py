@@ -297,6 +297,46 @@ def test_fallback_overflow_hf_walkers_signed_permutations(B, n, eta):
     assert np.all(np.abs(sg_ - so) <= 1e-10 * np.maximum(np.abs(so), 1e-3 * scale))
 
 
+def test_single_mode_walkers_signed_permutations_paper_size(B):
+    """Single-mode (Hartree-Fock-like) walkers on the paper's signed-permutation
+    ensemble at the paper's size (n = 16, eta = 8, 1024 walkers x 10,000
+    shadows): most pairs meet a zero pivot in the reduced elimination and take
+    the full-size path, far more than its queue holds.  1,000 sampled pairs
+    against the oracle, 100 of them against the closed form, and S_w of 8
+    walkers over all shadows against the oracle.  Many of these pairs are
+    exactly zero, so the floor of the pair tolerance is taken from the nonzero
+    ones."""
+    n, eta, W, S = 16, 8, 1024, 10000
+    rng = np.random.default_rng(1616)
+    phi = hf_walkers(rng, W, n, eta)
+    Q = wl.signed_permutations(rng, S, 2 * n)
+    bits = wl.even_bits(rng, S, n)
+    t = to_dev(phi, Q, bits)
+    print("single-mode walkers x signed permutations: inputs ready", flush=True)
+    out, pairs, st = B.shadow_overlap(*t, return_pairs=True)
+    cnt = B.fallback_count(*t)
+    assert not st.cpu().numpy().any()
+    assert cnt > W * S // 2
+    sw, ss = rng.integers(0, W, 1000), rng.integers(0, S, 1000)
+    pg = pairs[torch.from_numpy(sw).to(dev()), torch.from_numpy(ss).to(dev())].cpu().numpy()
+    sg = out.cpu().numpy()
+    del pairs
+    po = oracle.overlap_pairs(phi, Q, bits, pairs=np.stack([sw, ss], 1))
+    nz = np.abs(po)[np.abs(po) > 0]
+    floor = 1e-3 * np.median(nz)
+    rel = np.abs(pg - po) / np.maximum(np.abs(po), floor)
+    assert rel.max() <= RTOL, f"worst sampled pair rel {rel.max():.3e}"
+    for k in range(100):
+        perm = np.argmax(np.abs(Q[ss[k]]), axis=1)
+        signs = Q[ss[k]][np.arange(2 * n), perm]
+        ref = closed_form.overlap_pair(phi[sw[k]], perm, signs, int(bits[ss[k]]))
+        assert abs(pg[k] - ref) <= RTOL * max(abs(ref), floor)
+    pick = np.arange(8) * 127
+    so = oracle.overlap(phi[pick], Q, bits)
+    assert np.all(np.abs(sg[pick] - so) <= RTOL * np.maximum(np.abs(so), floor))
+    print(f"{cnt} of {W * S} pairs on the full-size path ({cnt / (W * S):.2f}); worst sampled pair rel {rel.max():.2e}")
+
+
 def test_signed_permutation_paper_workload(B):
     """The paper's own shadow ensemble at the paper's size: 1024 walkers x
     10,000 random signed permutations (n = 16, eta = 8).  2,000 sampled pairs
