@@ -27,7 +27,8 @@ second Pfaffian derivatives, with its own oracle baseline), ``perm`` (the
 main workload's size on random signed-permutation shadows, with the number
 of pairs that took the full-size path) and ``uneven``
 (four geometries in one batched call, graph-replayed, FP64 and mixed,
-beside separate calls).
+beside the same call in one launch per register level and beside separate
+calls).
 """
 from __future__ import annotations
 
@@ -243,6 +244,25 @@ def uneven_leg(args, B, wl, torch, np):
     for st in bt.status:
         if int(st.abs().sum()) != 0:
             raise RuntimeError("uneven batch reported a numerical status")
+    # the same batch in one launch per register level (SO_FLAG_BATCH_BY_LEVEL)
+    bl = B.Batch(probs, by_level=True)
+    for k in range(bt.n):
+        bl.arr[k].shadows_per_item = bt.arr[k].shadows_per_item
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bl.run()
+    torch.cuda.current_stream().wait_stream(side)
+    gl = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gl):
+        bl.run()
+    gl.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.uneven_steps):
+        gl.replay()
+    torch.cuda.synchronize()
+    t_level = (time.perf_counter() - t0) / args.uneven_steps
+    del gl, bl
     # the same batch with the single-precision formation, autotuned and replayed
     bm = B.Batch([dict(pr, precision="mixed") for pr in probs])
     bm.autotune()
@@ -263,6 +283,8 @@ def uneven_leg(args, B, wl, torch, np):
     return {"metric": "walker x shadow overlaps/s, uneven batch", "value": pairs / t_graph, "unit": "overlaps/s",
             "ms_per_step": t_graph * 1e3, "steps": args.uneven_steps, "pairs_per_step": pairs,
             "plain_calls": {"value": pairs / t_plain, "ms_per_step": t_plain * 1e3},
+            "per_level_graph": {"value": pairs / t_level, "ms_per_step": t_level * 1e3,
+                                "launches": "one per register level (2 here) instead of 1"},
             "mixed_graph": {"value": pairs / t_mixed, "ms_per_step": t_mixed * 1e3},
             "tuning": [{"n": c["n"], "shadows_per_item": k[0], "waves_per_cu": k[1]}
                        for c, k in zip(wl.UNEVEN, knobs)],

@@ -86,6 +86,10 @@ enum { SO_PREC_FP64 = 0, SO_PREC_MIXED = 1 };
                                  (principal branch) instead of S_w; S_w == 0 sets
                                  SO_WSTAT_ZERO.  shadow_overlap, shadow_overlap_grad,
                                  shadow_overlap_batched, so_vce_overlap */
+#define SO_FLAG_BATCH_BY_LEVEL 4u /* shadow_overlap_batched: if any problem sets it,
+                                     the fused problems go in one launch per
+                                     register level instead of one (ignored by
+                                     the other calls) */
 
 typedef struct {
     int n;          /* modes = qubits = spin orbitals; see so_max_n() */
@@ -218,7 +222,12 @@ so_status so_batch_workspace_size(const so_problem *probs, int n_probs, size_t *
  * every problem, the costliest problem first, with the items of walkers
  * w = x (mod 8) on XCD x of the MI355X so that each XCD keeps its walkers'
  * matrices in its L2.  Problems of other shapes use the two-kernel path
- * inside the same call.  Everything is enqueued on `stream` with no
+ * inside the same call.  The one launch runs every class at the register
+ * allocation of the heaviest, so light classes lose occupancy: on the paper's
+ * four reaction-path geometries (n = 8..20) it takes 386 ms against 359 ms as
+ * separate calls.  With SO_FLAG_BATCH_BY_LEVEL the problems go instead in one
+ * launch per register level (two there, 368 ms); the values are the same bits
+ * either way.  Everything is enqueued on `stream` with no
  * allocation, no memset and no host synchronisation, so the call may be
  * captured into a hipGraph and replayed (the workspace and outputs must then
  * stay fixed). */

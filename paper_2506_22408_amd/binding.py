@@ -22,6 +22,7 @@ SO_NODES = {"unit": 0, "chebyshev": 1}
 SO_PREC = {"fp64": 0, "mixed": 1}
 SO_FLAG_PAPER_NORM = 1
 SO_FLAG_LOG_OUTPUT = 2
+SO_FLAG_BATCH_BY_LEVEL = 4
 SO_WSTAT_RANK, SO_WSTAT_NONFINITE, SO_WSTAT_ZERO, SO_WSTAT_FALLBACK_LOST, SO_WSTAT_SINGULAR = 1, 2, 4, 8, 16
 
 
@@ -463,9 +464,10 @@ class Batch:
     phi, Q, bits (device tensors) and optionally n_nodes, nodes, precision,
     paper_norm, return_pairs, shadows_per_item, waves_per_cu.  After ``run`` (and a
     synchronisation) ``overlap[k]``, ``status[k]`` and ``pairs[k]`` hold
-    problem k's results."""
+    problem k's results.  ``by_level`` sets SO_FLAG_BATCH_BY_LEVEL (one launch
+    per register level instead of one)."""
 
-    def __init__(self, problems):
+    def __init__(self, problems, by_level: bool = False):
         if not 1 <= len(problems) <= 16:
             raise ValueError("1 to 16 problems")
         self.keep, self.overlap, self.status, self.pairs = [], [], [], []
@@ -486,6 +488,8 @@ class Batch:
             a.params = make_params(n, eta, pr.get("n_nodes", 0), pr.get("nodes", "unit"),
                                    pr.get("precision", "fp64"), pr.get("paper_norm", False),
                                    pr.get("log_output", False))
+            if by_level:
+                a.params.flags |= SO_FLAG_BATCH_BY_LEVEL
             a.phi, a.n_walkers, a.Q, a.bits, a.n_shadows = phi.data_ptr(), W, Q.data_ptr(), bits.data_ptr(), S
             a.overlap, a.status = out.data_ptr(), st.data_ptr()
             a.pair_out = pairs.data_ptr() if pairs is not None else None

@@ -126,7 +126,7 @@ bool params_ok(const so_params *p, int *K_out) {
     if (p->eta < 2 || p->eta > p->n || (p->eta & 1)) return false;
     if (p->nodes != SO_NODES_UNIT && p->nodes != SO_NODES_CHEBYSHEV) return false;
     if (p->precision != SO_PREC_FP64 && p->precision != SO_PREC_MIXED) return false;
-    if (p->flags & ~(SO_FLAG_PAPER_NORM | SO_FLAG_LOG_OUTPUT)) return false;
+    if (p->flags & ~(SO_FLAG_PAPER_NORM | SO_FLAG_LOG_OUTPUT | SO_FLAG_BATCH_BY_LEVEL)) return false;
     const int ell = p->n - p->eta / 2;
     const int K = p->n_nodes ? p->n_nodes : p->n + 1;
     if (K < ell + 1 || K > SO_KMAX) return false;
@@ -752,7 +752,7 @@ hipError_t launch_batch(const ProbPlan *plans, const so_problem *probs, const in
         jb.eta = P.eta;
         jb.W = (int)P.W;
         jb.spw = item_shadows(probs[ix[k]], NE);
-        jb.cls = 16 * T + NE;
+        jb.cls = 16 * T + NE + (P.n == 8 * T ? 256 : 0);   // + 256: the n = 8T instance
         const int64_t nY = (S + jb.spw - 1) / jb.spw;
         for (int x = 0; x < SO_BATCH_XCD; ++x) {
             const int64_t Wx = (P.W - x + SO_BATCH_XCD - 1) / SO_BATCH_XCD;
@@ -1326,10 +1326,17 @@ so_status shadow_overlap_batched(const so_problem *probs, int n_probs, void *wor
         }
     for (int a = 1; a < nf; ++a)
         for (int b = a; b > 0 && cost[order[b]] > cost[order[b - 1]]; --b) std::swap(order[b], order[b - 1]);
-    for (int prec = 0; prec < 2; ++prec) {
+    // one launch per formation precision, or, with SO_FLAG_BATCH_BY_LEVEL, one
+    // per precision and register level (pair_class_level)
+    bool by_level = false;
+    for (int k = 0; k < n_probs; ++k) by_level = by_level || (probs[k].params.flags & SO_FLAG_BATCH_BY_LEVEL);
+    for (int prec = 0; prec < 2; ++prec)
+    for (int lev = 0; lev < (by_level ? 3 : 1); ++lev) {
         int ix[kBatchMax], nj = 0, wpc = 0;
         for (int a = 0; a < nf; ++a)
-            if (plans[order[a]].mix == (prec == 1)) {
+            if (plans[order[a]].mix == (prec == 1) &&
+                (!by_level || pair_class_level(so_tiles(plans[order[a]].n), plans[order[a]].n - plans[order[a]].eta,
+                                               plans[order[a]].mix) == lev)) {
                 ix[nj++] = order[a];
                 if (probs[order[a]].waves_per_cu > wpc) wpc = probs[order[a]].waves_per_cu;
             }

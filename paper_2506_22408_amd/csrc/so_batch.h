@@ -73,13 +73,21 @@ __device__ __forceinline__ void batch_item(const BatchJob &jb, int w, int64_t sb
             pair_range<TT, NN, MIX, false, true>(jb.n, jb.eta, jb.Xa, jb.Ca, jb.S, jb.tab, jb.pairs, jb.fb_count, jb.fb_list, \
                                     jb.fb_cap, jb.wstat, w, sb0, sb1);                                         \
         break;
+#define SO_BFULL(TT, NN)                                                                                       \
+    case 256 + 16 * TT + NN:                                                                                   \
+        if constexpr (pair_class_level(TT, NN, MIX) <= LEVEL)                                                \
+            pair_range<TT, NN, MIX, true, true>(jb.n, jb.eta, jb.Xa, jb.Ca, jb.S, jb.tab, jb.pairs, jb.fb_count, jb.fb_list, \
+                                    jb.fb_cap, jb.wstat, w, sb0, sb1);                                         \
+        break;
     switch (jb.cls) {
+        SO_BFULL(1, 2) SO_BFULL(1, 4) SO_BFULL(1, 6) SO_BFULL(2, 8) SO_BFULL(3, 10) SO_BFULL(3, 12)
         SO_BCASE(1, 2) SO_BCASE(1, 4) SO_BCASE(1, 6) SO_BCASE(1, 8)
         SO_BCASE(2, 2) SO_BCASE(2, 4) SO_BCASE(2, 6) SO_BCASE(2, 8) SO_BCASE(2, 10) SO_BCASE(2, 12)
         SO_BCASE(3, 2) SO_BCASE(3, 4) SO_BCASE(3, 6) SO_BCASE(3, 8) SO_BCASE(3, 10) SO_BCASE(3, 12)
         default: break;
     }
 #undef SO_BCASE
+#undef SO_BFULL
 }
 
 // grid 8 max_x qlen[x], one wave per block

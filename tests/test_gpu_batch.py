@@ -70,6 +70,19 @@ def test_batched_matches_individual_calls(B):
         assert not got[k][2].any()
 
 
+def test_one_launch_per_level_gives_the_same_bits(B):
+    """SO_FLAG_BATCH_BY_LEVEL (one launch per register level) changes only the
+    grouping of the work items, not any pair's arithmetic."""
+    ws = mini_uneven()
+    one = batch_results(_run(B.Batch([dev_problem(w) for w in ws])))
+    lev = batch_results(_run(B.Batch([dev_problem(w) for w in ws], by_level=True)))
+    for a, b in zip(lev, one):
+        assert_same(a, b)
+    mixed = [dev_problem(w, precision="mixed") for w in ws]
+    for a, b in zip(batch_results(_run(B.Batch(mixed, by_level=True))), batch_results(_run(B.Batch(mixed)))):
+        assert_same(a, b)
+
+
 def test_tuning_knobs_do_not_change_results(B):
     ws = mini_uneven()
     ref = batch_results(_run(B.Batch([dev_problem(w) for w in ws])))
