@@ -195,9 +195,21 @@ def perm_leg(args, B, wl, torch, np):
     flagged = B.fallback_count(phi, Q, bits)
     if int(status.abs().sum()) != 0 or not bool(torch.isfinite(out.real).all()):
         raise RuntimeError("signed-permutation run reported a numerical status")
+    # the same with the gather formation (SO_FLAG_SIGNED_PERM), same bits
+    out_g, _, _ = B.shadow_overlap(phi, Q, bits, signed_perm=True)
+    torch.cuda.synchronize()
+    if not torch.equal(out_g, out):
+        raise RuntimeError("gather formation changed the overlaps")
+    t0 = time.perf_counter()
+    for _ in range(args.perm_steps):
+        B.shadow_overlap(phi, Q, bits, signed_perm=True)
+    torch.cuda.synchronize()
+    per_g = (time.perf_counter() - t0) / args.perm_steps
     return {"metric": "walker x shadow overlaps/s, signed-permutation shadows", "value": w.W * w.S / per,
             "unit": "overlaps/s", "ms_per_step": per * 1e3, "steps": args.perm_steps,
             "full_size_path_pairs": flagged, "full_size_path_frac": flagged / (w.W * w.S),
+            "gather_formation": {"value": w.W * w.S / per_g, "ms_per_step": per_g * 1e3,
+                                 "flag": "SO_FLAG_SIGNED_PERM"},
             "config": {"workload": "perm_n16", "n": w.n, "eta": w.eta, "walkers": w.W, "shadows": w.S,
                        "shadow_family": "random signed permutations"}}
 

@@ -90,6 +90,14 @@ enum { SO_PREC_FP64 = 0, SO_PREC_MIXED = 1 };
                                      the fused problems go in one launch per
                                      register level instead of one (ignored by
                                      the other calls) */
+#define SO_FLAG_SIGNED_PERM 8u /* shadow_overlap: every Q_s is a signed permutation
+                                  (the paper's shadow ensemble).  With FP64
+                                  formation and n = 8T (n = 8, 16, 24) the pair
+                                  kernel then forms U = C'X^T as a signed gather
+                                  instead of a matrix product, same values bit
+                                  for bit; a shadow that is not a signed
+                                  permutation gives NaN pairs (its walkers get
+                                  SO_WSTAT_NONFINITE).  Ignored elsewhere. */
 
 typedef struct {
     int n;          /* modes = qubits = spin orbitals; see so_max_n() */

@@ -23,6 +23,7 @@ SO_PREC = {"fp64": 0, "mixed": 1}
 SO_FLAG_PAPER_NORM = 1
 SO_FLAG_LOG_OUTPUT = 2
 SO_FLAG_BATCH_BY_LEVEL = 4
+SO_FLAG_SIGNED_PERM = 8
 SO_WSTAT_RANK, SO_WSTAT_NONFINITE, SO_WSTAT_ZERO, SO_WSTAT_FALLBACK_LOST, SO_WSTAT_SINGULAR = 1, 2, 4, 8, 16
 
 
@@ -207,13 +208,17 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 def shadow_overlap(phi: torch.Tensor, Q: torch.Tensor, bits: torch.Tensor, *, n_nodes: int = 0,
                    nodes: str = "unit", precision: str = "fp64", paper_norm: bool = False,
-                   log_output: bool = False, return_pairs: bool = False, workspace: torch.Tensor | None = None):
+                   log_output: bool = False, return_pairs: bool = False, signed_perm: bool = False,
+                   workspace: torch.Tensor | None = None):
     """S_w = (1/S) sum_s o_ws for every walker (complex128 [W]; log S_w with
     ``log_output``); with ``return_pairs`` also the [W,S] pair estimates.
+    ``signed_perm`` declares every Q_s a signed permutation (SO_FLAG_SIGNED_PERM).
     Returns (overlap, pairs or None, status int32 [W])."""
     W, n, eta, S = _check_inputs(phi, Q, bits)
     phi, Q, bits = phi.contiguous(), Q.contiguous(), bits.contiguous()
     p = make_params(n, eta, n_nodes, nodes, precision, paper_norm, log_output)
+    if signed_perm:
+        p.flags |= SO_FLAG_SIGNED_PERM
     nbytes = workspace_size(p, W, S)
     ws = workspace if workspace is not None else _workspace(nbytes, phi.device)
     out = torch.empty(W, dtype=torch.complex128, device=phi.device)

@@ -126,7 +126,7 @@ bool params_ok(const so_params *p, int *K_out) {
     if (p->eta < 2 || p->eta > p->n || (p->eta & 1)) return false;
     if (p->nodes != SO_NODES_UNIT && p->nodes != SO_NODES_CHEBYSHEV) return false;
     if (p->precision != SO_PREC_FP64 && p->precision != SO_PREC_MIXED) return false;
-    if (p->flags & ~(SO_FLAG_PAPER_NORM | SO_FLAG_LOG_OUTPUT | SO_FLAG_BATCH_BY_LEVEL)) return false;
+    if (p->flags & ~(SO_FLAG_PAPER_NORM | SO_FLAG_LOG_OUTPUT | SO_FLAG_BATCH_BY_LEVEL | SO_FLAG_SIGNED_PERM)) return false;
     const int ell = p->n - p->eta / 2;
     const int K = p->n_nodes ? p->n_nodes : p->n + 1;
     if (K < ell + 1 || K > SO_KMAX) return false;
@@ -291,7 +291,7 @@ constexpr int kRowBatchesPerWave = SO_ROW_BATCHES_PER_WAVE;   // the same for ne
 constexpr int64_t kRdmBlocks = 2048;                    // blocks of the density-matrix reduction
 
 struct Layout {
-    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_F, off_O;
+    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_F, off_O, off_M;
     size_t off_X32, off_C32;   // single-precision formation operands (mixed precision)
     size_t total;
     int Sc;
@@ -334,6 +334,7 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false,
     size_t o = 0;
     L.off_X = o; o = align_up(o + (size_t)W * DP * DP * sizeof(double));
     L.off_C = o; o = align_up(o + (size_t)S * DP * DP * sizeof(double));
+    L.off_M = o; o = align_up(o + (size_t)S * DP * sizeof(int32_t));   // signed matchings (SO_FLAG_SIGNED_PERM)
     L.off_S = o; o = align_up(o + (size_t)W * Sc * M2 * M2 * sizeof(double2));
     L.off_P = o; o = align_up(o + (size_t)W * Sc * sizeof(double2));
     L.off_pairs = o; o = align_up(o + (size_t)W * S * sizeof(double2));
@@ -416,19 +417,29 @@ hipError_t launch_form(const FormArgs &a, hipStream_t st) {
 template <int T, int NE, bool MIX>
 hipError_t launch_pair_tn(int n, int eta, const void *Xa, const void *Ca, int64_t W, int64_t S,
                           const RedTab &rt, double2 *pairs, so_u64 *fbc, int64_t *fbl, int64_t fb_cap,
-                          int32_t *wst, hipStream_t st) {
+                          int32_t *wst, const int32_t *match, hipStream_t st) {
     constexpr int NB = pair_node_batch(NE);
     const int spw = NB * (NE > 8 ? kRowBatchesPerWave : kPairBatchesPerWave);
     const size_t lds = pair_lds_bytes(T, n, NE);
     const int64_t ny = (S + spw - 1) / spw;
     for (int64_t y0 = 0; y0 < ny; y0 += 65535) {
         const int64_t gy = (ny - y0) < 65535 ? (ny - y0) : 65535;
-        if (n == 8 * T)
+        bool done = false;
+        if constexpr (!MIX) {
+            if (match && n == 8 * T) {   // signed-permutation shadows: gather formation
+                hipLaunchKernelGGL((k_pair<T, NE, false, true, true>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds,
+                                   st, n, eta, Xa, Ca, S, y0, spw, rt, pairs, fbc, fbl, fb_cap, wst, match);
+                done = true;
+            }
+        }
+        if (done) {
+        } else if (n == 8 * T) {
             hipLaunchKernelGGL((k_pair<T, NE, MIX, true>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds, st, n, eta,
-                               Xa, Ca, S, y0, spw, rt, pairs, fbc, fbl, fb_cap, wst);
-        else
+                               Xa, Ca, S, y0, spw, rt, pairs, fbc, fbl, fb_cap, wst, nullptr);
+        } else {
             hipLaunchKernelGGL((k_pair<T, NE, MIX, false>), dim3((unsigned)W, (unsigned)gy), dim3(64), lds, st, n, eta,
-                               Xa, Ca, S, y0, spw, rt, pairs, fbc, fbl, fb_cap, wst);
+                               Xa, Ca, S, y0, spw, rt, pairs, fbc, fbl, fb_cap, wst, nullptr);
+        }
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }
     return hipSuccess;
@@ -437,18 +448,18 @@ hipError_t launch_pair_tn(int n, int eta, const void *Xa, const void *Ca, int64_
 template <int T, bool MIX>
 hipError_t launch_pair_t(int n, int eta, const void *Xa, const void *Ca, int64_t W, int64_t S,
                          const RedTab &rt, double2 *pairs, so_u64 *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
-                         hipStream_t st) {
+                         const int32_t *match, hipStream_t st) {
     switch (n - eta) {
-        case 2: return launch_pair_tn<T, 2, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 4: return launch_pair_tn<T, 4, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 6: return launch_pair_tn<T, 6, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 8: return launch_pair_tn<T, 8, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 2: return launch_pair_tn<T, 2, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+        case 4: return launch_pair_tn<T, 4, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+        case 6: return launch_pair_tn<T, 6, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+        case 8: return launch_pair_tn<T, 8, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
         default: break;
     }
     if constexpr (T >= 2) {   // ne > 8 needs n > 8
         switch (n - eta) {
-            case 10: return launch_pair_tn<T, 10, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-            case 12: return launch_pair_tn<T, 12, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+            case 10: return launch_pair_tn<T, 10, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+            case 12: return launch_pair_tn<T, 12, MIX>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
             default: break;
         }
     }
@@ -457,17 +468,17 @@ hipError_t launch_pair_t(int n, int eta, const void *Xa, const void *Ca, int64_t
 
 hipError_t launch_pair(int n, int eta, bool mix, const void *Xa, const void *Ca, int64_t W, int64_t S,
                        const NodeTab &tab, double2 *pairs, so_u64 *fbc, int64_t *fbl, int64_t fb_cap, int32_t *wst,
-                       hipStream_t st) {
+                       const int32_t *match, hipStream_t st) {
     RedTab rt;
     std::memset(&rt, 0, sizeof(rt));
     for (int j = 0; j < tab.Ke; ++j) { rt.e[j] = tab.e[j]; rt.v[j] = tab.v[j]; }
     switch (so_tiles(n) * 2 + (mix ? 1 : 0)) {
-        case 2: return launch_pair_t<1, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 3: return launch_pair_t<1, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 4: return launch_pair_t<2, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 5: return launch_pair_t<2, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 6: return launch_pair_t<3, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
-        case 7: return launch_pair_t<3, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, st);
+        case 2: return launch_pair_t<1, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+        case 3: return launch_pair_t<1, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+        case 4: return launch_pair_t<2, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+        case 5: return launch_pair_t<2, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+        case 6: return launch_pair_t<3, false>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
+        case 7: return launch_pair_t<3, true>(n, eta, Xa, Ca, W, S, rt, pairs, fbc, fbl, fb_cap, wst, match, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -547,6 +558,7 @@ struct ProbPlan {
     double *Xw, *Cw;
     bool mix;                 // mixed precision: single-precision formation operands
     bool logout;              // SO_FLAG_LOG_OUTPUT
+    int32_t *match;           // signed matchings of the C'_s, or null (SO_FLAG_SIGNED_PERM)
     float *X32, *C32;
     const void *Xf, *Cf;      // the formation's operands
     int32_t *wst;
@@ -592,6 +604,10 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
     P->wst = status ? status : reinterpret_cast<int32_t *>(ws + P->L.off_stat);
     P->fbc = reinterpret_cast<so_u64 *>(ws + P->L.off_fbc);
     P->fbl = reinterpret_cast<int64_t *>(ws + P->L.off_fbl);
+    // the gather formation: FP64, fused kernel, n = 8T
+    const bool perm = (p->flags & SO_FLAG_SIGNED_PERM) && !P->mix && fused_ok(P->n, P->eta) &&
+                      P->n == 8 * so_tiles(P->n);
+    P->match = perm ? reinterpret_cast<int32_t *>(ws + P->L.off_M) : nullptr;
     return SO_OK;
 }
 
@@ -603,6 +619,11 @@ hipError_t enqueue_prep(const ProbPlan &P, hipStream_t st) {
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)P.S), dim3(256), (size_t)P.d * P.d * sizeof(double), st, P.n,
                        P.Q, P.bits, P.Cw);
     e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (P.match) {
+        hipLaunchKernelGGL(k_perm_match, dim3((unsigned)P.S), dim3(64), 0, st, P.n, P.Cw, P.match);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess || !P.mix) return e;
     // single-precision formation operands (the FP64 ones stay for the full-size path)
     const int T = so_tiles(P.n), DP = 16 * T;
@@ -1000,8 +1021,8 @@ so_status shadow_overlap(const so_params *p, const so_c64 *phi, int64_t n_walker
     if (fused_ok(P.n, P.eta)) {
         hipEvent_t ea = nullptr;
         if (prof_begin(st, &ea) != hipSuccess) return SO_ERR_HIP;
-        if (launch_pair(P.n, P.eta, P.mix, P.Xf, P.Cf, P.W, P.S, P.tab, P.pairs, P.fbc, P.fbl, P.L.fb_cap, P.wst, st) !=
-            hipSuccess)
+        if (launch_pair(P.n, P.eta, P.mix, P.Xf, P.Cf, P.W, P.S, P.tab, P.pairs, P.fbc, P.fbl, P.L.fb_cap, P.wst,
+                        P.match, st) != hipSuccess)
             return SO_ERR_HIP;
         if (prof_end(st, ea, PROF_PAIR, P.W * P.S) != hipSuccess) return SO_ERR_HIP;
     } else if (enqueue_two_kernel(P, st) != hipSuccess) {

@@ -111,20 +111,10 @@ __device__ __forceinline__ double2 pf_lane_from(double2 (&A)[N][N]) {
 // single-precision accumulation; P is widened to FP64 when it is stored and
 // everything after the formation runs in FP64.  FULL: ld = 16 T + 1 (2n =
 // DP), so every tile entry is stored without a bounds test.
-template <int T, bool MIX, bool FULL = false>
-__device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, const void *__restrict__ Cv,
-                                               double *Pl, int l, int ld) {
-    constexpr int KK = 4 * T;
-    using Op = typename std::conditional<MIX, float, double>::type;
-    using Vec = typename std::conditional<MIX, float4, double2>::type;
-    using Acc = typename std::conditional<MIX, so_f4, so_d4>::type;
-    // operands: the walker's Xall (re-read from L2 per pair: keeping it live
-    // through the elimination and node stages costs occupancy) and C'_s
-    Op xa[T][KK], ca[T][KK];
-    load_ops<T>(static_cast<const Vec *>(Xv), xa, l);
-    load_ops<T>(static_cast<const Vec *>(Cv), ca, l);
-    Acc P[T][T], U[T][T];
-    form_p<T>(xa, ca, P, U);
+// Stores the upper P tiles (both triangles of P) at stride ld, zeroes row and
+// column ld - 1; starts and ends with a barrier.
+template <int T, bool FULL, typename Acc>
+__device__ __forceinline__ void pair_store(const Acc (&P)[T][T], double *Pl, int l, int ld) {
     __syncthreads();   // region A is free
     const int z = ld - 1;   // the zero row and column
 #pragma unroll
@@ -146,6 +136,73 @@ __device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, cons
         Pl[c * ld + z] = 0.0;
     }
     __syncthreads();
+}
+
+template <int T, bool MIX, bool FULL = false>
+__device__ __forceinline__ void pair_formation(const void *__restrict__ Xv, const void *__restrict__ Cv,
+                                               double *Pl, int l, int ld) {
+    constexpr int KK = 4 * T;
+    using Op = typename std::conditional<MIX, float, double>::type;
+    using Vec = typename std::conditional<MIX, float4, double2>::type;
+    using Acc = typename std::conditional<MIX, so_f4, so_d4>::type;
+    // operands: the walker's Xall (re-read from L2 per pair: keeping it live
+    // through the elimination and node stages costs occupancy) and C'_s
+    Op xa[T][KK], ca[T][KK];
+    load_ops<T>(static_cast<const Vec *>(Xv), xa, l);
+    load_ops<T>(static_cast<const Vec *>(Cv), ca, l);
+    Acc P[T][T], U[T][T];
+    form_p<T>(xa, ca, P, U);
+    pair_store<T, FULL>(P, Pl, l, ld);
+}
+
+// ---- formation for a signed-permutation shadow (FP64) ----------------------------
+// There C' = Q^T C_b Q is a signed matching: row mu has its one entry s_mu =
+// +-1 at column pi(mu).  match_s[mu] = pi(mu) | 0x100 if s_mu = -1, 0x200 for
+// the zero padding rows mu >= 2n, negative if the row is not of that form.
+// U = C' Xall^T is then the signed gather U[mu][j] = s_mu Xall[j][pi(mu)],
+// written straight into the register layout the MFMA product would give
+// (register r of lane l of tile (I, J): U[16 I + 4 r + l/16][16 J + l%16]);
+// P = Xall U on the matrix cores as in form_p.  A row that is not a signed
+// matching makes P NaN, so the pair value and the walker's status report it.
+template <int T>
+__device__ __forceinline__ void pair_formation_perm(const void *__restrict__ Xv, const int32_t *__restrict__ match_s,
+                                                    double *Pl, int l, int ld) {
+    constexpr int KK = 4 * T;
+    const double *Xd = static_cast<const double *>(Xv);
+    double xa[T][KK];
+    load_ops<T>(static_cast<const double2 *>(Xv), xa, l);
+    so_d4 U[T][T], P[T][T];
+    bool bad = false;
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int mm = match_s[16 * I + 4 * r + (l >> 4)];
+            bad = bad || mm < 0;
+            const int c = mm & 0xff;
+            const double sg = (mm & 0x200) ? 0.0 : ((mm & 0x100) ? -1.0 : 1.0);
+#pragma unroll
+            for (int J = 0; J < T; ++J) U[I][J][r] = sg * Xd[ao_index(16 * J + (l & 15), mm < 0 ? 0 : c, T)];
+        }
+    if (bad) {
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = 0; J < T; ++J) U[I][J] = so_d4{__builtin_nan(""), __builtin_nan(""), __builtin_nan(""),
+                                                        __builtin_nan("")};
+    }
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = 0; J < T; ++J) P[I][J] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int J = I; J < T; ++J)
+                P[I][J] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][J][kk & 3], P[I][J], 0, 0, 0);
+    pair_store<T, true>(P, Pl, l, ld);
 }
 
 // ---- pairwise elimination of K in the bordered rows ---------------------------
@@ -314,13 +371,16 @@ __host__ __device__ inline size_t pair_lds_bytes(int T, int n, int NE) {
 // elements each, in the formation's operand order.  FULL: n = 8 T, so P's
 // row stride is the compile-time 16 T + 1 and its stores need no bounds
 // test (measured 1.6% of k_pair at n = 16 and 3.5% at n = 24).  OPAQUE_LANE:
-// see below.
-template <int T, int NE, bool MIX, bool FULL, bool OPAQUE_LANE>
+// see below.  PERM: every shadow is a signed permutation, match holds the
+// signed matchings of the C'_s (DP entries per shadow, pair_formation_perm).
+template <int T, int NE, bool MIX, bool FULL, bool OPAQUE_LANE, bool PERM = false>
 __device__ __forceinline__ void pair_range(int n, int eta, const void *__restrict__ Xa,
                                            const void *__restrict__ Ca, int64_t S_total, const RedTab &tab,
                                            double2 *__restrict__ pairs, so_u64 *__restrict__ fb_count,
                                            int64_t *__restrict__ fb_list, int64_t fb_cap,
-                                           int32_t *__restrict__ wstat, int w, int64_t sb0, int64_t sb1) {
+                                           int32_t *__restrict__ wstat, int w, int64_t sb0, int64_t sb1,
+                                           const int32_t *__restrict__ match = nullptr) {
+    static_assert(!PERM || (FULL && !MIX), "the signed-permutation formation is FP64, n = 8T");
     constexpr int DP = 16 * T;
     constexpr size_t MATB = (size_t)DP * DP * (MIX ? sizeof(float) : sizeof(double));   // bytes per matrix
     constexpr int KE = NE + 1;
@@ -382,7 +442,10 @@ __device__ __forceinline__ void pair_range(int n, int eta, const void *__restric
         for (int b = 0; b < nb; ++b) {
             const int64_t s = bs + b;
             // ---------------- formation: P = Xall C' Xall^T
-            pair_formation<T, MIX, FULL>(Xw, static_cast<const char *>(Ca) + (size_t)s * MATB, Pl, l, LDP);
+            if constexpr (PERM)
+                pair_formation_perm<T>(Xw, match + s * DP, Pl, l, LDP);
+            else
+                pair_formation<T, MIX, FULL>(Xw, static_cast<const char *>(Ca) + (size_t)s * MATB, Pl, l, LDP);
 
             // ---------------- R = rows K of Z, trailing T = [[B_LL, 0], [0, 0]]
             constexpr int RPL = (8 * T * (8 * T + NE) + 63) / 64;   // B entries of R per lane (n <= 8 T)
@@ -548,14 +611,15 @@ __host__ __device__ constexpr int pair_class_level(int T, int NE, bool mix) {
 // spw is a multiple of pair_node_batch(NE).  Three waves per SIMD for the
 // classes of level 0, two otherwise (the three-tile instances would take
 // more than 256 registers).
-template <int T, int NE, bool MIX, bool FULL>
+template <int T, int NE, bool MIX, bool FULL, bool PERM = false>
 __global__ __launch_bounds__(64, pair_class_level(T, NE, MIX) == 0 ? 3 : 2) void k_pair(int n, int eta, const void *__restrict__ Xa,
                                              const void *__restrict__ Ca, int64_t S_total, int64_t sy0, int spw,
                                              RedTab tab, double2 *__restrict__ pairs,
                                              so_u64 *__restrict__ fb_count, int64_t *__restrict__ fb_list,
-                                             int64_t fb_cap, int32_t *__restrict__ wstat) {
+                                             int64_t fb_cap, int32_t *__restrict__ wstat,
+                                             const int32_t *__restrict__ match) {
     const int64_t sb0 = (sy0 + blockIdx.y) * (int64_t)spw;
     const int64_t sb1 = min(S_total, sb0 + spw);
-    pair_range<T, NE, MIX, FULL, false>(n, eta, Xa, Ca, S_total, tab, pairs, fb_count, fb_list, fb_cap, wstat,
-                                        (int)blockIdx.x, sb0, sb1);
+    pair_range<T, NE, MIX, FULL, false, PERM>(n, eta, Xa, Ca, S_total, tab, pairs, fb_count, fb_list, fb_cap, wstat,
+                                              (int)blockIdx.x, sb0, sb1, match);
 }

@@ -168,3 +168,31 @@ __global__ __launch_bounds__(256) void k_to_f32(int T, int sig, int64_t count, c
         A32[base + f] = (float)A64[base + src];
     }
 }
+
+// k_perm_match: for a signed-permutation shadow C'_s = Q^T C_b Q is a signed
+// matching (one entry +-1 per row, computed exactly from entries 0 and +-1).
+// match[s][mu] = pi(mu) | 0x100 if the entry is -1, for the rows mu < 2n;
+// 0x200 for the padding rows mu < DP; -1 for a row that is not one entry +-1
+// among zeros.  Grid S, 64 threads.
+__global__ __launch_bounds__(64) void k_perm_match(int n, const double *__restrict__ Ca, int32_t *__restrict__ match) {
+    const int mu = threadIdx.x, d = 2 * n, T = so_tiles(n), DP = 16 * T;
+    if (mu >= DP) return;
+    const int64_t s = blockIdx.x;
+    int32_t out = 0x200;
+    if (mu < d) {
+        const double *C = Ca + (size_t)s * DP * DP;
+        int cnt = 0, col = 0;
+        double v = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double x = C[ao_index(mu, c, T)];
+            if (x != 0.0) {
+                ++cnt;
+                col = c;
+                v = x;
+            }
+        }
+        out = (cnt == 1 && (v == 1.0 || v == -1.0)) ? (col | (v < 0.0 ? 0x100 : 0)) : -1;
+    }
+    match[s * DP + mu] = out;
+}
+

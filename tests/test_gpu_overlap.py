@@ -297,6 +297,44 @@ def test_fallback_overflow_hf_walkers_signed_permutations(B, n, eta):
     assert np.all(np.abs(sg_ - so) <= 1e-10 * np.maximum(np.abs(so), 1e-3 * scale))
 
 
+@pytest.mark.parametrize("n,eta,W,S", [(8, 4, 5, 37), (16, 8, 6, 41), (16, 4, 3, 19), (24, 12, 3, 11), (12, 6, 3, 9)])
+def test_signed_perm_formation_same_bits(B, n, eta, W, S):
+    """SO_FLAG_SIGNED_PERM: for signed-permutation shadows the gather formation
+    (n = 8T) gives the bits of the matrix-core formation, whose sums have one
+    nonzero term; other n ignore the flag."""
+    rng = np.random.default_rng(80 + n + eta)
+    phi = wl.walkers(rng, W, n, eta)
+    Q = wl.signed_permutations(rng, S, 2 * n)
+    bits = wl.even_bits(rng, S, n)
+    t = to_dev(phi, Q, bits)
+    o1, p1, s1 = B.shadow_overlap(*t, return_pairs=True)
+    o2, p2, s2 = B.shadow_overlap(*t, return_pairs=True, signed_perm=True)
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p2) and torch.equal(o1, o2) and torch.equal(s1, s2)
+    po = oracle.overlap_pairs(phi, Q, bits)
+    assert_pairs_close(p2.cpu().numpy(), po, what=f"signed-perm formation n={n}")
+
+
+def test_signed_perm_flag_with_other_shadows_is_loud(B):
+    """A shadow that is not a signed permutation under SO_FLAG_SIGNED_PERM
+    gives NaN pair values and SO_WSTAT_NONFINITE; the mixed precision mode
+    ignores the flag."""
+    n, eta, W = 16, 8, 4
+    rng = np.random.default_rng(88)
+    phi = wl.walkers(rng, W, n, eta)
+    Q = np.concatenate([wl.signed_permutations(rng, 5, 2 * n), wl.haar_so(rng, 1, 2 * n)])
+    bits = wl.even_bits(rng, 6, n)
+    t = to_dev(phi, Q, bits)
+    _, pairs, st = B.shadow_overlap(*t, return_pairs=True, signed_perm=True)
+    pg, st = pairs.cpu().numpy(), st.cpu().numpy()
+    assert np.isnan(pg[:, 5]).all() and np.isfinite(pg[:, :5]).all()
+    assert (st & B.SO_WSTAT_NONFINITE).all()
+    om, _, sm = B.shadow_overlap(*t, precision="mixed", signed_perm=True)
+    om2, _, _ = B.shadow_overlap(*t, precision="mixed")
+    torch.cuda.synchronize()
+    assert torch.equal(om, om2) and not sm.any()
+
+
 def test_single_mode_walkers_signed_permutations_paper_size(B):
     """Single-mode (Hartree-Fock-like) walkers on the paper's signed-permutation
     ensemble at the paper's size (n = 16, eta = 8, 1024 walkers x 10,000
