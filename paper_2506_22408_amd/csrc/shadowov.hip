@@ -50,19 +50,29 @@
 // --------------------------------------------------------------------------
 // k_reduce: S_w = (1/S) sum_s o_ws, fixed order: lane l sums s = l, l+64, ...
 // then a fixed butterfly.  Sets SO_WSTAT_NONFINITE; rank-deficient walkers
-// get NaN.
+// get NaN.  With logdet (the pairs are those of the orthonormal factor,
+// k_walker_prep) S_w = det R times the mean, or log S_w = log det R + log of
+// the mean with the log output; with scale_pairs the pair values are
+// rescaled by det R in place (the caller asked for them).
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_reduce(const double2 *__restrict__ pairs, int64_t S,
+__global__ __launch_bounds__(64) void k_reduce(double2 *__restrict__ pairs, int64_t S,
                                                double2 *__restrict__ out, int32_t *__restrict__ wstat,
-                                               int logout) {
+                                               int logout, const double2 *__restrict__ logdet, int scale_pairs) {
     const int w = blockIdx.x;
     const int lane = threadIdx.x;
-    const double2 *pw = pairs + (size_t)w * S;
+    double2 *pw = pairs + (size_t)w * S;
+    double2 f = c_make(1.0, 0.0);
+    if (logdet) {
+        const double2 ld = logdet[w];
+        const double mg = exp(ld.x);
+        f = c_make(mg * cos(ld.y), mg * sin(ld.y));
+    }
     double ar = 0.0, ai = 0.0;
     for (int64_t s = lane; s < S; s += 64) {
         const double2 v = pw[s];
         ar += v.x;
         ai += v.y;
+        if (scale_pairs) pw[s] = c_mul(f, v);
     }
     ar = grp_sum<64>(ar);
     ai = grp_sum<64>(ai);
@@ -75,6 +85,13 @@ __global__ __launch_bounds__(64) void k_reduce(const double2 *__restrict__ pairs
         if (logout) {
             if (r.x == 0.0 && r.y == 0.0) st |= SO_WSTAT_ZERO;
             r = c_log(r);
+            if (logdet) {
+                const double2 ld = logdet[w];
+                r = c_make(r.x + ld.x, remainder(r.y + ld.y, 2.0 * M_PI));
+            }
+        } else if (logdet) {
+            r = c_mul(f, r);
+            if (!isfinite(r.x) || !isfinite(r.y)) st |= SO_WSTAT_NONFINITE;
         }
         out[w] = r;
         wstat[w] = st;
@@ -291,7 +308,7 @@ constexpr int kRowBatchesPerWave = SO_ROW_BATCHES_PER_WAVE;   // the same for ne
 constexpr int64_t kRdmBlocks = 2048;                    // blocks of the density-matrix reduction
 
 struct Layout {
-    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_F, off_O, off_M;
+    size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_F, off_O, off_M, off_LD;
     size_t off_X32, off_C32;   // single-precision formation operands (mixed precision)
     size_t total;
     int Sc;
@@ -335,6 +352,7 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false,
     L.off_X = o; o = align_up(o + (size_t)W * DP * DP * sizeof(double));
     L.off_C = o; o = align_up(o + (size_t)S * DP * DP * sizeof(double));
     L.off_M = o; o = align_up(o + (size_t)S * DP * sizeof(int32_t));   // signed matchings (SO_FLAG_SIGNED_PERM)
+    L.off_LD = o; o = align_up(o + (size_t)W * sizeof(double2));          // log det R per walker
     L.off_S = o; o = align_up(o + (size_t)W * Sc * M2 * M2 * sizeof(double2));
     L.off_P = o; o = align_up(o + (size_t)W * Sc * sizeof(double2));
     L.off_pairs = o; o = align_up(o + (size_t)W * S * sizeof(double2));
@@ -559,6 +577,8 @@ struct ProbPlan {
     bool mix;                 // mixed precision: single-precision formation operands
     bool logout;              // SO_FLAG_LOG_OUTPUT
     int32_t *match;           // signed matchings of the C'_s, or null (SO_FLAG_SIGNED_PERM)
+    double2 *logdet;          // log det R per walker (the walkers' orthonormal factors are evaluated)
+    bool user_pairs;          // the caller asked for the pair values
     float *X32, *C32;
     const void *Xf, *Cf;      // the formation's operands
     int32_t *wst;
@@ -601,6 +621,8 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
     P->Sb = reinterpret_cast<double2 *>(ws + P->L.off_S);
     P->Pb = reinterpret_cast<double2 *>(ws + P->L.off_P);
     P->pairs = pair_out ? reinterpret_cast<double2 *>(pair_out) : reinterpret_cast<double2 *>(ws + P->L.off_pairs);
+    P->user_pairs = pair_out != nullptr;
+    P->logdet = reinterpret_cast<double2 *>(ws + P->L.off_LD);
     P->wst = status ? status : reinterpret_cast<int32_t *>(ws + P->L.off_stat);
     P->fbc = reinterpret_cast<so_u64 *>(ws + P->L.off_fbc);
     P->fbl = reinterpret_cast<int64_t *>(ws + P->L.off_fbl);
@@ -613,7 +635,8 @@ so_status plan_problem(const so_params *p, const so_c64 *phi, int64_t W, const d
 
 // walker and shadow preparation (X_w, C'_s; clears the fallback queue)
 hipError_t enqueue_prep(const ProbPlan &P, hipStream_t st) {
-    hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)P.W), dim3(64), 0, st, P.n, P.eta, P.phi, P.Xw, P.wst, P.fbc);
+    hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)P.W), dim3(64), 0, st, P.n, P.eta, P.phi, P.Xw, P.wst, P.fbc,
+                       P.logdet);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)P.S), dim3(256), (size_t)P.d * P.d * sizeof(double), st, P.n,
@@ -676,7 +699,7 @@ hipError_t enqueue_finish(const ProbPlan &P, hipStream_t st) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce, dim3((unsigned)P.W), dim3(64), 0, st, P.pairs, P.S, P.overlap, P.wst,
-                       P.logout ? 1 : 0);
+                       P.logout ? 1 : 0, P.logdet, P.user_pairs ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1082,7 +1105,7 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
     for (int j = 0; j < tab.Ke; ++j) { rt.e[j] = tab.e[j]; rt.v[j] = tab.v[j]; }
 
     hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
-                       reinterpret_cast<const double2 *>(phi), Xa, wst, fbc);
+                       reinterpret_cast<const double2 *>(phi), Xa, wst, fbc, static_cast<double2 *>(nullptr));
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q,
                        bits, Ca);
@@ -1257,7 +1280,8 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     energy_nodetab(p, &tab);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
-                       reinterpret_cast<const double2 *>(phi), Xa, wst, nullptr);
+                       reinterpret_cast<const double2 *>(phi), Xa, wst, static_cast<so_u64 *>(nullptr),
+                       static_cast<double2 *>(nullptr));
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q, bits, Ca);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;

@@ -24,10 +24,20 @@
 // (-Im g_p, Re g_p)_p.  Row i of B is X_O row i (i < eta) or X_U row i - eta.
 // One 64-lane workgroup per walker, lane = orbital row p (n <= 32).  Block 0
 // also clears the fallback-queue counter of this call.
+//
+// With logdet (the overlap path): the occupied rows are taken from the
+// orthonormal factor instead, Phi = Qf R (the same Householder QR), and
+// logdet[w] = log det R = sum_j log|R_jj| + i sum_j arg R_jj.  The estimator
+// is multilinear in the walker's orbitals, o(Phi) = det R o(Qf), so the
+// kernels evaluate o(Qf), whose node Pfaffians are bounded for every walker
+// norm, and k_reduce applies det R (in log form when the log output is asked
+// for).  Without logdet (derivative and energy paths, which differentiate
+// through Phi) X_O comes from Phi itself.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double2 *__restrict__ phi,
                                                     double *__restrict__ Xa, int32_t *__restrict__ wstat,
-                                                    so_u64 *__restrict__ fb_count) {
+                                                    so_u64 *__restrict__ fb_count,
+                                                    double2 *__restrict__ logdet = nullptr) {
     __shared__ double2 R[SO_NMAX][SO_NMAX];
     __shared__ double2 V[SO_NMAX][SO_NMAX];
     __shared__ double betas[SO_NMAX];
@@ -51,6 +61,7 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
     finite = __all(finite);
     const double fnorm = sqrt(fro);
     int rank_ok = 1;
+    double lmag = 0.0, larg = 0.0;   // log det R (lane-uniform)
     __syncthreads();
     for (int j = 0; j < eta; ++j) {
         double2 x = (p < n && p >= j) ? R[p][j] : c_make(0, 0);
@@ -63,6 +74,9 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
         double2 v = x;
         if (p == j) v = c_add(v, c_scale(phs, nx));
         double beta = (nx > 0) ? 1.0 / (nx2 + nx * ax) : 0.0;   // 2 / (v^H v)
+        // H x = -phs nx e_j: R_jj = -phs nx
+        lmag += log(nx);
+        larg += atan2(-phs.y, -phs.x);
         if (p < n) V[p][j] = v;
         if (p == 0) betas[j] = beta;
         __syncthreads();
@@ -76,9 +90,13 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
             __syncthreads();
         }
     }
-    // g_t = H_0 ... H_{eta-1} e_{eta+t}, kept in R[t][.] (R is no longer needed)
-    for (int t = 0; t < ne; ++t) {
-        double2 g = c_make(p == eta + t ? 1.0 : 0.0, 0.0);
+    // g_t = H_0 ... H_{eta-1} e_{eta+t}, kept in R[t][.] (R is no longer
+    // needed); with logdet also the orthonormal factor's columns
+    // q_j = H_0 ... H_{eta-1} e_j, kept in R[ne + j][.]
+    const int ncols = logdet ? ne + eta : ne;
+    for (int t = 0; t < ncols; ++t) {
+        const int e = t < ne ? eta + t : t - ne;
+        double2 g = c_make(p == e ? 1.0 : 0.0, 0.0);
         for (int j = eta - 1; j >= 0; --j) {
             double2 vj = (p < n) ? V[p][j] : c_make(0, 0);
             double2 tt = c_mul(c_conj(vj), g);
@@ -99,7 +117,7 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
             const int q = col >> 1, odd = col & 1;
             if (row < 2 * eta) {
                 const int j = row < eta ? row : row - eta;
-                const double2 v = ph[q * eta + j];
+                const double2 v = logdet ? R[ne + j][q] : ph[q * eta + j];
                 if (row < eta) val = odd ? v.y * rs2 : v.x * rs2;    // Re X_O
                 else val = odd ? -v.x * rs2 : v.y * rs2;            // Im X_O
             } else {
@@ -116,6 +134,7 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
         Xw[f] = val;
     }
     if (p == 0 && wstat) wstat[w] = (rank_ok ? 0 : SO_WSTAT_RANK) | (finite ? 0 : SO_WSTAT_NONFINITE);
+    if (p == 0 && logdet) logdet[w] = c_make(lmag, remainder(larg, 2.0 * M_PI));
 }
 
 // --------------------------------------------------------------------------

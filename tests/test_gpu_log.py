@@ -88,3 +88,33 @@ def test_log_output_zero_overlap_sets_status(B):
     assert np.isfinite(o[0]) and st[0] == 0
     # the active-space S_w is finite and the prefactor zero: log form gives -inf real part
     assert np.isneginf(o[1].real)
+
+
+def test_walker_scale_beyond_double_range(B):
+    """The overlap path evaluates each walker's orthonormal factor and applies
+    det R at the end (o(Phi R) = det R o(Phi)).  Scaling every orbital by c
+    multiplies S_w by c^eta: with the log output log S_w moves by exactly
+    eta log c, also for c = 1e+-60 where c^8 lies outside double precision;
+    without it S_w is c^eta S_w (against the oracle where that is finite) and
+    an overflowing one is flagged non-finite."""
+    import oracle
+    n, eta, W, S = 16, 8, 4, 30
+    w = wl.make("sc", n, eta, W, S, seed=71)
+    Q, bits = td(w.Q), td(w.bits.view(np.int64))
+    l0, _, _ = B.shadow_overlap(td(w.phi), Q, bits, log_output=True)
+    l0 = l0.cpu().numpy()
+    for c in (1e-60, 1e-20, 1e20, 1e60):
+        ph = td(w.phi * c)
+        lc, _, st = B.shadow_overlap(ph, Q, bits, log_output=True)
+        lc, st = lc.cpu().numpy(), st.cpu().numpy()
+        assert not st.any()
+        d = lc - (l0 + eta * np.log(c))
+        d = d.real + 1j * ((d.imag + np.pi) % (2 * np.pi) - np.pi)
+        assert np.all(np.abs(d) <= 1e-12 * np.abs(lc.real) + 1e-12), (c, d)
+        oc, _, sc = B.shadow_overlap(ph, Q, bits)
+        oc, sc = oc.cpu().numpy(), sc.cpu().numpy()
+        if abs(np.log10(c)) * eta < 300:
+            so = oracle.overlap(w.phi * c, w.Q, w.bits)
+            assert np.all(np.abs(oc - so) <= 1e-10 * np.abs(so)) and not sc.any()
+        elif c > 1:
+            assert (sc & B.SO_WSTAT_NONFINITE).all()
