@@ -66,6 +66,7 @@ __global__ __launch_bounds__(64) void k_reduce(double2 *__restrict__ pairs, int6
         const double2 ld = logdet[w];
         const double mg = exp(ld.x);
         f = c_make(mg * cos(ld.y), mg * sin(ld.y));
+        if (wstat[w] & SO_WSTAT_RANK) f = c_make(NAN, NAN);   // no orthonormal factor: NaN pairs too
     }
     double ar = 0.0, ai = 0.0;
     for (int64_t s = lane; s < S; s += 64) {

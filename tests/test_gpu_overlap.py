@@ -172,7 +172,7 @@ def test_edge_cases(B):
     phi3 = phi.copy()
     phi3[2][:, 3] = phi3[2][:, 1]
     sg3, pg3, st3 = gpu_overlap(B, phi3, Q, bits)
-    assert st3[2] & B.SO_WSTAT_RANK and np.isnan(sg3[2])
+    assert st3[2] & B.SO_WSTAT_RANK and np.isnan(sg3[2]) and np.isnan(pg3[2]).all()
     assert not st3[[0, 1, 3]].any()
     assert_pairs_close(pg3[[0, 1, 3]], oracle.overlap_pairs(phi3[[0, 1, 3]], Q, bits), what="others")
     # non-finite input
