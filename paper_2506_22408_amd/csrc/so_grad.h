@@ -153,6 +153,60 @@ __device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int 
     if (zero) sing = true;
 }
 
+// ---- formation shared by the two waves: wave J forms column tile J, U[., J]
+// = C' Xall^T[., J] and then P[I][J] = Xall[I] U[., J] for I <= J, and stores
+// its tiles (both triangles of P).  With one tile (T = 1) wave 1 only keeps
+// the barriers.  Starts and ends with a barrier, as pair_formation does.
+template <int T, int J>
+__device__ __forceinline__ void form_column(const double2 *__restrict__ Xv, const double2 *__restrict__ Cv,
+                                            double *Pl, int l, int ld) {
+    constexpr int KK = 4 * T;
+    double xa[T][KK], ca[T][KK];
+    load_ops<T>(Xv, xa, l);
+    load_ops<T>(Cv, ca, l);
+    so_d4 U[T], P[J + 1];
+#pragma unroll
+    for (int I = 0; I < T; ++I) U[I] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+        for (int I = 0; I < T; ++I) U[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[I][kk], xa[J][kk], U[I], 0, 0, 0);
+#pragma unroll
+    for (int I = 0; I <= J; ++I) P[I] = so_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < KK; ++kk)
+#pragma unroll
+        for (int I = 0; I <= J; ++I)
+            P[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[I][kk], U[kk >> 2][kk & 3], P[I], 0, 0, 0);
+    __syncthreads();   // region RP is free
+#pragma unroll
+    for (int I = 0; I <= J; ++I)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = 16 * I + 4 * r + (l >> 4), bcol = 16 * J + (l & 15);
+            Pl[a * ld + bcol] = P[I][r];
+            if (J > I) Pl[bcol * ld + a] = -P[I][r];
+        }
+}
+template <int T>
+__device__ __forceinline__ void formation_two_waves(const double2 *__restrict__ Xv, const double2 *__restrict__ Cv,
+                                                    double *Pl, int l, int ld, int wv) {
+    static_assert(T <= 2, "two waves, one column tile each");
+    if (wv == 0)
+        form_column<T, 0>(Xv, Cv, Pl, l, ld);
+    else if constexpr (T == 2)
+        form_column<T, 1>(Xv, Cv, Pl, l, ld);
+    else
+        __syncthreads();
+    const int z = ld - 1;   // the zero row and column (16 T)
+    if (wv == 0)
+        for (int c = l; c <= z; c += 64) {
+            Pl[z * ld + c] = 0.0;
+            Pl[c * ld + z] = 0.0;
+        }
+    __syncthreads();
+}
+
 // LDS regions of k_grad_pair (bytes), in order RP, RB, RR, RG, RS.
 //   RP: P, then the trailing block (the pencil's source), then the node
 //       inverses N_j, then Abar;
@@ -282,8 +336,8 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
         asm volatile("" : "+v"(t));
         const int l = t & 63;
         const double2 *Cs = Ca + (size_t)s * MAT2;
-        // both waves form P (the same values; the formation is a few percent of a pair)
-        pair_formation<T, false, true>(Xw, Cs, RP, l, LDP);
+        // P = Xall C' Xall^T, each wave forming one column tile
+        formation_two_waves<T>(Xw, Cs, RP, l, LDP, wv);
 
         // ---------------- B (m x m), then R = rows K of Z
         double bmax = 0.0;
