@@ -65,21 +65,65 @@ __device__ __forceinline__ double2 hh_pf_lds(double2 *A, int lda, int m, double2
     return pf;
 }
 
+// Two Pfaffians at once for m <= 32, one per 32-lane half of the wave: half
+// h = l / 32 works on A + h hA with its vectors at u + h hv, y + h hv (lane
+// q = l % 32 = row); otherwise as hh_pf_lds.  Every lane of a half returns
+// its half's value.  Starts and ends with a barrier.
+__device__ __forceinline__ double2 hh_pf_lds2(double2 *A0, int lda, int m, double2 *u0, double2 *y0, int hA, int hv,
+                                              int l) {
+    const int h = l >> 5, q = l & 31;
+    double2 *A = A0 + h * hA;
+    double2 *ubuf = u0 + h * hv;
+    double2 *ybuf = y0 + h * hv;
+    __syncthreads();
+    double2 pf = c_make(1, 0);
+    for (int k = 0; k < m; k += 2) {
+        const double2 x = (q > k && q < m) ? A[q * lda + k] : c_make(0, 0);
+        const double nx2 = grp_sum<32>(c_abs2(x));
+        const double2 xf = grp_bcast<32>(x, k + 1);
+        const double nx = sqrt(nx2);
+        const double ax = sqrt(c_abs2(xf));
+        const double2 phs = ax > 0.0 ? c_scale(xf, 1.0 / ax) : c_make(1, 0);
+        const double2 alpha = c_scale(phs, -nx);
+        pf = c_mul(pf, alpha);
+        if (k + 2 >= m) break;
+        const double beta = nx > 0.0 ? 1.0 / (nx2 + nx * ax) : 0.0;
+        const double2 u = (q == k + 1) ? c_sub(xf, alpha) : x;
+        if (q >= k + 1 && q < m) ubuf[q] = c_conj(u);
+        __syncthreads();
+        double2 y = c_make(0, 0);
+        if (q >= k + 2 && q < m)
+            for (int j = k + 1; j < m; ++j) y = c_fma(A[q * lda + j], ubuf[j], y);
+        y = c_scale(y, beta);
+        if (q >= k + 2 && q < m) ybuf[q] = y;
+        __syncthreads();
+        if (q >= k + 2 && q < m)
+            for (int j = k + 2; j < m; ++j)
+                A[q * lda + j] = c_fma(u, ybuf[j], c_fma(c_neg(y), c_conj(ubuf[j]), A[q * lda + j]));
+        __syncthreads();
+    }
+    __syncthreads();
+    return pf;
+}
+
 // Dynamic LDS of k_fallback (bytes), m = 2n - eta, d = 2n: the staged
 // operands C' (d x d) and Xall (d x (d + 1), rows padded to an odd stride),
-// which the node matrix (m x (m + 1) complex) overlays once B is built; then
-// B (m x m complex), kept across the nodes; then 2m complex for the
-// formation's row buffer and the Householder vectors.
+// which the node matrices overlay once B is built (two of m x (m + 1)
+// complex for m <= 32, when the two halves of the wave take a node each,
+// else one); then B (m x m complex), kept across the nodes; then the
+// Householder vectors (2m complex per node matrix), the first d of which
+// also serve as the formation's row buffer.
+__host__ __device__ inline int fb_node_mats(int n, int eta) { return 2 * n - eta <= 32 ? 2 : 1; }
 __host__ __device__ inline size_t fb_stage_bytes(int n, int eta) {
     const size_t m = (size_t)(2 * n - eta), d = (size_t)(2 * n);
     size_t stage = (d * d + d * (d + 1)) * sizeof(double);
-    const size_t a = m * (m + 1) * sizeof(double2);
+    const size_t a = (size_t)fb_node_mats(n, eta) * m * (m + 1) * sizeof(double2);
     if (a > stage) stage = a;
     return (stage + 15) & ~(size_t)15;
 }
 __host__ __device__ inline size_t fb_lds_bytes(int n, int eta) {
     const size_t m = (size_t)(2 * n - eta);
-    return fb_stage_bytes(n, eta) + (m * m + 2 * m) * sizeof(double2);
+    return fb_stage_bytes(n, eta) + (m * m + 2 * m * fb_node_mats(n, eta)) * sizeof(double2);
 }
 
 // o_ws of walker w and shadow s on the full-size path (one wave); lds is the
@@ -129,6 +173,30 @@ __device__ __forceinline__ double2 fb_pair(int n, int eta, const double *__restr
     }
     __syncthreads();
     double2 o = c_make(0, 0);
+    if (fb_node_mats(n, eta) == 2) {
+        // two nodes per pass, one per 32-lane half
+        const int h = q >> 5, qq = q & 31, hA = m * LDA;
+        for (int node = 0; node < Ke; node += 2) {
+            const int jn = node + h;
+            const bool live = jn < Ke;
+            const double2 ck = tab.e[live ? jn : node];
+            double2 *Ah = A + h * hA;
+            __syncthreads();
+            if (qq < m)
+                for (int j = 0; j < m; ++j) {
+                    double2 v = (j > qq) ? Bl[qq * m + j] : ((j < qq) ? c_neg(Bl[j * m + qq]) : c_make(0, 0));
+                    if (qq >= eta && j >= eta) {
+                        const int t = qq - eta;
+                        if (j - eta == 2 * ne - 1 - t) v = c_add(v, c_scale(ck, t < ne ? 1.0 : -1.0));
+                    }
+                    Ah[qq * LDA + j] = v;
+                }
+            const double2 pf = hh_pf_lds2(A, LDA, m, ubuf, ubuf + m, hA, 2 * m, q);
+            if (live) o = c_fma(tab.v[jn], pf, o);
+        }
+        // each half holds its nodes' share: the total in every lane
+        return c_make(o.x + __shfl_xor(o.x, 32, 64), o.y + __shfl_xor(o.y, 32, 64));
+    }
     for (int node = 0; node < Ke; ++node) {
         const double2 ck = tab.e[node];
         __syncthreads();
