@@ -47,18 +47,19 @@ def run(B, w, t, L):
     return S_.cpu().numpy(), N_.cpu().numpy(), E_.cpu().numpy(), st.cpu().numpy()
 
 
-def check(Sg, Ng, Eg, o, e):
+def check(Sg, Ng, Eg, o, e, tol=1e-9):
     """Walker sums and, element by element, the pair terms of the last run."""
     for name, r in (("o", o), ("e", e)):
         g = LAST_PAIRS[name]
         scale = np.maximum(np.abs(r), np.abs(r).mean(axis=1, keepdims=True))
-        assert np.all(np.abs(g - r) <= 1e-9 * scale), f"pair {name}: {(np.abs(g - r) / scale).max():.2e}"
+        assert np.all(np.abs(g - r) <= tol * scale), f"pair {name}: {(np.abs(g - r) / scale).max():.2e}"
+        print(f"pair {name}: worst {(np.abs(g - r) / scale).max():.2e} of the scale")
     So, No = o.mean(axis=1), e.mean(axis=1)
     so, se = np.abs(o).mean(axis=1), np.abs(e).mean(axis=1)
-    assert np.all(np.abs(Sg - So) <= 1e-9 * so), np.abs(Sg - So) / so
-    assert np.all(np.abs(Ng - No) <= 1e-9 * se), np.abs(Ng - No) / se
+    assert np.all(np.abs(Sg - So) <= tol * so), np.abs(Sg - So) / so
+    assert np.all(np.abs(Ng - No) <= tol * se), np.abs(Ng - No) / se
     Eo = No / So
-    assert np.all(np.abs(Eg - Eo) <= 1e-8 * np.abs(Eo)), np.abs(Eg - Eo) / np.abs(Eo)
+    assert np.all(np.abs(Eg - Eo) <= 10 * tol * np.abs(Eo)), np.abs(Eg - Eo) / np.abs(Eo)
 
 
 CASES = [  # n, eta, W, S, n_gamma
@@ -80,6 +81,27 @@ def test_energy_matches_oracle(B, n, eta, W, S, ng):
     assert not st.any()
     o, e = oracle.energy_pairs(w.phi, w.Q, w.bits, t, L)
     check(Sg, Ng, Eg, o, e)
+
+
+@pytest.mark.parametrize("n,eta,W,S,ng", [(10, 4, 3, 6, 8), (12, 6, 3, 6, 10), (16, 8, 2, 5, 12)])
+def test_energy_signed_permutation_shadows(B, n, eta, W, S, ng):
+    """The paper's own shadow ensemble (random signed permutations) through the
+    local energy, against the oracle pair by pair.  The kernel's nodes avoid
+    +-1 and +-i, where Q of such shadows has exact roots.  Tolerance 1e-7: on
+    this ensemble the oracle's Chebyshev route agrees with itself across node
+    counts (K = n + 1, n + 2, n + 4) to 2e-10 at n = 10, 12 and 1.2e-8 at
+    n = 16.  At n = 8 some of these shadows make B + cJ singular for every c,
+    where the route through A^{-1} is undefined on both sides."""
+    print(f"energy signed permutations n={n} eta={eta}", flush=True)
+    rng = np.random.default_rng(4400 + n)
+    w = wl.make("ep", n, eta, W, S, seed=4410 + n, n_gamma=ng, with_t=True)
+    Q = wl.signed_permutations(rng, S, 2 * n)
+    w.Q[:] = Q
+    Sg, Ng, Eg, st = run(B, w, w.t, w.L)
+    ok = (st & ~B.SO_WSTAT_SINGULAR) == 0
+    assert ok.all() and not (st & B.SO_WSTAT_SINGULAR).any()
+    o, e = oracle.energy_pairs(w.phi, w.Q, w.bits, w.t, w.L)
+    check(Sg, Ng, Eg, o, e, tol=1e-7)
 
 
 @pytest.mark.parametrize("n,eta,W,S,ng", [(6, 2, 2, 5, 4), (10, 6, 2, 4, 6), (16, 8, 1, 3, 12)])
