@@ -188,7 +188,11 @@ so_status shadow_overlap_noalloc(const so_params *p, const so_c64 *phi, int64_t 
  *   green     [n_walkers][n][n] complex128 out, or NULL: mixed Green's function
  *             G_pq = <Psi_T|a_p^dag a_q|phi>/<Psi_T|phi> = (D_w Phi_w^T)_pq
  *   other arguments as in shadow_overlap (workspace from with_grad = 1).
- * Walkers with S_w == 0 get SO_WSTAT_ZERO and NaN derivatives.
+ * Walkers with S_w == 0 get SO_WSTAT_ZERO and NaN derivatives.  The pairs are
+ * evaluated at each walker's orthonormal factor Q_w (Phi_w = Q_w R_w, a
+ * Householder QR) and carried back: S_w = det R_w S(Q_w), D_w = D(Q_w) R_w^{-T},
+ * G_w = G(Q_w); so walkers of any norm a double holds keep full accuracy, and
+ * with SO_FLAG_LOG_OUTPUT log S_w stays finite where S_w itself is not.
  * Supported shapes: n - eta even with 2 <= n - eta <= 8 and n <= 16 (the
  * paper's N = 16, eta = 8 included); others return SO_ERR_UNSUPPORTED.
  * Deterministic (fixed reduction order). */

@@ -310,6 +310,7 @@ constexpr int64_t kRdmBlocks = 2048;                    // blocks of the density
 
 struct Layout {
     size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_F, off_O, off_M, off_LD;
+    size_t off_QF, off_RF;     // derivative path: the walkers' QR factors Phi = Qf R
     size_t off_X32, off_C32;   // single-precision formation operands (mixed precision)
     size_t total;
     int Sc;
@@ -361,11 +362,13 @@ Layout make_layout(int n, int eta, int64_t W, int64_t S, bool with_grad = false,
     L.off_fbc = o; o = align_up(o + sizeof(so_u64));
     L.off_fbl = o; o = align_up(o + (size_t)cap * sizeof(int64_t));
     L.Gy = 0;
-    L.off_F = L.off_O = o;
+    L.off_F = L.off_O = L.off_QF = L.off_RF = o;
     if (with_grad) {
         L.Gy = grad_ranges(W, S);
         L.off_F = o; o = align_up(o + (size_t)W * L.Gy * 2 * n * m * sizeof(double2));
         L.off_O = o; o = align_up(o + (size_t)W * L.Gy * sizeof(double2));
+        L.off_QF = o; o = align_up(o + (size_t)W * n * eta * sizeof(double2));
+        L.off_RF = o; o = align_up(o + (size_t)W * eta * eta * sizeof(double2));
     }
     L.off_X32 = L.off_C32 = o;
     if (mixed) {
@@ -1099,14 +1102,19 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
     so_u64 *fbc = reinterpret_cast<so_u64 *>(ws + L.off_fbc);
     double2 *Fp = reinterpret_cast<double2 *>(ws + L.off_F);
     double2 *Op = reinterpret_cast<double2 *>(ws + L.off_O);
+    double2 *Qf = reinterpret_cast<double2 *>(ws + L.off_QF);
+    double2 *Rf = reinterpret_cast<double2 *>(ws + L.off_RF);
+    double2 *Ld = reinterpret_cast<double2 *>(ws + L.off_LD);
     NodeTab tab;
     build_nodetab(p, K, &tab);
     RedTab rt;
     std::memset(&rt, 0, sizeof(rt));
     for (int j = 0; j < tab.Ke; ++j) { rt.e[j] = tab.e[j]; rt.v[j] = tab.v[j]; }
 
+    // Phi = Qf R: the pairs are evaluated at Qf and k_grad_walker carries
+    // S, D and G back to Phi, so no node Pfaffian depends on the walker norm
     hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
-                       reinterpret_cast<const double2 *>(phi), Xa, wst, fbc, static_cast<double2 *>(nullptr));
+                       reinterpret_cast<const double2 *>(phi), Xa, wst, fbc, Ld, Qf, Rf);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q,
                        bits, Ca);
@@ -1133,10 +1141,10 @@ so_status shadow_overlap_grad(const so_params *p, const so_c64 *phi, int64_t n_w
 #undef SO_GRAD_LAUNCH
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     if (prof_end(st, ea, PROF_GRAD, W * S) != hipSuccess) return SO_ERR_HIP;
-    hipLaunchKernelGGL(k_grad_walker, dim3((unsigned)W), dim3(64), 0, st, n, eta,
-                       reinterpret_cast<const double2 *>(phi), Xa, Fp, Op, L.Gy, S,
-                       reinterpret_cast<double2 *>(overlap), reinterpret_cast<double2 *>(dlog),
-                       reinterpret_cast<double2 *>(green), wst, (p->flags & SO_FLAG_LOG_OUTPUT) ? 1 : 0);
+    hipLaunchKernelGGL(k_grad_walker, dim3((unsigned)W), dim3(64), 0, st, n, eta, static_cast<const double2 *>(Qf),
+                       Xa, Fp, Op, L.Gy, S, reinterpret_cast<double2 *>(overlap), reinterpret_cast<double2 *>(dlog),
+                       reinterpret_cast<double2 *>(green), wst, (p->flags & SO_FLAG_LOG_OUTPUT) ? 1 : 0,
+                       static_cast<const double2 *>(Rf), static_cast<const double2 *>(Ld));
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     return SO_OK;
 }

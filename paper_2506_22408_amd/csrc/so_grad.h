@@ -618,11 +618,18 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
 // g_t its complement vector ((G^{-1})_{eta+t, p} = conj(g_t[p])) and
 // Phi+ = (Phi^H Phi)^{-1} Phi^H the first eta rows of G^{-1}.  Then
 // D = (d sum_s o / d Phi) / sum_s o, G = D Phi^T, S_w = sum_s o / S.
+// With rf and logdet, phi is the orthonormal factor Qf of the walker
+// Phi = Qf R (k_walker_prep) and the pairs were evaluated at Qf.  The
+// overlap is multilinear in the orbitals, S(Psi A) = det A S(Psi) for every
+// invertible eta x eta A, so S(Phi) = det R S(Qf), D(Phi) = D(Qf) R^{-T} and
+// G(Phi) = G(Qf): the outputs reach every walker norm that a double can hold
+// without a node Pfaffian leaving the double range.
 __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double2 *__restrict__ phi,
                                                     const double *__restrict__ Xa, const double2 *__restrict__ Fpart,
                                                     const double2 *__restrict__ Opart, int Gy, int64_t S_total,
                                                     double2 *__restrict__ overlap, double2 *__restrict__ dlog,
-                                                    double2 *__restrict__ green, int32_t *__restrict__ wstat, int logout) {
+                                                    double2 *__restrict__ green, int32_t *__restrict__ wstat, int logout,
+                                                    const double2 *__restrict__ rf, const double2 *__restrict__ logdet) {
     __shared__ double2 Fs[2 * SO_GRAD_NMAX * SO_GRAD_MMAX];
     __shared__ double2 Ph[SO_GRAD_NMAX * SO_GRAD_NMAX];        // Phi (n x eta)
     __shared__ double2 Gm[SO_GRAD_NMAX * 2 * SO_GRAD_NMAX];    // [Phi^H Phi | I] (eta x 2 eta)
@@ -692,7 +699,7 @@ __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double
         }
         const double2 dv = zero ? c_make(NAN, NAN) : c_mul(gv, rinv);
         Dd[e] = dv;
-        dlog[(size_t)w * n * eta + e] = dv;
+        if (!rf) dlog[(size_t)w * n * eta + e] = dv;
     }
     __syncthreads();
     if (green)
@@ -702,6 +709,22 @@ __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double
             for (int j = 0; j < eta; ++j) v = c_fma(Dd[p * eta + j], Ph[q * eta + j], v);
             green[(size_t)w * n * n + e] = v;
         }
+    // with rf: phi holds the orthonormal factor Qf of the caller's walker
+    // Phi = Qf R.  G = D Phi^T does not change (the state is the same up to
+    // scale), and D(Phi) = D(Qf) R^{-T}: row p of D solves D[p] R^T = D(Qf)[p]
+    if (rf) {
+        __syncthreads();
+        if (l < n) {
+            const double2 *Rw = rf + (size_t)w * eta * eta;
+            double2 *Dr = Dd + l * eta;
+            for (int j = eta - 1; j >= 0; --j) {
+                double2 v = Dr[j];
+                for (int i = j + 1; i < eta; ++i) v = c_sub(v, c_mul(Dr[i], Rw[j * eta + i]));
+                Dr[j] = c_mul(v, c_inv(Rw[j * eta + j]));
+                dlog[(size_t)w * n * eta + l * eta + j] = Dr[j];
+            }
+        }
+    }
     if (l == 0) {
         int32_t st = wstat[w];
         double2 r = c_scale(osum, 1.0 / (double)S_total);
@@ -709,7 +732,15 @@ __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double
         if (zero) st |= SO_WSTAT_ZERO;
         if (!ok) st |= SO_WSTAT_RANK;
         if (!isfinite(r.x) || !isfinite(r.y)) st |= SO_WSTAT_NONFINITE;
-        overlap[w] = logout ? c_log(r) : r;
+        if (logout) {
+            r = c_log(r);
+            if (logdet) r = c_make(r.x + logdet[w].x, remainder(r.y + logdet[w].y, 2.0 * M_PI));
+        } else if (logdet) {
+            const double mg = exp(logdet[w].x);
+            r = c_mul(c_make(mg * cos(logdet[w].y), mg * sin(logdet[w].y)), r);
+            if (!isfinite(r.x) || !isfinite(r.y)) st |= SO_WSTAT_NONFINITE;
+        }
+        overlap[w] = r;
         wstat[w] = st;
     }
 }

@@ -32,12 +32,17 @@
 // kernels evaluate o(Qf), whose node Pfaffians are bounded for every walker
 // norm, and k_reduce applies det R (in log form when the log output is asked
 // for).  Without logdet (derivative and energy paths, which differentiate
-// through Phi) X_O comes from Phi itself.
+// through Phi) X_O comes from Phi itself.  With qf and rf (the derivative
+// path) the factors Qf (n x eta) and R (eta x eta) are written out as well:
+// the derivative is then taken at Qf and carried back to Phi
+// (k_grad_walker).
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double2 *__restrict__ phi,
                                                     double *__restrict__ Xa, int32_t *__restrict__ wstat,
                                                     so_u64 *__restrict__ fb_count,
-                                                    double2 *__restrict__ logdet = nullptr) {
+                                                    double2 *__restrict__ logdet = nullptr,
+                                                    double2 *__restrict__ qf = nullptr,
+                                                    double2 *__restrict__ rf = nullptr) {
     __shared__ double2 R[SO_NMAX][SO_NMAX];
     __shared__ double2 V[SO_NMAX][SO_NMAX];
     __shared__ double betas[SO_NMAX];
@@ -90,6 +95,10 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
             __syncthreads();
         }
     }
+    // with rf: R (eta x eta, upper triangular, row-major) before R's rows are reused
+    if (rf && p < eta)
+        for (int c = 0; c < eta; ++c) rf[((size_t)w * eta + p) * eta + c] = c >= p ? R[p][c] : c_make(0, 0);
+    __syncthreads();
     // g_t = H_0 ... H_{eta-1} e_{eta+t}, kept in R[t][.] (R is no longer
     // needed); with logdet also the orthonormal factor's columns
     // q_j = H_0 ... H_{eta-1} e_j, kept in R[ne + j][.]
@@ -135,6 +144,9 @@ __global__ __launch_bounds__(64) void k_walker_prep(int n, int eta, const double
     }
     if (p == 0 && wstat) wstat[w] = (rank_ok ? 0 : SO_WSTAT_RANK) | (finite ? 0 : SO_WSTAT_NONFINITE);
     if (p == 0 && logdet) logdet[w] = c_make(lmag, remainder(larg, 2.0 * M_PI));
+    // with qf: the orthonormal factor (n x eta, row-major like Phi)
+    if (qf && logdet && p < n)
+        for (int j = 0; j < eta; ++j) qf[((size_t)w * n + p) * eta + j] = R[ne + j][p];
 }
 
 // --------------------------------------------------------------------------

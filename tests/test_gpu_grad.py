@@ -245,6 +245,42 @@ def test_grad_zero_overlap_is_flagged(B):
     assert np.all(np.isnan(dg)) and np.all(np.isnan(gg))
 
 
+def test_grad_under_right_multiplication_of_the_walkers(B):
+    """The overlap is multilinear in the walker's orbitals, so for every
+    invertible eta x eta A: S(Phi A) = det A S(Phi), D(Phi A) = D(Phi) A^{-T}
+    and G(Phi A) = G(Phi).  A random well-conditioned A, and A = c I with
+    c = 1e+-20 and 1e+-60 (c^8 outside double precision at 1e+-60, where the
+    log output holds log S(Phi) + eta log c exactly and the walker's
+    Householder factors keep D and G at full accuracy)."""
+    n, eta, W, S = 16, 8, 4, 23
+    w = wl.make("gr", n, eta, W, S, seed=83)
+    s0, d0, g0, st0 = gpu_grad(B, w.phi, w.Q, w.bits)
+    assert not st0.any()
+    rng = np.random.default_rng(84)
+    A = np.eye(eta) + 0.3 * (rng.standard_normal((W, eta, eta)) + 1j * rng.standard_normal((W, eta, eta)))
+    sa, da, ga, sta = gpu_grad(B, w.phi @ A, w.Q, w.bits)
+    assert not sta.any()
+    assert np.all(np.abs(sa - np.linalg.det(A) * s0) <= 1e-10 * np.abs(sa))
+    close_per_walker(da, d0 @ np.linalg.inv(A).transpose(0, 2, 1), 1e-10)
+    close_per_walker(ga, g0, 1e-10)
+    Q, bits = w.Q, w.bits
+    l0 = B.shadow_overlap_grad(*to_dev(w.phi, Q, bits), log_output=True)[0].cpu().numpy()
+    for c in (1e-60, 1e-20, 1e20, 1e60):
+        lc, dc, gc, stc = (t.cpu().numpy() for t in B.shadow_overlap_grad(*to_dev(w.phi * c, Q, bits),
+                                                                            log_output=True))
+        assert not stc.any()
+        dl = lc - (l0 + eta * np.log(c))
+        dl = dl.real + 1j * ((dl.imag + np.pi) % (2 * np.pi) - np.pi)
+        assert np.all(np.abs(dl) <= 1e-12 * np.abs(lc.real) + 1e-12), (c, dl)
+        close_per_walker(dc, d0 / c, 1e-10)
+        close_per_walker(gc, g0, 1e-10)
+        _, _, _, sp = gpu_grad(B, w.phi * c, Q, bits)
+        if c > 1 and eta * np.log10(c) > 308:
+            assert (sp & B.SO_WSTAT_NONFINITE).all()
+        else:
+            assert not sp.any()
+
+
 def test_grad_unsupported_shapes_are_refused(B):
     for n, eta in ((16, 2), (20, 16), (9, 4)):       # ne = 14; n > 16; ne odd
         w = wl.make("u", n, eta, 2, 3, seed=1)
