@@ -47,13 +47,17 @@ __device__ __forceinline__ double2 grp_bcast(double2 v, int src) {
 }
 
 // ---- DPP within 16-lane rows ------------------------------------------------
+// Every move below writes every lane (all row and bank masks set, and each
+// pattern reads a lane of the same row), so no lane keeps its old value: the
+// moves take no "old" operand and the compiler need not copy the source into
+// the destination first.
 // a 32-bit DPP move applied to both halves of a double
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64_32(double v) {
     const long long b = __double_as_longlong(v);
     int lo = (int)b, hi = (int)(b >> 32);
-    lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
-    hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+    lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, false);
     return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
 }
 // broadcast lane SRC of each 16-lane row to the whole row (row_newbcast, a
@@ -61,7 +65,7 @@ __device__ __forceinline__ double dpp_f64_32(double v) {
 template <int SRC>
 __device__ __forceinline__ double bc16(double v) {
     long long b = __double_as_longlong(v);
-    b = __builtin_amdgcn_update_dpp(b, b, 0x150 + SRC, 0xf, 0xf, false);
+    b = __builtin_amdgcn_mov_dpp(b, 0x150 + SRC, 0xf, 0xf, false);
     return __longlong_as_double(b);
 }
 template <int SRC>
@@ -108,10 +112,10 @@ __device__ __forceinline__ double2 c_inv_nr(double2 a) {
 // row_mirror leave every lane of a row with the row's maximum), then the four
 // rows on the scalar unit
 __device__ __forceinline__ unsigned wave_max_u32(unsigned v) {
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xf, 0xf, false));
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xf, 0xf, false));
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xf, 0xf, false));
-    v = max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xf, 0xf, false));
+    v = max(v, (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xf, 0xf, false));
     const unsigned a = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
     const unsigned b = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
     const unsigned c = (unsigned)__builtin_amdgcn_readlane((int)v, 32);

@@ -131,7 +131,7 @@ __device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int 
                  if (a > best) { best = a; bi = r; }
              }
              const double bk = bc16<k>(best);
-             const int p = __builtin_amdgcn_update_dpp(bi, bi, 0x150 + k, 0xf, 0xf, false);
+             const int p = __builtin_amdgcn_mov_dpp(bi, 0x150 + k, 0xf, 0xf, false);
              zero = zero || !(bk > 0.0);
 #pragma unroll
              for (int r = k + 1; r < NE; ++r)
@@ -251,7 +251,7 @@ __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
 // Opart[w Gy + gy].  Both waves execute every barrier; steps that one wave
 // does alone contain none.
 template <int T, int NE>
-__global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const double2 *__restrict__ Xa,
+__global__ __launch_bounds__(128, 2) void k_grad_pair(int n_in, int eta_in, const double2 *__restrict__ Xa,
                                                       const double2 *__restrict__ Ca, int64_t S_total, int spw,
                                                       RedTab tab, double2 *__restrict__ Fpart,
                                                       double2 *__restrict__ Opart, int32_t *__restrict__ wstat) {
@@ -265,28 +265,9 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
     constexpr int TM = (8 * T + NE + 15) / 16;              // 16-row tiles of F^T (m = n + NE <= 8T + NE)
     // GW, SWP: row strides of RG and of the solution rows, odd in complex
     // entries so that a column read by consecutive rows spreads over the banks
-    const int m = n + NE, d = 2 * n, WR = n + 2 * NE, GW = n + 2 * NE + 1, SWP = n + 2 * NE + 1;
+    const int n = n_in, eta = eta_in;
+    const int m = n + NE, d = 2 * n;
     const int t0 = threadIdx.x, wv = t0 >> 6, w = blockIdx.x;
-    extern __shared__ double lds[];
-    const GradLds L = grad_lds(T, n, NE);
-    char *base = reinterpret_cast<char *>(lds);
-    double *RP = reinterpret_cast<double *>(base);
-    double2 *RA = reinterpret_cast<double2 *>(base);   // over P once B is built
-    double2 *NJ = RA;                                  // node inverses, before Abar
-    double2 *RB = reinterpret_cast<double2 *>(base + L.rp);
-    double2 *RR = reinterpret_cast<double2 *>(base + L.rp + L.rb);
-    double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr);
-    double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr + L.rg);
-    double2 *Mup = RS;                       // M0, M1, M2 upper triangles
-    double2 *pfm = RS + 3 * NT;              // Pf(M(e_j))
-    double2 *piv = pfm + KE;                 // the pivots a of B_KK's 2 x 2 blocks
-    int *pis = reinterpret_cast<int *>(piv + SO_GRAD_NMAX / 2);
-    double *xred = reinterpret_cast<double *>(pis + SO_GRAD_NMAX);
-    double2 *Ahat = RR;                      // A_0, A_1, A_2 (NE x NE each)
-    double2 *Zr = RR + 3 * NE * NE;          // Z, Z' (n x NE each)
-    double2 *ubuf = RR + 2 * m * m;          // Householder vectors of the full-size route
-    double2 *ybuf = ubuf + m;
-
     // trailing entries (a < b) of the 2NE x 2NE block handled by this thread
     int ta[NTQ], tb[NTQ];
 #pragma unroll
@@ -298,23 +279,6 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
         tb[q] = a + 1 + e;
     }
     const double2 *Xw = Xa + (size_t)w * MAT2;
-    auto rre = [&](int i) -> int { return i < eta ? i : eta + i; };
-    auto rim = [&](int i) -> int { return i < eta ? eta + i : DP; };
-    // J of the stored order: +1 at (eta+t, eta+2ne-1-t), -1 at the transpose
-    auto Jel = [&](int i, int j) -> double {
-        if (i < eta || j < eta) return 0.0;
-        const int u = i - eta, v = j - eta;
-        return (u + v == 2 * NE - 1) ? (u < NE ? 1.0 : -1.0) : 0.0;
-    };
-    // block-wide maximum of a value that each wave has reduced
-    auto block_max = [&](double v) -> double {
-        if ((t0 & 63) == 0) xred[wv] = v;
-        __syncthreads();
-        const double r = fmax(xred[0], xred[1]);
-        __syncthreads();
-        return r;
-    };
-
     // F^T = sum over the range of Abar''^T (Xall C'^T), real and imaginary
     // parts, in the matrix-core accumulators: wave wv holds the column tile
     // J = wv (tile (I, J), register r, lane l: F^T[16 I + 4 r + l/16][16 J + l%16])
@@ -329,6 +293,49 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n, int eta, const doub
     const int64_t s0 = (int64_t)blockIdx.y * spw;
     const int64_t s1 = min(S_total, s0 + spw);
     for (int64_t s = s0; s < s1; ++s) {
+        // n and eta through an opaque move as well: the uniform values derived
+        // from them (LDS offsets, row strides) are recomputed per pair on the
+        // scalar unit instead of being hoisted out of the shadow loop, where
+        // they would exceed the scalar registers and be kept in vector-register
+        // lanes (a vector instruction per reload)
+        int n = n_in, eta = eta_in;
+        asm volatile("" : "+s"(n), "+s"(eta));
+        const int m = n + NE, d = 2 * n, WR = n + 2 * NE, GW = n + 2 * NE + 1, SWP = n + 2 * NE + 1;
+        extern __shared__ double lds[];
+        const GradLds L = grad_lds(T, n, NE);
+        char *base = reinterpret_cast<char *>(lds);
+        double *RP = reinterpret_cast<double *>(base);
+        double2 *RA = reinterpret_cast<double2 *>(base);   // over P once B is built
+        double2 *NJ = RA;                                  // node inverses, before Abar
+        double2 *RB = reinterpret_cast<double2 *>(base + L.rp);
+        double2 *RR = reinterpret_cast<double2 *>(base + L.rp + L.rb);
+        double2 *RG = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr);
+        double2 *RS = reinterpret_cast<double2 *>(base + L.rp + L.rb + L.rr + L.rg);
+        double2 *Mup = RS;                       // M0, M1, M2 upper triangles
+        double2 *pfm = RS + 3 * NT;              // Pf(M(e_j))
+        double2 *piv = pfm + KE;                 // the pivots a of B_KK's 2 x 2 blocks
+        int *pis = reinterpret_cast<int *>(piv + SO_GRAD_NMAX / 2);
+        double *xred = reinterpret_cast<double *>(pis + SO_GRAD_NMAX);
+        double2 *Ahat = RR;                      // A_0, A_1, A_2 (NE x NE each)
+        double2 *Zr = RR + 3 * NE * NE;          // Z, Z' (n x NE each)
+        double2 *ubuf = RR + 2 * m * m;          // Householder vectors of the full-size route
+        double2 *ybuf = ubuf + m;
+        auto rre = [&](int i) -> int { return i < eta ? i : eta + i; };
+        auto rim = [&](int i) -> int { return i < eta ? eta + i : DP; };
+        // J of the stored order: +1 at (eta+t, eta+2ne-1-t), -1 at the transpose
+        auto Jel = [&](int i, int j) -> double {
+            if (i < eta || j < eta) return 0.0;
+            const int u = i - eta, v = j - eta;
+            return (u + v == 2 * NE - 1) ? (u < NE ? 1.0 : -1.0) : 0.0;
+        };
+        // block-wide maximum of a value that each wave has reduced
+        auto block_max = [&](double v) -> double {
+            if ((t0 & 63) == 0) xred[wv] = v;
+            __syncthreads();
+            const double r = fmax(xred[0], xred[1]);
+            __syncthreads();
+            return r;
+        };
         // the thread index through an opaque move: indices derived from it are
         // recomputed per pair instead of being hoisted out of the shadow loop,
         // where they would stay live (and spill) through every stage
