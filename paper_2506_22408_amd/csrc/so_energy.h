@@ -193,7 +193,7 @@ __host__ __device__ inline size_t energy_lds_bytes(int n, int eta) {
 // mostly leave LDS for one or two blocks (115 KB at n = 24, eta = 12), and the
 // register budget of two blocks avoids the spills (1.26x at that shape).
 template <int T>
-__global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(int n, int eta, const double2 *__restrict__ Xr,
+__global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(int n_in, int eta_in, const double2 *__restrict__ Xr,
                                                                const double *__restrict__ Cr,
                                                                const double *__restrict__ Ms,
                                                                const double *__restrict__ Vt,
@@ -209,6 +209,7 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
     __shared__ int ri[1];
     __shared__ int piv[DM];
     const int t = threadIdx.x;
+    const int n = n_in, eta = eta_in;
     const int d = 2 * n, m = 2 * n - eta, ne = n - eta, n2 = n * n;
     const int asz = m * m > 2 * n2 ? m * m : 2 * n2;
     double2 *Bm = esm;                // m x m
@@ -237,20 +238,38 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
     __syncthreads();
     double2 osum = c_make(0.0, 0.0), esum = c_make(0.0, 0.0);
     bool singular = false;
-    auto build_a = [&](double2 sk, double2 ck) {
-        for (int e = t; e < m * m; e += SO_EN_THREADS) {
-            const int i = e / m, j = e - i * m;
-            double2 v = c_mul(sk, Bm[e]);
-            if (i >= eta && j >= eta) {
-                const int u = i - eta, v2 = j - eta;
-                if (u < ne && v2 == 2 * ne - 1 - u) v = c_add(v, ck);
-                else if (u >= ne && v2 == 2 * ne - 1 - u) v = c_sub(v, ck);
-            }
-            A[e] = v;
-        }
-        __syncthreads();
-    };
     for (int k = 0; k < tab.K; ++k) {
+        // the sizes, the LDS layout and the thread index again, through opaque
+        // moves: what derives from them is recomputed per node (scalar unit,
+        // one vector add) instead of being hoisted out of the node loop and
+        // kept live, and spilled, through every stage of it
+        int n = n_in, eta = eta_in;
+        asm volatile("" : "+s"(n), "+s"(eta));
+        int t = threadIdx.x;
+        asm volatile("" : "+v"(t));
+        const int d = 2 * n, m = 2 * n - eta, ne = n - eta, n2 = n * n;
+        const int asz = m * m > 2 * n2 ? m * m : 2 * n2;
+        double2 *Bm = esm;
+        double2 *A = Bm + m * m;
+        double2 *YZ = A + asz;
+        double2 *Yt = YZ + d * d;
+        double2 *zeta = A, *zetaT = A + n2;
+        const double2 *X = Xr + w0 * m * d;
+        const double *C = Cr + s0 * d * d;
+        const double *Mg = Ms + s0 * d * d;
+        auto build_a = [&](double2 sk, double2 ck) {
+            for (int e = t; e < m * m; e += SO_EN_THREADS) {
+                const int i = e / m, j = e - i * m;
+                double2 v = c_mul(sk, Bm[e]);
+                if (i >= eta && j >= eta) {
+                    const int u = i - eta, v2 = j - eta;
+                    if (u < ne && v2 == 2 * ne - 1 - u) v = c_add(v, ck);
+                    else if (u >= ne && v2 == 2 * ne - 1 - u) v = c_sub(v, ck);
+                }
+                A[e] = v;
+            }
+            __syncthreads();
+        };
         const double2 sk = tab.s[k], ck = tab.c[k], wk = tab.w[k];
         // ---- Pf(A) and YZ = A^{-1} X by one pairwise (Parlett-Reid) elimination
         // with partial pivoting that carries X as right-hand sides (A destroyed).
