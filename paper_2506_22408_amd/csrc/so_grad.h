@@ -16,7 +16,8 @@
 //   Abar_LK =  pfk Z^T,
 //   Abar_KK = o B_KK^{-1} + pfk (Z Y0^T + Z' Y1^T),   Z' = Y0 A_1 + Y1 A_2.
 // Y0, Y1 and B_KK^{-1} come from the pivoted elimination of K and a back
-// substitution; the N_j from Gauss-Jordan passes over [M_j | I].  Each node's
+// substitution; N_j and Pf(M_j) from Gauss-Jordan passes over [M_j | I] (Pf as
+// the root of det M_j = Pf(M_j)^2 that the pivots give, pf_sign_row).  Each node's
 // Pf(M_j) weights both its N_j and its share of o, so the large parts of
 // o B_KK^{-1} and Y N Y^T cancel node by node when B_KK is ill conditioned
 // (interpolating Pf(M) N from ne - 1 other nodes, a polynomial of degree
@@ -99,9 +100,12 @@ __device__ __forceinline__ bool gj_wave(double2 *G, int nr, int nc, int l, bool 
 // column c of M(c) and lane NE + y column y of the identity; the steps use DPP
 // broadcasts inside the row.  On return lane NE + y holds column y of
 // M(c)^{-1} in col[0..NE).  The pivot is the largest |M[r][k]|, the first one
-// on ties; a zero pivot column sets sing.
+// on ties; a zero pivot column sets sing.  det receives det M(c), the signed
+// product of the pivots, and the upper triangle of M(c) is left at Mf
+// (row-major, NE x NE) for pf_sign_row.
 template <int NE>
-__device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int c, bool &sing, double2 (&col)[NE]) {
+__device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int c, bool &sing, double2 (&col)[NE],
+                                            double2 &det, double2 *Mf) {
     constexpr int NT = NE * (NE - 1) / 2;
     const double2 cj2 = c_mul(cj, cj);
 #pragma unroll
@@ -118,8 +122,10 @@ __device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int 
             v = c_make(1.0, 0.0);
         }
         col[r] = v;
+        if (c < NE && r < c) Mf[r * NE + c] = v;
     }
     bool zero = false;
+    det = c_make(1.0, 0.0);
     [&]<int... K>(std::integer_sequence<int, K...>) {
         (([&] {
              constexpr int k = K;
@@ -141,6 +147,7 @@ __device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int 
                      col[r] = tmp;
                  }
              const double2 piv = bc16c<k>(col[k]);
+             det = c_mul(p != k ? c_neg(det) : det, piv);
              col[k] = c_mul(col[k], c_inv_nr(bk > 0.0 ? piv : c_make(1.0, 0.0)));
 #pragma unroll
              for (int r = 0; r < NE; ++r)
@@ -151,6 +158,76 @@ __device__ __forceinline__ void gj_node_row(const double2 *Mup, double2 cj, int 
          }()), ...);
     }(std::make_integer_sequence<int, NE>{});
     if (zero) sing = true;
+}
+
+// Pfaffian of the skew matrix on the index set MASK (bits of 0..5), from its
+// upper entries u[a][b] (a < b), by expansion along the first index: the
+// compile-time recursion unrolls into the (k-1)!! products of k indices
+// directly (15 for six).
+template <unsigned MASK>
+__device__ __forceinline__ double2 pf_expand(const double2 (&u)[6][6]) {
+    if constexpr (MASK == 0u) {
+        return c_make(1.0, 0.0);
+    } else {
+        constexpr int a = __builtin_ctz(MASK);
+        constexpr unsigned rest = MASK & (MASK - 1u);
+        double2 acc = c_make(0.0, 0.0);
+        [&]<int... B>(std::integer_sequence<int, B...>) {
+            ([&] {
+                if constexpr ((rest >> B) & 1u) {
+                    constexpr unsigned sub = rest & ~(1u << B);
+                    constexpr bool neg = __builtin_popcount(rest & ((1u << B) - 1u)) & 1;
+                    double2 term;
+                    if constexpr (sub == 0u) term = u[a][B];
+                    else term = c_mul(u[a][B], pf_expand<sub>(u));
+                    acc = neg ? c_sub(acc, term) : c_add(acc, term);
+                }
+            }(), ...);
+        }(std::make_integer_sequence<int, 6>{});
+        return acc;
+    }
+}
+
+// principal square root, sqrt((|z| + |Re z|) / 2) first so that neither part
+// cancels
+__device__ __forceinline__ double2 c_sqrt(double2 z) {
+    const double r = hypot(z.x, z.y);
+    if (r == 0.0) return c_make(0.0, 0.0);
+    const double t = sqrt(0.5 * (r + fabs(z.x)));
+    const double u = z.y / (2.0 * t);
+    return z.x >= 0.0 ? c_make(t, u) : c_make(fabs(u), copysign(t, z.y));
+}
+
+// Pf(M) of one node matrix from det M = Pf(M)^2 (the pivots of gj_node_row,
+// the same elimination as the node's inverse): of the two roots, the one
+// nearer the expansion of Pf along row 0, sum_y (-1)^(y+1) M[0][y]
+// Pf(M without 0, y), whose lanes q < NE - 1 each expand one minor of the
+// upper triangle at Mf (left there by this wave; a wave's LDS instructions
+// execute in order, and the clobber keeps the compiler from moving the reads
+// above the writes).  The expansion only chooses the sign: where it cancels
+// it may be inaccurate, but it would take an error larger than |Pf(M)| to
+// choose the wrong root.  Returns Pf(M) in every lane of the row.
+template <int NE>
+__device__ __forceinline__ double2 pf_sign_row(const double2 *Mf, int q, double2 det) {
+    constexpr int K = NE - 2;
+    asm volatile("" ::: "memory");
+    double2 a = c_make(0.0, 0.0);
+    if (q < NE - 1) {
+        const int y = q + 1;
+        double2 u[6][6];
+        int rr[K > 0 ? K : 1];
+#pragma unroll
+        for (int i = 0; i < K; ++i) rr[i] = i + 1 + (i + 1 >= y ? 1 : 0);
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+#pragma unroll
+            for (int j = i + 1; j < K; ++j) u[i][j] = Mf[rr[i] * NE + rr[j]];
+        a = c_mul(Mf[y], pf_expand<(1u << K) - 1u>(u));
+        if (!(y & 1)) a = c_neg(a);
+    }
+    a = c_make(sum16(a.x), sum16(a.y));
+    const double2 s = c_sqrt(det);
+    return c_abs2(c_sub(s, a)) <= c_abs2(c_add(s, a)) ? s : c_neg(s);
 }
 
 // ---- formation shared by the two waves: wave J forms column tile J, U[., J]
@@ -212,7 +289,8 @@ __device__ __forceinline__ void formation_two_waves(const double2 *__restrict__ 
 //       inverses N_j, then Abar;
 //   RB: B, then the back substitution's solution rows (n x (n + 2NE + 1));
 //   RR: the rows K of Z, then A_0, A_1, A_2 and Z, Z';
-//   RG: [Y0 | Y1 | B_KK^{-1}] (n x (n + 2NE + 1));
+//   RG: the node passes' scratch (M_j, one per 16-lane row), then
+//       [Y0 | Y1 | B_KK^{-1}] (n x (n + 2NE + 1));
 //   RS: M0, M1, M2, Pf(M(e_j)), the pivots of B_KK, the pivot permutation and
 //       cross-wave scratch.
 // The full-size route's [B + cJ | I] (m x 2m) and its Householder vectors span
@@ -237,6 +315,8 @@ __host__ __device__ inline GradLds grad_lds(int T, int n, int NE) {
     size_t rg = (size_t)n * (n + 2 * NE + 1);
     const size_t full = ((size_t)2 * m * m + 2 * m) * sizeof(double2);
     if (full > g.rr + rg * sizeof(double2)) rg = (full - g.rr + sizeof(double2) - 1) / sizeof(double2);
+    // the node passes' scratch: one NE x NE matrix per 16-lane row of the two waves
+    if ((size_t)8 * NE * NE > rg) rg = (size_t)8 * NE * NE;
     g.rg = al(rg * sizeof(double2));
     // M0, M1, M2, Pf(M(e_j)), the pivots, the permutation (n ints) and 4 doubles of scratch
     g.rs = al((size_t)(3 * (NE * (NE - 1) / 2) + (NE + 1) + SO_GRAD_NMAX / 2) * sizeof(double2) +
@@ -401,11 +481,10 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n_in, int eta_in, cons
             bool sing = false;
             auto node_pass = [&](int j) {
                 const double2 cj = tab.e[j < KE ? j : KE - 1];
-                const double2 pf = pencil_pf_row<NE>(Mup, cj, q16);
-                if (q16 == 0 && j < KE) pfm[j] = pf;
-                double2 col[NE];
+                double2 col[NE], det;
                 bool sg = false;
-                gj_node_row<NE>(Mup, cj, q16, sg, col);
+                double2 *Mf = RG + (wv * 4 + g4) * NE * NE;   // this row's scratch: RG is free until the scatter
+                gj_node_row<NE>(Mup, cj, q16, sg, col, det, Mf);
                 if (j < KE) {
                     sing = sing || sg;
                     if (q16 >= NE && q16 < 2 * NE) {
@@ -414,6 +493,8 @@ __global__ __launch_bounds__(128, 2) void k_grad_pair(int n_in, int eta_in, cons
                         for (int x = 0; x < NE; ++x) NJ[(j * NE + x) * NE + y] = col[x];
                     }
                 }
+                const double2 pf = pf_sign_row<NE>(Mf, q16, det);   // after the inverse is stored
+                if (q16 == 0 && j < KE) pfm[j] = pf;
             };
             // U [Y' | W] = [R_LE | I] in the pivoted order (U = the rows of R, block
             // upper triangular with pivots [[0, a], [-a, 0]]); then, with pi the
