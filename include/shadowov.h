@@ -360,6 +360,11 @@ so_status so_vce_overlap(const so_params *p, const so_vce_dims *dims, const so_c
  *            are then NaN) / _NONFINITE, and SO_WSTAT_SINGULAR if a node
  *            matrix of some pair was exactly singular (the energy of that
  *            pair is undefined: N_w and E_w are then NaN, S_w is kept)
+ * The pairs are evaluated at each walker's orthonormal factor Q_w (Phi_w =
+ * Q_w R_w, a Householder QR) and S_w, N_w and the single-shadow terms are
+ * multiplied by det R_w; E_w, which does not depend on it, is taken before,
+ * so it stays finite for walkers whose S_w and N_w leave the double range
+ * (those are flagged SO_WSTAT_NONFINITE).
  * Supported: n <= 24, FP64 (SO_ERR_UNSUPPORTED otherwise); n_walkers <=
  * 65535.  One 256-thread workgroup per pair; deterministic (fixed
  * reduction order); no allocation; enqueued on `stream`. */

@@ -904,7 +904,7 @@ hipError_t launch_vce_prep(const VceDims &v, const so_c64 *pa, const so_c64 *pb,
 // Workspace of so_local_energy: walker matrices and shadow covariances in A
 // order, the Hamiltonian tables, the per-shadow M, per-pair values, status.
 struct EnLayout {
-    size_t off_X, off_C, off_V, off_K2, off_Kt, off_M, off_o, off_e, off_stat, off_Xr, off_Cr, total;
+    size_t off_X, off_C, off_V, off_K2, off_Kt, off_M, off_o, off_e, off_stat, off_Xr, off_Cr, off_LD, total;
 };
 EnLayout energy_layout(int n, int64_t W, int64_t S) {
     const int T = so_tiles(n), DP = 16 * T, d = 2 * n;
@@ -921,6 +921,7 @@ EnLayout energy_layout(int n, int64_t W, int64_t S) {
     L.off_stat = o; o = align_up(o + (size_t)W * sizeof(int32_t));
     L.off_Xr = o; o = align_up(o + (size_t)W * (2 * n - 2) * d * sizeof(double2));   // m <= 2n - 2
     L.off_Cr = o; o = align_up(o + (size_t)S * d * d * sizeof(double));
+    L.off_LD = o; o = align_up(o + (size_t)W * sizeof(double2));   // log det R per walker
     L.total = o;
     return L;
 }
@@ -1284,13 +1285,15 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     int32_t *wst = status ? status : reinterpret_cast<int32_t *>(ws + Lo.off_stat);
     double2 *Xr = reinterpret_cast<double2 *>(ws + Lo.off_Xr);
     double *Cr = reinterpret_cast<double *>(ws + Lo.off_Cr);
+    double2 *Ld = reinterpret_cast<double2 *>(ws + Lo.off_LD);
     // n - eta + 1 nodes off the roots of unity, whatever p->nodes asks for
     EnTab tab;
     energy_nodetab(p, &tab);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    // the pairs run at each walker's orthonormal factor (Phi = Qf R); the
+    // reduction applies det R to S_w and N_w (E_w does not depend on it)
     hipLaunchKernelGGL(k_walker_prep, dim3((unsigned)W), dim3(64), 0, st, n, eta,
-                       reinterpret_cast<const double2 *>(phi), Xa, wst, static_cast<so_u64 *>(nullptr),
-                       static_cast<double2 *>(nullptr));
+                       reinterpret_cast<const double2 *>(phi), Xa, wst, static_cast<so_u64 *>(nullptr), Ld);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
     hipLaunchKernelGGL(k_shadow_prep, dim3((unsigned)S), dim3(256), (size_t)d * d * sizeof(double), st, n, Q, bits, Ca);
     if (hipGetLastError() != hipSuccess) return SO_ERR_HIP;
@@ -1335,7 +1338,8 @@ so_status so_local_energy(const so_params *p, const so_c64 *phi, int64_t n_walke
     if (prof_end(st, ea, PROF_ENERGY, W * S) != hipSuccess) return SO_ERR_HIP;
     hipLaunchKernelGGL(k_energy_reduce, dim3((unsigned)W), dim3(256), 0, st, S, op, ep,
                        reinterpret_cast<double2 *>(overlap), reinterpret_cast<double2 *>(numerator),
-                       reinterpret_cast<double2 *>(energy), wst);
+                       reinterpret_cast<double2 *>(energy), wst, static_cast<const double2 *>(Ld),
+                       (pair_overlap || pair_numerator) ? 1 : 0);
     return hipGetLastError() == hipSuccess ? SO_OK : SO_ERR_HIP;
 }
 

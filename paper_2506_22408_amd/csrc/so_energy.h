@@ -528,18 +528,32 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
 
 // Per walker, in a fixed order: S_w = (1/S) sum_s o_ws, N_w = (1/S) sum_s e_ws,
 // E_w = N_w / S_w; NaN for a walker flagged rank-deficient, as in the overlap
-// path, and N_w, E_w NaN for a walker with a singular node matrix.  One block of 256 threads per walker.
-__global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, const double2 *__restrict__ opair,
-                                                       const double2 *__restrict__ epair, double2 *__restrict__ overlap,
+// path, and N_w, E_w NaN for a walker with a singular node matrix.  The pair
+// terms were evaluated at the walker's orthonormal factor Qf (Phi = Qf R,
+// k_walker_prep); the state, and with it <Psi_T|phi> and <Psi_T|H|phi>, is
+// linear in det R, so S_w and N_w are multiplied by det R = exp(logdet[w])
+// while E_w comes from the unscaled sums and stays finite where S_w and N_w
+// leave the double range.  With scale_pairs the caller's single-shadow terms
+// are multiplied by det R as well.  One block of 256 threads per walker.
+__global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, double2 *__restrict__ opair,
+                                                       double2 *__restrict__ epair, double2 *__restrict__ overlap,
                                                        double2 *__restrict__ numer, double2 *__restrict__ energy,
-                                                       int32_t *__restrict__ wst) {
+                                                       int32_t *__restrict__ wst, const double2 *__restrict__ logdet,
+                                                       int scale_pairs) {
     __shared__ double2 red[8];
     const int t = threadIdx.x;
     const int64_t w = blockIdx.x;
+    const double mg = exp(logdet[w].x);
+    const double2 dr = c_make(mg * cos(logdet[w].y), mg * sin(logdet[w].y));
     double2 so = c_make(0.0, 0.0), se = c_make(0.0, 0.0);
     for (int64_t s = t; s < S; s += 256) {
-        so = c_add(so, opair[w * S + s]);
-        se = c_add(se, epair[w * S + s]);
+        const double2 o = opair[w * S + s], e = epair[w * S + s];
+        so = c_add(so, o);
+        se = c_add(se, e);
+        if (scale_pairs) {
+            opair[w * S + s] = c_mul(o, dr);
+            epair[w * S + s] = c_mul(e, dr);
+        }
     }
     en_sum2(so, se, red);
     if (t == 0) {
@@ -547,12 +561,17 @@ __global__ __launch_bounds__(256) void k_energy_reduce(int64_t S, const double2 
         so = c_scale(so, inv);
         se = c_scale(se, inv);
         if (wst && (wst[w] & SO_WSTAT_RANK)) so = se = c_make(NAN, NAN);
-        if (wst && !(isfinite(so.x) && isfinite(so.y) && isfinite(se.x) && isfinite(se.y)))
-            wst[w] |= SO_WSTAT_NONFINITE;
+        bool fin = isfinite(so.x) && isfinite(so.y) && isfinite(se.x) && isfinite(se.y);
         // a singular node matrix leaves its energy term undefined: no number
-        if (wst && (wst[w] & SO_WSTAT_SINGULAR)) se = c_make(NAN, NAN);
+        const bool sing = wst && (wst[w] & SO_WSTAT_SINGULAR);
+        if (sing) se = c_make(NAN, NAN);
+        const double2 el = c_mul(se, c_inv(so));
+        so = c_mul(so, dr);
+        se = c_mul(se, dr);
+        fin = fin && isfinite(so.x) && isfinite(so.y) && (sing || (isfinite(se.x) && isfinite(se.y)));
+        if (wst && !fin) wst[w] |= SO_WSTAT_NONFINITE;
         if (overlap) overlap[w] = so;
         if (numer) numer[w] = se;
-        if (energy) energy[w] = c_mul(se, c_inv(so));
+        if (energy) energy[w] = el;
     }
 }

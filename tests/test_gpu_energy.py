@@ -216,6 +216,46 @@ def test_energy_beyond_16_modes(B, n, eta, W, S, ng):
     check(Sg, Ng, Eg, o, e)
 
 
+def test_energy_under_right_multiplication_of_the_walkers(B):
+    """The state of a walker is linear in det of its orbital mixing:
+    Phi -> Phi A multiplies every o_ws and e_ws (and S_w, N_w) by det A and
+    leaves E_L unchanged.  A random well-conditioned A, and A = c I with
+    c = 1e+-20 and 1e+-60: at 1e+60, c^6 leaves the double range, S_w and N_w
+    overflow and are flagged non-finite while E_L keeps its value; at 1e-60
+    they underflow to zero, unflagged, and E_L still keeps its value (the
+    pairs are evaluated at the walkers' orthonormal factors)."""
+    n, eta, W, S = 10, 6, 3, 5
+    w = wl.make("er", n, eta, W, S, seed=91, n_gamma=6, with_t=True)
+    S0, N0, E0, st0 = run(B, w, w.t, w.L)
+    o0, e0 = LAST_PAIRS["o"].copy(), LAST_PAIRS["e"].copy()
+    assert not st0.any()
+    so, se = np.abs(o0).mean(axis=1), np.abs(e0).mean(axis=1)
+    rng = np.random.default_rng(92)
+    A = np.eye(eta) + 0.3 * (rng.standard_normal((W, eta, eta)) + 1j * rng.standard_normal((W, eta, eta)))
+    dA = np.linalg.det(A)
+    wa = wl.Workload("er", n, eta, w.phi @ A, w.Q, w.bits, w.L, w.t)
+    Sa, Na, Ea, sta = run(B, wa, w.t, w.L)
+    assert not sta.any()
+    assert np.all(np.abs(Sa - dA * S0) <= 1e-10 * np.abs(dA) * so)
+    assert np.all(np.abs(Na - dA * N0) <= 1e-10 * np.abs(dA) * se)
+    assert np.all(np.abs(Ea - E0) <= 1e-10 * np.abs(E0))
+    for name, r in (("o", o0), ("e", e0)):
+        sc = np.abs(dA)[:, None] * np.maximum(np.abs(r), np.abs(r).mean(axis=1, keepdims=True))
+        assert np.all(np.abs(LAST_PAIRS[name] - dA[:, None] * r) <= 1e-10 * sc), name
+    for c in (1e-60, 1e-20, 1e20, 1e60):
+        wc = wl.Workload("er", n, eta, w.phi * c, w.Q, w.bits, w.L, w.t)
+        Sc, Nc, Ec, stc = run(B, wc, w.t, w.L)
+        assert np.all(np.abs(Ec - E0) <= 1e-10 * np.abs(E0)), c
+        if eta * abs(np.log10(c)) < 300:
+            f = c ** eta
+            assert not stc.any()
+            assert np.all(np.abs(Sc - f * S0) <= 1e-10 * f * so) and np.all(np.abs(Nc - f * N0) <= 1e-10 * f * se)
+        elif c > 1:
+            assert np.all(stc == B.SO_WSTAT_NONFINITE)
+        else:
+            assert not stc.any() and np.all(Sc == 0) and np.all(Nc == 0)
+
+
 def test_energy_singular_node_gives_nan(B):
     """Single-mode walkers with the identity shadow make every node matrix
     singular (the pair's Pfaffian polynomial vanishes): the walker is
