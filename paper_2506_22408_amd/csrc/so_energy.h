@@ -174,7 +174,7 @@ __device__ __forceinline__ int en_argmax(double v, int idx, double *rv, int *ri,
 }
 
 // LDS of k_energy_pair, in complex entries: B [m][m], A [max(m^2, 2 n^2)]
-// (the node matrix and its inverse, then zeta and its transpose), YZ [d][d]
+// (the node matrix and its inverse, then zeta^T, row stride n + 1), YZ [d][d]
 // (A^{-1} X, then Z), Yt [d][d].  X and C' are read through the caches from
 // row-major copies.  At n = 16, eta = 8 this is 52 KB: three blocks per CU;
 // at most 141 KB (n = 24, eta = 2): one block.
@@ -213,10 +213,9 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
     const int d = 2 * n, m = 2 * n - eta, ne = n - eta, n2 = n * n;
     const int asz = m * m > 2 * n2 ? m * m : 2 * n2;
     double2 *Bm = esm;                // m x m
-    double2 *A = Bm + m * m;          // m x m; later zeta (n2) and zetaT (n2)
+    double2 *A = Bm + m * m;          // m x m; later zeta^T (n (n + 1))
     double2 *YZ = A + asz;            // d x d
     double2 *Yt = YZ + d * d;         // d x d
-    double2 *zeta = A, *zetaT = A + n2;
     const int64_t s0 = blockIdx.x, w0 = blockIdx.y;
     const double2 *X = Xr + w0 * m * d;    // m x d, row-major (global, cached)
     const double *C = Cr + s0 * d * d;     // d x d, row-major (global, cached)
@@ -253,7 +252,11 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
         double2 *A = Bm + m * m;
         double2 *YZ = A + asz;
         double2 *Yt = YZ + d * d;
-        double2 *zeta = A, *zetaT = A + n2;
+        // zeta^T with the odd row stride n + 1 (in complex entries): the
+        // contraction reads it at a few rows q per wave, which a stride of n
+        // would put on the same LDS banks
+        const int ZS = n + 1;
+        double2 *zetaT = A;
         const double2 *X = Xr + w0 * m * d;
         const double *C = Cr + s0 * d * d;
         const double *Mg = Ms + s0 * d * d;
@@ -398,8 +401,7 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
             const int p = e / n, q = e - p * n;
             const double2 df = c_sub(Z[(2 * q) * d + 2 * p + 1], Z[(2 * q + 1) * d + 2 * p]);
             const double2 z = c_make(-df.y, df.x);
-            zeta[e] = z;
-            zetaT[q * n + p] = z;
+            zetaT[q * ZS + p] = z;
         }
         __syncthreads();
         // one-body s tr(Z Kt) and s tr(Yt M)
@@ -451,8 +453,8 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
                         y10 = c_add(y10, c_scale(e10, w));
                         y11 = c_add(y11, c_scale(e11, w));
                         if constexpr (AS) {
-                            pa = c_add(pa, c_scale(zetaT[qa * n + p], v));
-                            pb = c_add(pb, c_scale(zetaT[qb * n + p], w));
+                            pa = c_add(pa, c_scale(zetaT[qa * ZS + p], v));
+                            pb = c_add(pb, c_scale(zetaT[qb * ZS + p], w));
                         }
                     };
                     int p = 0;
@@ -468,8 +470,8 @@ __global__ __launch_bounds__(SO_EN_THREADS, T == 3 ? 2 : 3) void k_energy_pair(i
                     }
                     for (; p < n; ++p) term(p, va[so + (size_t)p * n2], vb[so + (size_t)p * n2]);
                     if constexpr (AS) {
-                        asq = c_fma(pa, zetaT[s * n + ra], asq);
-                        if (hb) asq = c_fma(pb, zetaT[s * n + rb], asq);
+                        asq = c_fma(pa, zetaT[s * ZS + ra], asq);
+                        if (hb) asq = c_fma(pb, zetaT[s * ZS + rb], asq);
                     }
                 }
                 // combine with the column's own block: Z^(qr) for c1, W^(qr) = (Z C')^(qr) for c2
