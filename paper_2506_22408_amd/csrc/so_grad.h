@@ -776,6 +776,8 @@ __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double
     const double *Xw = Xa + (size_t)w * DP * DP;
     const double rs2 = 0.70710678118654752440;
     const bool zero = (osum.x == 0.0 && osum.y == 0.0);
+    // a rank-deficient walker (flagged by k_walker_prep) has no derivative: NaN
+    const bool rank = (wstat[w] & SO_WSTAT_RANK) != 0;
     const double2 rinv = zero ? c_make(0, 0) : c_inv(osum);
     for (int e = l; e < n * eta; e += 64) {
         const int p = e / eta, j = e - p * eta;
@@ -785,7 +787,7 @@ __global__ __launch_bounds__(64) void k_grad_walker(int n, int eta, const double
             const double2 gt = c_make(Xw[ao_index(2 * eta + t, 2 * p, T)], Xw[ao_index(2 * eta + t, 2 * p + 1, T)]);
             gv = c_sub(gv, c_mul(c_conj(gt), Vv[j * ne + t]));
         }
-        const double2 dv = zero ? c_make(NAN, NAN) : c_mul(gv, rinv);
+        const double2 dv = (zero || rank) ? c_make(NAN, NAN) : c_mul(gv, rinv);
         Dd[e] = dv;
         if (!rf) dlog[(size_t)w * n * eta + e] = dv;
     }

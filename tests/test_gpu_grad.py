@@ -281,6 +281,23 @@ def test_grad_under_right_multiplication_of_the_walkers(B):
             assert not sp.any()
 
 
+def test_grad_rank_deficient_walker_is_nan(B):
+    """A walker whose orbitals are linearly dependent has no derivative: it
+    is flagged SO_WSTAT_RANK and its S_w, D_w and G_w are NaN, while the
+    other walkers of the call keep the oracle's values."""
+    n, eta, W, S = 8, 4, 3, 6
+    w = wl.make("rk", n, eta, W, S, seed=77)
+    phi = w.phi.copy()
+    phi[1, :, 3] = phi[1, :, 0] * (0.5 - 0.25j)
+    sg, dg, gg, st = gpu_grad(B, phi, w.Q, w.bits)
+    assert st[1] & B.SO_WSTAT_RANK and not st[[0, 2]].any()
+    assert np.isnan(sg[1]) and np.all(np.isnan(dg[1])) and np.all(np.isnan(gg[1]))
+    so, do, go = oracle.grad(phi[[0, 2]], w.Q, w.bits)
+    assert np.all(np.abs(sg[[0, 2]] - so) <= 1e-10 * np.abs(so))
+    close_per_walker(dg[[0, 2]], do, 1e-10)
+    close_per_walker(gg[[0, 2]], go, 1e-10)
+
+
 def test_grad_unsupported_shapes_are_refused(B):
     for n, eta in ((16, 2), (20, 16), (9, 4)):       # ne = 14; n > 16; ne odd
         w = wl.make("u", n, eta, 2, 3, seed=1)
