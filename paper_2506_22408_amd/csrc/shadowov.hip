@@ -306,7 +306,7 @@ constexpr int kPairBatchesPerWave = 2;                 // node batches per fused
 #define SO_ROW_BATCHES_PER_WAVE 8
 #endif
 constexpr int kRowBatchesPerWave = SO_ROW_BATCHES_PER_WAVE;   // the same for ne > 8 (single-pair batches)
-constexpr int64_t kRdmBlocks = 2048;                    // blocks of the density-matrix reduction
+constexpr int64_t kRdmBlocks = 1024;                    // blocks of the density-matrix reduction (1024 measured best of 512, 1024, 2048 at n = 16 and 24)
 
 struct Layout {
     size_t off_X, off_C, off_S, off_P, off_pairs, off_stat, off_fbc, off_fbl, off_F, off_O, off_M, off_LD;
